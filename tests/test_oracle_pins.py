@@ -1,0 +1,277 @@
+"""Pins of the FP64 oracle against closed forms, invariants, library routines
+and brute force. None of these retype the oracle's own formulas."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+import synth
+from oracle import (System, expm_taylor, frechet_block, liouvillian, vec,
+                    unvec, propagate, fidelity, superop_of_unitary, pauli)
+
+SX, SY, SZ, SM = pauli("x"), pauli("y"), pauli("z"), pauli("m")
+I2 = np.eye(2, dtype=complex)
+
+
+def one_spin(B=0.0, T1=np.inf, T2=np.inf):
+    return System(1, [B], T1, T2)
+
+
+# ---------------------------------------------------------------- expm pins
+@pytest.mark.parametrize("scale", [1e-3, 0.3, 2.0, 40.0])
+def test_expm_taylor_matches_scipy(scale):
+    rng = np.random.default_rng(11)
+    A = (rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)))
+    A *= scale / np.abs(A).sum(0).max()
+    E = expm_taylor(A)
+    R = sla.expm(A)
+    assert np.linalg.norm(E - R) <= 1e-13 * max(1.0, np.linalg.norm(R))
+
+
+def test_frechet_block_matches_scipy():
+    rng = np.random.default_rng(12)
+    for scale in (0.05, 1.0, 5.0):
+        A = rng.standard_normal((10, 10)) + 1j * rng.standard_normal((10, 10))
+        A *= scale / np.abs(A).sum(0).max()
+        E = rng.standard_normal((10, 10)) + 1j * rng.standard_normal((10, 10))
+        ours = frechet_block(A, E)
+        _, ref = sla.expm_frechet(A, E)
+        assert np.linalg.norm(ours - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_adjoint_identity():
+    # Tr(M L(A,E)) == Tr(L(A,M) E)
+    rng = np.random.default_rng(13)
+    A, E, M = [rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9))
+               for _ in range(3)]
+    A *= 0.7 / np.abs(A).sum(0).max()
+    lhs = np.trace(M @ frechet_block(A, E))
+    rhs = np.trace(frechet_block(A, M) @ E)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+# ------------------------------------------------------------ closed forms
+def test_rabi_single_spin():
+    # H = (W/2) sigma_x, no dissipation: U = cos(Wt/2) I - i sin(Wt/2) sigma_x
+    W, t = 2 * np.pi * 3.0, 0.37
+    H = 0.5 * W * SX
+    S = expm_taylor(t * liouvillian(H, []))
+    U = np.cos(W * t / 2) * I2 - 1j * np.sin(W * t / 2) * SX
+    assert np.allclose(S, np.kron(U.conj(), U), atol=1e-13)
+    # vec convention: S vec(rho) = vec(U rho U^dag)
+    rho = np.array([[0.7, 0.2 - 0.1j], [0.2 + 0.1j, 0.3]])
+    assert np.allclose(unvec(S @ vec(rho), 2), U @ rho @ U.conj().T, atol=1e-13)
+
+
+def test_larmor_through_slices():
+    B, h, N = 2 * np.pi * 7.0, 1e-3, 25
+    sysm = one_spin(B)
+    amps = np.zeros((N, 0))
+    U = propagate(sysm.omegas(amps, h, 1, "zoh"))
+    t = N * h
+    V = np.diag([np.exp(-1j * B * t / 2), np.exp(1j * B * t / 2)])
+    assert np.allclose(U, np.kron(V.conj(), V), atol=1e-13)
+
+
+def test_two_spin_exchange_swap_power():
+    # S1.S2 = SWAP/2 - I/4 -> U = e^{iJt/4}[cos(Jt/2) I - i sin(Jt/2) SWAP]
+    SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
+                    dtype=complex)
+    sysm = System(2, [0.0, 0.0])
+    J = 2 * np.pi * 5.0
+    for Jt in (np.pi, np.pi / 2, 1.234):
+        t = Jt / J
+        N = 10
+        amps = np.full((N, 1), J)
+        S = propagate(sysm.omegas(amps, t / N, 1, "zoh"))
+        U = np.exp(1j * Jt / 4) * (np.cos(Jt / 2) * np.eye(4) - 1j * np.sin(Jt / 2) * SWAP)
+        assert np.allclose(S, np.kron(U.conj(), U), atol=1e-12)
+    # J t = pi is SWAP up to a phase: process fidelity exactly one
+    amps = np.full((4, 1), J)
+    S = propagate(sysm.omegas(amps, np.pi / J / 4, 1, "zoh"))
+    F, Fi = fidelity(S, SWAP)
+    assert abs(F - 1.0) < 1e-12 and abs(Fi) < 1e-12
+
+
+def test_no_dissipation_is_unitary_channel():
+    cfg = synth.small_case(3, n_slices=12, dt=1e-3)
+    sysm = System.from_cfg(cfg, dissipative=False)
+    S = propagate(sysm.omegas(cfg["amps"], cfg["dt"], 1, "zoh"))
+    UH = np.eye(8, dtype=complex)
+    for n in range(12):
+        UH = sla.expm(-1j * cfg["dt"] * sysm.H(cfg["amps"][n])) @ UH
+    assert np.allclose(S, np.kron(UH.conj(), UH), atol=1e-12)
+    # unitary channels stay unitary through the product
+    assert np.allclose(S.conj().T @ S, np.eye(64), atol=1e-12)
+
+
+@pytest.mark.parametrize("order,hold", [(1, "zoh"), (2, "foh")])
+def test_trace_and_hermiticity_preservation(order, hold):
+    cfg = synth.small_case(4, n_slices=10, dt=1e-3)
+    sysm = System.from_cfg(cfg)
+    S = propagate(sysm.omegas(cfg["amps"], cfg["dt"], order, hold))
+    d = 8
+    vI = vec(np.eye(d))
+    assert np.allclose(vI.conj() @ S, vI.conj(), atol=1e-13)
+    # S[(i,j),(k,l)] = conj(S[(j,i),(l,k)]) with (i,j) -> i + d j
+    P = np.zeros((d * d, d * d))
+    for i in range(d):
+        for j in range(d):
+            P[j + d * i, i + d * j] = 1.0
+    assert np.allclose(S, (P @ S @ P).conj(), atol=1e-13)
+    # a mixed state stays a density matrix
+    rng = np.random.default_rng(1)
+    G = rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))
+    rho = G @ G.conj().T
+    rho /= np.trace(rho)
+    out = unvec(S @ vec(rho), d)
+    assert abs(np.trace(out) - 1) < 1e-13
+    assert np.allclose(out, out.conj().T, atol=1e-13)
+    assert np.linalg.eigvalsh(0.5 * (out + out.conj().T)).min() > -1e-12
+
+
+def test_dephasing_closed_form():
+    T2, t = 2.0, 0.9
+    sysm = one_spin(0.0, np.inf, T2)
+    S = propagate(sysm.omegas(np.zeros((9, 0)), t / 9, 1, "zoh"))
+    rho = np.array([[0.5, 0.5], [0.5, 0.5]], dtype=complex)
+    out = unvec(S @ vec(rho), 2)
+    assert np.isclose(out[0, 1], 0.5 * np.exp(-2 * t / T2), atol=1e-14)
+    assert np.isclose(out[0, 0], 0.5, atol=1e-14)
+
+
+def test_relaxation_closed_form():
+    T1, t = 3.0, 1.7
+    sysm = one_spin(0.0, T1, np.inf)
+    S = propagate(sysm.omegas(np.zeros((5, 0)), t / 5, 1, "zoh"))
+    rho = np.array([[0.5, 0.5], [0.5, 0.5]], dtype=complex)  # |+><+|
+    out = unvec(S @ vec(rho), 2)
+    assert np.isclose(out[0, 0], 0.5 * np.exp(-t / T1), atol=1e-14)   # up decays
+    assert np.isclose(out[0, 1], 0.5 * np.exp(-t / (2 * T1)), atol=1e-14)
+
+
+def test_constant_pulse_single_exponential():
+    cfg = synth.small_case(6, n_slices=1, dt=1e-3)
+    sysm = System.from_cfg(cfg)
+    u = cfg["amps"][0]
+    N, h = 17, 2e-4
+    amps = np.tile(u, (N, 1))
+    U = propagate(sysm.omegas(amps, h, 2, "foh"))
+    ref = sla.expm(N * h * sysm.liouv(u))
+    assert np.allclose(U, ref, atol=1e-12)
+
+
+# --------------------------------------------------------------- Magnus pins
+def test_magnus2_term_for_linear_liouvillian():
+    # For L(t) = L0 + t L', the second Magnus term over [0, h] is
+    # (1/2) int_0^h int_0^t1 [L(t1), L(t2)] = (h^3 / 12) [L', L0].
+    cfg = synth.small_case(7, n_slices=2, dt=5e-4)
+    sysm = System.from_cfg(cfg)
+    amps, h = cfg["amps"], cfg["dt"]
+    L0 = sysm.liouv(amps[0])
+    Lp = (sysm.liouv(amps[1]) - L0) / h
+    om1 = oracle.slice_omega(sysm.liouv, amps, 0, h, 1, "foh")
+    om2 = oracle.slice_omega(sysm.liouv, amps, 0, h, 2, "foh")
+    expect = (h ** 3 / 12.0) * (Lp @ L0 - L0 @ Lp)
+    assert np.linalg.norm(om2 - om1 - expect) <= 1e-12 * np.linalg.norm(expect)
+    # and the first term is the exact slice average h L(t + h/2)
+    assert np.allclose(om1, h * sysm.liouv(0.5 * (amps[0] + amps[1])), atol=1e-14)
+    # ZOH: second-order term vanishes
+    z1 = oracle.slice_omega(sysm.liouv, amps, 0, h, 1, "zoh")
+    z2 = oracle.slice_omega(sysm.liouv, amps, 0, h, 2, "zoh")
+    assert np.array_equal(z1, z2)
+
+
+def test_magnus_convergence_orders():
+    # coarse piecewise-linear pulse (FOH, last sample held), every coarse slice
+    # split k times with the same interpolation; error vs a fine RK4 reference
+    rng = np.random.default_rng(21)
+    sysm = System(2, rng.uniform(-60, 60, 2), 50.0, 5.0)
+    coarse = rng.uniform(0, 2 * np.pi * 20, (5, 1))
+    H = 0.005
+    ref = oracle.rk4_propagator(sysm, coarse, H, "foh", 400)
+    ext = np.vstack([coarse, coarse[-1:]])
+    errs = {1: [], 2: []}
+    ks = [1, 2, 4, 8]
+    for k in ks:
+        fine = np.array([ext[s] + (j / k) * (ext[s + 1] - ext[s])
+                         for s in range(5) for j in range(k)])
+        for order in (1, 2):
+            U = propagate(sysm.omegas(fine, H / k, order, "foh"))
+            errs[order].append(np.linalg.norm(U - ref))
+    s1 = np.polyfit(np.log(ks), np.log(errs[1]), 1)[0]
+    s2 = np.polyfit(np.log(ks), np.log(errs[2]), 1)[0]
+    assert -2.3 < s1 < -1.7, (s1, errs)
+    assert -4.4 < s2 < -3.6, (s2, errs)
+
+
+def test_zoh_product_equals_fine_rk4():
+    # ZOH slices are exact exponentials; RK4 on the same pulse converges to them
+    cfg = synth.small_case(8, n_spins=2, n_slices=6, dt=1e-3)
+    sysm = System.from_cfg(cfg)
+    U = propagate(sysm.omegas(cfg["amps"], cfg["dt"], 1, "zoh"))
+    R = oracle.rk4_propagator(sysm, cfg["amps"], cfg["dt"], "zoh", 60)
+    assert np.linalg.norm(U - R) < 1e-9 * np.linalg.norm(U)
+
+
+def test_foh_order2_close_to_rk4_three_spins():
+    cfg = synth.small_case(9, n_slices=4, dt=2.5e-4)
+    sysm = System.from_cfg(cfg)
+    U = propagate(sysm.omegas(cfg["amps"], cfg["dt"], 2, "foh"))
+    U1 = propagate(sysm.omegas(cfg["amps"], cfg["dt"], 1, "foh"))
+    R = oracle.rk4_propagator(sysm, cfg["amps"], cfg["dt"], "foh", 20)
+    e2 = np.linalg.norm(U - R) / np.linalg.norm(U)
+    e1 = np.linalg.norm(U1 - R) / np.linalg.norm(U)
+    # 0.25 ns slices of the config-1 distributions: order 2 is ~1e-7, order 1 ~1e-5
+    assert e2 < 3e-7 and e1 > 100 * e2
+
+
+# ------------------------------------------------------------- fidelity pins
+def test_fidelity_identities():
+    rng = np.random.default_rng(31)
+    UT = synth.haar_unitary(rng, 8)
+    F, Fi = fidelity(superop_of_unitary(UT), UT)
+    assert abs(F - 1) < 1e-13 and abs(Fi) < 1e-13
+    V = synth.haar_unitary(rng, 8)
+    F, _ = fidelity(superop_of_unitary(V), UT)
+    assert abs(F - abs(np.trace(UT.conj().T @ V)) ** 2 / 64) < 1e-13
+    # global phase invariance
+    F2, _ = fidelity(superop_of_unitary(np.exp(0.7j) * V), UT)
+    assert abs(F - F2) < 1e-13
+    # CPTP maps give F in [0, 1] and real
+    cfg = synth.small_case(10, n_slices=8, dt=1e-3)
+    S = propagate(System.from_cfg(cfg).omegas(cfg["amps"], 1e-3, 1, "zoh"))
+    F, Fi = fidelity(S, UT)
+    assert 0 <= F <= 1 and abs(Fi) < 1e-13
+
+
+# ------------------------------------------------------------- gradient pins
+def test_gradient_matches_central_differences():
+    cfg = synth.small_case(14, n_slices=8)
+    sysm = System.from_cfg(cfg)
+    amps = cfg["amps"]
+    F, g = oracle.grad_adjoint(sysm, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    coords = np.arange(amps.size)
+    fd = oracle.grad_fd(sysm, amps, cfg["dt"], 2, "foh", cfg["U_target"], coords)
+    assert np.linalg.norm(g.reshape(-1) - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_gradient_zoh_order1_matches_fd():
+    cfg = synth.small_case(15, n_slices=6, dt=1e-3)
+    sysm = System.from_cfg(cfg)
+    F, g = oracle.grad_adjoint(sysm, cfg["amps"], 1e-3, 1, "zoh", cfg["U_target"])
+    fd = oracle.grad_fd(sysm, cfg["amps"], 1e-3, 1, "zoh", cfg["U_target"],
+                        np.arange(cfg["amps"].size))
+    assert np.linalg.norm(g.reshape(-1) - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_gradient_vanishes_at_reached_target():
+    # closed system, target = Hilbert propagator of u*: F = 1 is the maximum
+    cfg = synth.small_case(16, n_slices=6, dt=1e-3)
+    sysm = System.from_cfg(cfg, dissipative=False)
+    UH = np.eye(8, dtype=complex)
+    for n in range(6):
+        UH = sla.expm(-1j * 1e-3 * sysm.H(cfg["amps"][n])) @ UH
+    F, g = oracle.grad_adjoint(sysm, cfg["amps"], 1e-3, 1, "zoh", UH)
+    assert abs(F - 1) < 1e-12
+    assert np.abs(g).max() < 1e-10
