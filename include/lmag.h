@@ -1,0 +1,167 @@
+/*
+ * lmag.h -- C ABI of the Lindblad-Magnus pulse propagator for AMD MI355X (gfx950).
+ *
+ * The library evaluates, for piecewise control pulses on a small open quantum
+ * system, the superoperator propagator of the Lindblad master equation and the
+ * process fidelity against a target unitary, together with the gradient of that
+ * fidelity with respect to every pulse amplitude:
+ *
+ *   L(t)   = -i (I (x) H(t) - H(t)^T (x) I)
+ *            + sum_k [ conj(L_k) (x) L_k - 1/2 I (x) L_k^dag L_k
+ *                      - 1/2 (L_k^dag L_k)^T (x) I ]            (paper Eq. 8)
+ *   H(t)   = sum_c eps_c u_c(t) H_ctrl[c] + sum_i b_i H_static[i]
+ *   Omega_n = int_slice L dt                                     (Eq. 13)
+ *             [+ (sqrt(3) h^2 / 12) [L(tau_2), L(tau_1)], second order]
+ *   S_n    = exp(Omega_n)                                        (Eq. 14)
+ *   U      = S_N ... S_1                                         (Eq. 15)
+ *   F      = Re Tr(S_T^dag U) / d^2,  S_T = conj(U_T) (x) U_T
+ *
+ * The problem statement follows the paper's Sec. III: a system (Hamiltonian
+ * terms and jump operators built from T1/T2, Sec. II-B and Eq. 8), a
+ * coefficient matrix of slices x controls (Sec. III-C) and a target unitary
+ * (Sec. III-C); the outputs are the propagator (Eq. 15) and a score with its
+ * gradient for the optimiser (Sec. III-C).
+ *
+ * Conventions
+ *  - Complex numbers are interleaved (re, im). Hilbert-space operators are
+ *    row-major d x d. Superoperators are row-major n x n, n = d^2, in the
+ *    column-stacking convention vec(rho)[i + d j] = rho[i][j].
+ *  - Units are the caller's (e.g. rad/us and us); hbar = 1.
+ *  - Every call returns an lmag_status. Nothing aborts and no C++ exception
+ *    crosses the ABI. On a non-OK status lmag_last_error() describes it and no
+ *    output has been written (argument errors are detected on the host before
+ *    any launch).
+ *  - Compute calls are asynchronous on the caller's HIP stream (hipStream_t
+ *    passed as void*, NULL = default stream). Errors raised by the device
+ *    surface on a later call or on lmag_sync().
+ *  - Reductions are deterministic (no floating-point atomics): repeated calls
+ *    on the same inputs give bitwise-identical results.
+ *  - The library owns only its workspace, which lmag_destroy() frees. The
+ *    caller owns every pointer it passes in.
+ *  - Supported superoperator size: n = d^2 <= 64 (d = 2, 4 or 8). Smaller
+ *    systems are embedded in 64 x 64 tiles with zero padding.
+ */
+#ifndef LMAG_H
+#define LMAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LMAG_OK = 0,
+  LMAG_E_INVALID = -1,     /* bad argument (dimension, pointer, count, NaN in host data) */
+  LMAG_E_NOSYSTEM = -2,    /* compute call before lmag_set_system */
+  LMAG_E_NOMEM = -3,       /* device allocation failed */
+  LMAG_E_DEVICE = -4,      /* HIP runtime / kernel error */
+  LMAG_E_UNSUPPORTED = -5  /* valid request outside what this build supports */
+} lmag_status;
+
+enum { LMAG_F32 = 32, LMAG_F64 = 64 };
+enum { LMAG_ZOH = 0, LMAG_FOH = 1 };
+
+typedef struct lmag_ctx lmag_ctx;  /* opaque; one per (device, host thread) */
+
+/* Library version string (static storage). */
+const char *lmag_version(void);
+
+/* Create a context bound to HIP device hip_device. *out receives the context
+ * (NULL on failure). LMAG_E_DEVICE if no such device exists. */
+lmag_status lmag_create(lmag_ctx **out, int hip_device);
+
+/* Destroy a context and free its workspace. NULL is ignored. Waits for work
+ * the context queued on its last stream. */
+void lmag_destroy(lmag_ctx *ctx);
+
+/* Message for the last non-OK status of this context (static storage of the
+ * context, valid until the next call on it). */
+const char *lmag_last_error(const lmag_ctx *ctx);
+
+/* System description (Sec. II-B, Eq. 6 and 8). All pointers are HOST pointers;
+ * the arrays are copied before the call returns and the caller keeps them. */
+typedef struct {
+  int d;                        /* Hilbert dimension, d*d <= 64                        */
+  int n_static;                 /* number of static Hamiltonian terms               */
+  const double *H_static;       /* [n_static][d][d] complex (e.g. sigma_z_i / 2)     */
+  int n_ctrl;                   /* number of control terms, <= 8                     */
+  const double *H_ctrl;         /* [n_ctrl][d][d] complex (e.g. S_c . S_{c+1})       */
+  int n_jump;                   /* number of jump operators                          */
+  const double *L_jump;         /* [n_jump][d][d] complex, rates folded in (op/sqrt T) */
+  int precision;                /* LMAG_F32 or LMAG_F64: compute type of the slices  */
+  int magnus_order;             /* 1 (Eq. 13) or 2 (adds the Gauss-Legendre term)    */
+  int hold;                     /* LMAG_ZOH (u constant per slice) or LMAG_FOH        */
+                                /* (u linear from u_n to u_{n+1}; u_N := u_{N-1})   */
+  size_t workspace_bytes_max;   /* 0 = no limit beyond device memory                 */
+  int chunk_slices;             /* slices per work unit; 0 = automatic               */
+} lmag_system_desc;
+
+/* Install (or replace) the system. Builds the superoperator basis on the
+ * device in FP64 (and an FP32 copy). Blocks until the basis is built.
+ * LMAG_E_INVALID for bad dimensions/counts/NULL arrays or non-finite entries. */
+lmag_status lmag_set_system(lmag_ctx *ctx, const lmag_system_desc *desc);
+
+/* A batch of items (pulse x quasi-static noise sample). Metadata arrays are
+ * HOST pointers; data arrays are DEVICE pointers of the caller. */
+typedef struct {
+  int n_items;
+  const int32_t *n_slices;      /* HOST [n_items], each >= 1                         */
+  const int64_t *slice_offset;  /* HOST [n_items], first row of the item in amps     */
+  const void *amps;             /* DEVICE [rows][n_ctrl] real, compute type          */
+  const double *static_coef;    /* DEVICE [n_items][n_static] (b_i incl. offsets); NULL = 0 */
+  const double *ctrl_scale;     /* DEVICE [n_items][n_ctrl] (eps_c); NULL = 1        */
+  double dt;                    /* slice width h > 0                                 */
+  int n_groups;                 /* 0 = none; else items are averaged per group        */
+  const int32_t *group_of_item; /* HOST [n_items] in [0, n_groups); items of a group
+                                   must share slice_offset and n_slices              */
+} lmag_batch;
+
+/* S_out: DEVICE [n_items][n][n] complex of the compute type: U of every item. */
+lmag_status lmag_propagate(lmag_ctx *ctx, const lmag_batch *batch, void *S_out,
+                           void *hip_stream);
+
+/* Fidelity and (optionally) its gradient.
+ * U_target:       DEVICE [n_targets][d][d] complex128
+ * target_of_item: HOST [n_items] in [0, n_targets) or NULL (= target 0)
+ * F_out:          DEVICE double [n_items] (or [n_groups] when grouped)
+ * grad_out:       DEVICE like amps (compute type) or NULL for F only. With
+ *                 groups, the group mean of dF/du is written at the rows of the
+ *                 group's shared amplitudes. */
+lmag_status lmag_fidelity_and_grad(lmag_ctx *ctx, const lmag_batch *batch,
+                                   const void *U_target, int n_targets,
+                                   const int32_t *target_of_item, double *F_out,
+                                   void *grad_out, void *hip_stream);
+
+/* Wait for the stream and report any pending device error. */
+lmag_status lmag_sync(lmag_ctx *ctx, void *hip_stream);
+
+/* Host-only queries (no device needed). */
+/* Pade coefficients b_0..b_m of r_m = p_m / p_m(-x), m in {3, 5, 7}. */
+lmag_status lmag_pade_coefficients(int m, double *b_out);
+/* theta_m used for scaling selection: precision LMAG_F32 (m = 3) or
+ * LMAG_F64 (m in {3, 5, 7}). */
+lmag_status lmag_pade_theta(int precision, int m, double *theta_out);
+
+/* Histogram of the (m, s) selections of the last forward pass of this context:
+ * counts[m_index * 64 + s], m_index 0/1/2 for m = 3/5/7. Blocks (syncs the
+ * stream of the last call). */
+lmag_status lmag_last_selection_histogram(lmag_ctx *ctx, int64_t *counts_out /*[3*64]*/);
+
+/* Unit-test kernels on single 64 x 64 complex tiles of the given precision,
+ * DEVICE pointers, row-major. C = op(A) B (op = transpose when transA != 0);
+ * C = A^{-1} (no pivoting; A must be column diagonally dominant);
+ * C = exp(A) by the library's scaled Pade path, ms_out[0..1] = (m, s). */
+lmag_status lmag_debug_tile_gemm(lmag_ctx *ctx, int precision, const void *A, const void *B,
+                                 void *C, int transA, void *hip_stream);
+lmag_status lmag_debug_tile_inverse(lmag_ctx *ctx, int precision, const void *A, void *C,
+                                    void *hip_stream);
+lmag_status lmag_debug_tile_expm(lmag_ctx *ctx, int precision, const void *A, void *C,
+                                 int8_t *ms_out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMAG_H */

@@ -23,6 +23,7 @@ from .liouville import vec, unvec, liouvillian, lift_hamiltonian
 from .magnus import gl2_nodes, slice_omegas, slice_omega
 from .expm import expm_taylor, frechet_block
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
-                         grad_adjoint, grad_fd, rk4_propagator, slice_products)
+                         grad_adjoint, grad_adjoint_at, grad_fd, grad_fd_cached, rk4_propagator,
+                         slice_products)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

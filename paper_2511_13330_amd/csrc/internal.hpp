@@ -1,0 +1,151 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace lmag {
+
+// Pade coefficients b_j = (2m-j)! m! / ((2m)! j! (m-j)!), j = 0..m, and the
+// scaling thresholds theta_m, for the degrees this library evaluates.
+struct PadeTable {
+  double b3[4], b5[6], b7[8];
+};
+
+// One chunk of consecutive slices of one item; the unit of work of the slice
+// kernels. Slices are numbered globally over the whole call.
+struct Chunk {
+  int32_t item;        // item index
+  int32_t first;       // first global slice index
+  int32_t count;       // number of slices
+  int32_t chunk;       // global chunk index (into chunk-level arrays)
+};
+
+struct Item {
+  int32_t first_chunk; // global index of the item's first chunk
+  int32_t n_chunks;
+  int32_t first_slice; // global index of the item's first slice
+  int32_t n_slices;
+  int32_t target;      // target index (fidelity calls)
+  int32_t group;       // group index or -1
+};
+
+// Per-slice workspace tiles (row-major 64x64 complex of the compute type).
+enum { WS_S = 0, WS_PLOC = 1, WS_QINV = 2, WS_A2 = 3, WS_TILES = 4 };
+
+struct SliceArgs {
+  const void* basis;        // [nb][64][64] complex, compute type
+  int nb;
+  const double* alpha;      // [n_slices_total][nb]
+  const Chunk* chunks;
+  int n_chunks;
+  int* counter;             // persistent work counter (zeroed before launch)
+  void* ws_tiles;           // [n_slices_total][WS_TILES][64][64] (may be null for propagate)
+  int store;                // forward: store per-slice tiles
+  void* totals;             // [n_chunks][64][64] chunk products (forward output)
+  const void* env;          // [n_chunks][64][64] chunk environments W_c (backward input)
+  double* gtrace;           // [n_slices_total][nb] Re Tr(K_n B_j) (backward output)
+  int8_t* ms;               // [n_slices_total][2] Pade degree and scaling exponent
+  void* gscratch;           // per-workgroup global scratch slots (double precision)
+  PadeTable pade;
+};
+
+// launchers (kernel files)
+hipError_t launch_slice_forward(int prec, const SliceArgs& a, int grid, hipStream_t s);
+hipError_t launch_slice_backward(int prec, const SliceArgs& a, int grid, hipStream_t s);
+
+// system set-up (double precision, padded to 64x64 tiles)
+hipError_t launch_lift(const double* H, int d, double* out, hipStream_t s);
+hipError_t launch_dissipator(const double* Ls, int n_jump, int d, double* out, hipStream_t s);
+hipError_t launch_commutator(const double* X, const double* Y, double* out, hipStream_t s);
+hipError_t launch_cast(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_fill_int(int* p, int v, int n, hipStream_t s);
+
+struct AlphaArgs {
+  int prec;
+  const void* amps;          // [total_slices_in_amps][n_ctrl] of the compute type
+  const int64_t* item_amp_offset;   // [n_items] slice offset into amps
+  const Item* items;
+  int n_items;
+  const void* static_coef;  // [n_items][n_static] or null (zeros)
+  const void* ctrl_scale;   // [n_items][n_ctrl] or null (ones)
+  int n_ctrl, n_static, order, hold_foh, nb;
+  double dt;
+  const int32_t* slice_item;  // [n_slices_total] item of each global slice
+  double* alpha;            // out [n_slices_total][nb]
+  int n_slices_total;
+};
+hipError_t launch_alpha(const AlphaArgs& a, hipStream_t s);
+
+struct TargetArgs {
+  const double* U;          // [n_targets][d][d] complex128
+  int n_targets, d;
+  double* st64;             // out [n_targets][64][64] complex: S_T^dagger (padded)
+  float* st32;              // out, same in float (may be null)
+};
+hipError_t launch_targets(const TargetArgs& a, hipStream_t s);
+
+struct ScanArgs {
+  int prec;
+  const Item* items;
+  int n_items;
+  int n_chunks_total;
+  int step;                 // 2^k
+  const void* pre_in; void* pre_out;   // inclusive prefix arrays [n_chunks][64][64]
+  const void* suf_in; void* suf_out;   // inclusive suffix arrays (null = skip)
+};
+hipError_t launch_scan_level(const ScanArgs& a, const int32_t* chunk_item, hipStream_t s);
+
+struct EnvArgs {
+  int prec;
+  const Item* items;
+  int n_items;
+  const int32_t* chunk_item;   // [n_chunks]
+  int n_chunks_total;
+  const void* pre;          // inclusive prefixes
+  const void* suf;          // inclusive suffixes
+  const void* st;           // S_T^dagger tiles [n_targets][64][64] compute type
+  const double* st64;       // same in double
+  void* env;                // out W_c [n_chunks][64][64]
+  double* F;                // out [n_items] (Re), may be null
+  double* Fim;              // out [n_items] (Im), may be null
+  int d;
+};
+hipError_t launch_env(const EnvArgs& a, hipStream_t s);
+
+struct ExtractArgs {
+  int prec;
+  const Item* items;
+  int n_items;
+  const void* pre;          // inclusive prefixes; item total at its last chunk
+  void* out;                // [n_items][n][n] complex
+  int n;
+};
+hipError_t launch_extract(const ExtractArgs& a, hipStream_t s);
+
+struct GradArgs {
+  int prec;
+  const double* gtrace;     // [n_slices_total][nb]
+  const void* amps;
+  const int64_t* item_amp_offset;
+  const Item* items;
+  int n_items;
+  const void* static_coef;
+  const void* ctrl_scale;
+  int n_ctrl, n_static, order, hold_foh, nb;
+  double dt, inv_d2;
+  void* grad;               // out, like amps (per item) or per group
+  const int32_t* group_first_item;  // [n_groups+1] items sorted by group (null = no groups)
+  const int32_t* group_items;       // [n_items]
+  int n_groups;
+  double* F_items;          // [n_items] per-item fidelity (group mean input)
+  double* F_out;            // [n_groups] group means (grouped calls)
+};
+hipError_t launch_grad(const GradArgs& a, int max_slices, hipStream_t s);
+
+// debug / unit-test kernels (single 64x64 tiles)
+hipError_t launch_debug_gemm(int prec, const void* A, const void* B, void* C, int transA, hipStream_t s);
+hipError_t launch_debug_inverse(int prec, const void* A, void* C, hipStream_t s);
+hipError_t launch_debug_expm(int prec, const void* A, void* C, int8_t* ms, void* gscratch, PadeTable pt, hipStream_t s);
+
+}  // namespace lmag

@@ -1,0 +1,679 @@
+// Host side of the C ABI declared in include/lmag.h: context, validation,
+// system set-up, work planning, workspace and kernel sequencing.
+#include "../../include/lmag.h"
+#include "internal.hpp"
+#include "tile.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace lmag;
+
+namespace {
+
+constexpr int TILE = 64 * 64;
+constexpr int SLOT = 64 * PITCH;
+
+struct Status {
+  lmag_status code;
+  std::string msg;
+};
+
+// Pade coefficients from the closed form b_j = (2m-j)! m! / ((2m)! j! (m-j)!).
+void pade_coeffs(int m, double* b) {
+  auto fact = [](int k) { double f = 1.0; for (int i = 2; i <= k; ++i) f *= i; return f; };
+  for (int j = 0; j <= m; ++j)
+    b[j] = fact(2 * m - j) * fact(m) / (fact(2 * m) * fact(j) * fact(m - j));
+}
+
+const double kTheta32_3 = 4.258730016922831e-1;
+const double kTheta64[3] = {1.495585217958292e-2, 2.539398330063230e-1, 9.504178996162932e-1};
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct lmag_ctx {
+  int device = 0;
+  int n_cu = 0;
+  std::string err;
+  // system
+  bool has_sys = false;
+  int d = 0, n = 0, ns = 0, nc = 0, nj = 0, prec = 32, order = 1, hold = 0, nb = 0, chunk = 0;
+  size_t ws_max = 0;
+  double* basis64 = nullptr;
+  void* basis32 = nullptr;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  char* pinned = nullptr;
+  size_t pinned_size = 0;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  hipStream_t last_stream = nullptr;
+  int8_t* last_ms = nullptr;
+  int last_total_slices = 0;
+  void* dbg_scratch = nullptr;
+  PadeTable pade{};
+
+  lmag_status fail(lmag_status c, const std::string& m) {
+    err = m;
+    return c;
+  }
+  lmag_status hip_fail(hipError_t e, const char* where) {
+    err = std::string(where) + ": " + hipGetErrorString(e);
+    return LMAG_E_DEVICE;
+  }
+};
+
+namespace {
+
+struct Plan {
+  std::vector<Item> items;
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> chunk_item, slice_item;
+  std::vector<int64_t> amp_off;
+  std::vector<int32_t> group_first, group_items;
+  int total_slices = 0, total_chunks = 0, max_slices = 0, max_chunks = 0, n_groups = 0;
+};
+
+struct Layout {
+  size_t items, chunks, chunk_item, slice_item, amp_off, group_first, group_items, meta_end;
+  size_t counters, alpha, gtrace, ms, F_items, st64, st, totals, pre[2], suf[2], env, gscratch,
+      tiles, total;
+};
+
+lmag_status plan_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+                       int n_targets, Plan& p) {
+  if (!b) return c->fail(LMAG_E_INVALID, "batch is NULL");
+  if (b->n_items < 1) return c->fail(LMAG_E_INVALID, "n_items must be >= 1");
+  if (!b->n_slices || !b->slice_offset) return c->fail(LMAG_E_INVALID, "n_slices/slice_offset NULL");
+  if (!b->amps) return c->fail(LMAG_E_INVALID, "amps is NULL");
+  if (!(b->dt > 0.0) || !std::isfinite(b->dt)) return c->fail(LMAG_E_INVALID, "dt must be finite and > 0");
+  if (b->n_groups < 0) return c->fail(LMAG_E_INVALID, "n_groups < 0");
+  if (b->n_groups > 0 && !b->group_of_item) return c->fail(LMAG_E_INVALID, "group_of_item NULL");
+  long long total = 0;
+  for (int i = 0; i < b->n_items; ++i) {
+    if (b->n_slices[i] < 1) return c->fail(LMAG_E_INVALID, "n_slices[i] < 1");
+    if (b->slice_offset[i] < 0) return c->fail(LMAG_E_INVALID, "slice_offset[i] < 0");
+    total += b->n_slices[i];
+  }
+  if (total > (1LL << 30)) return c->fail(LMAG_E_UNSUPPORTED, "too many slices in one call");
+  if (target_of_item)
+    for (int i = 0; i < b->n_items; ++i)
+      if (target_of_item[i] < 0 || target_of_item[i] >= n_targets)
+        return c->fail(LMAG_E_INVALID, "target_of_item out of range");
+  // chunk size
+  int C = c->chunk;
+  if (C <= 0) {
+    long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
+    C = (int)std::min<long long>(64, std::max<long long>(1, per));
+  }
+  p.items.resize(b->n_items);
+  p.amp_off.resize(b->n_items);
+  int slice = 0, chunk = 0;
+  for (int i = 0; i < b->n_items; ++i) {
+    const int N = b->n_slices[i];
+    const int L = (N + C - 1) / C;
+    Item it{};
+    it.first_chunk = chunk; it.n_chunks = L; it.first_slice = slice; it.n_slices = N;
+    it.target = target_of_item ? target_of_item[i] : 0;
+    it.group = b->n_groups > 0 ? b->group_of_item[i] : -1;
+    p.items[i] = it;
+    p.amp_off[i] = b->slice_offset[i];
+    for (int k = 0; k < L; ++k) {
+      Chunk ch{};
+      ch.item = i; ch.first = slice + k * C; ch.count = std::min(C, N - k * C); ch.chunk = chunk + k;
+      p.chunks.push_back(ch);
+      p.chunk_item.push_back(i);
+    }
+    for (int k = 0; k < N; ++k) p.slice_item.push_back(i);
+    slice += N;
+    chunk += L;
+    p.max_slices = std::max(p.max_slices, N);
+    p.max_chunks = std::max(p.max_chunks, L);
+  }
+  p.total_slices = slice;
+  p.total_chunks = chunk;
+  // largest chunks first for the persistent kernels (all equal except item tails)
+  std::stable_sort(p.chunks.begin(), p.chunks.end(),
+                   [](const Chunk& a, const Chunk& b2) { return a.count > b2.count; });
+  if (b->n_groups > 0) {
+    p.n_groups = b->n_groups;
+    std::vector<std::vector<int32_t>> g(b->n_groups);
+    for (int i = 0; i < b->n_items; ++i) {
+      const int gi = b->group_of_item[i];
+      if (gi < 0 || gi >= b->n_groups) return c->fail(LMAG_E_INVALID, "group_of_item out of range");
+      g[gi].push_back(i);
+    }
+    p.group_first.push_back(0);
+    for (int gi = 0; gi < b->n_groups; ++gi) {
+      if (g[gi].empty()) return c->fail(LMAG_E_INVALID, "empty group");
+      const int i0 = g[gi][0];
+      for (int i : g[gi]) {
+        if (b->slice_offset[i] != b->slice_offset[i0] || b->n_slices[i] != b->n_slices[i0])
+          return c->fail(LMAG_E_INVALID, "items of a group must share amplitudes and length");
+        p.group_items.push_back(i);
+      }
+      p.group_first.push_back((int32_t)p.group_items.size());
+    }
+  }
+  return LMAG_OK;
+}
+
+Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int grid) {
+  const size_t es = (c->prec == 32 ? 8 : 16);
+  const size_t tile = (size_t)TILE * es;
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  L.items = take(p.items.size() * sizeof(Item));
+  L.chunks = take(p.chunks.size() * sizeof(Chunk));
+  L.chunk_item = take(p.chunk_item.size() * 4);
+  L.slice_item = take(p.slice_item.size() * 4);
+  L.amp_off = take(p.amp_off.size() * 8);
+  L.group_first = take(p.group_first.size() * 4);
+  L.group_items = take(p.group_items.size() * 4);
+  L.meta_end = o;
+  L.counters = take(256);
+  L.alpha = take((size_t)p.total_slices * c->nb * 8);
+  L.gtrace = grad ? take((size_t)p.total_slices * c->nb * 8) : 0;
+  L.ms = take((size_t)p.total_slices * 2);
+  L.F_items = take(p.items.size() * 8);
+  L.st64 = take((size_t)std::max(1, n_targets) * TILE * 16);
+  L.st = take((size_t)std::max(1, n_targets) * tile);
+  L.totals = take((size_t)p.total_chunks * tile);
+  L.pre[0] = take((size_t)p.total_chunks * tile);
+  L.pre[1] = take((size_t)p.total_chunks * tile);
+  L.suf[0] = grad ? take((size_t)p.total_chunks * tile) : 0;
+  L.suf[1] = grad ? take((size_t)p.total_chunks * tile) : 0;
+  L.env = grad ? take((size_t)p.total_chunks * tile) : 0;
+  L.gscratch = c->prec == 64 ? take((size_t)grid * 2 * SLOT * es) : 0;
+  L.tiles = grad ? take((size_t)p.total_slices * WS_TILES * tile) : 0;
+  L.total = o;
+  return L;
+}
+
+lmag_status ensure_ws(lmag_ctx* c, size_t bytes) {
+  if (c->ws_max && bytes > c->ws_max)
+    return c->fail(LMAG_E_NOMEM, "workspace of " + std::to_string(bytes) +
+                                     " bytes exceeds workspace_bytes_max");
+  if (bytes <= c->ws_size) return LMAG_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return c->hip_fail(e, "hipDeviceSynchronize");
+  if (c->ws) (void)hipFree(c->ws);
+  c->ws = nullptr;
+  c->ws_size = 0;
+  const size_t want = align_up(bytes + bytes / 8, 1 << 20);
+  e = hipMalloc((void**)&c->ws, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->ws = nullptr;
+    return c->fail(LMAG_E_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  c->ws_size = want;
+  return LMAG_OK;
+}
+
+lmag_status ensure_pinned(lmag_ctx* c, size_t bytes) {
+  if (c->upload_pending) {
+    hipError_t e = hipEventSynchronize(c->upload_done);
+    if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+    c->upload_pending = false;
+  }
+  if (bytes <= c->pinned_size) return LMAG_OK;
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  c->pinned = nullptr;
+  c->pinned_size = 0;
+  const size_t want = align_up(bytes + bytes / 4, 1 << 16);
+  hipError_t e = hipHostMalloc((void**)&c->pinned, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return c->fail(LMAG_E_NOMEM, "hipHostMalloc failed");
+  }
+  c->pinned_size = want;
+  return LMAG_OK;
+}
+
+lmag_status upload_plan(lmag_ctx* c, const Plan& p, const Layout& L, hipStream_t s) {
+  lmag_status st = ensure_pinned(c, L.meta_end);
+  if (st != LMAG_OK) return st;
+  char* h = c->pinned;
+  std::memset(h, 0, L.meta_end);
+  auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(h + off, src, bytes); };
+  put(L.items, p.items.data(), p.items.size() * sizeof(Item));
+  put(L.chunks, p.chunks.data(), p.chunks.size() * sizeof(Chunk));
+  put(L.chunk_item, p.chunk_item.data(), p.chunk_item.size() * 4);
+  put(L.slice_item, p.slice_item.data(), p.slice_item.size() * 4);
+  put(L.amp_off, p.amp_off.data(), p.amp_off.size() * 8);
+  put(L.group_first, p.group_first.data(), p.group_first.size() * 4);
+  put(L.group_items, p.group_items.data(), p.group_items.size() * 4);
+  hipError_t e = hipMemcpyAsync(c->ws, h, L.meta_end, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(plan)");
+  e = hipEventRecord(c->upload_done, s);
+  if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
+  c->upload_pending = true;
+  return LMAG_OK;
+}
+
+#define HIPCHK(expr, where)                           \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return c->hip_fail(e_, where); \
+  } while (0)
+
+// The common pipeline: alpha, forward slices, chunk scans, (environments,
+// fidelity, backward slices, chain rule). Returns the index (0/1) of the final
+// prefix buffer through *pre_final.
+lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L, bool grad,
+                bool fidelity, const void* U_target, int n_targets, double* F_out, void* grad_out,
+                void* S_out, hipStream_t s, int grid) {
+  char* w = c->ws;
+  auto at = [&](size_t off) { return (void*)(w + off); };
+  const Item* items = (const Item*)at(L.items);
+  const size_t es = (c->prec == 32 ? 8 : 16);
+  (void)es;
+
+  AlphaArgs aa{};
+  aa.prec = c->prec; aa.amps = b->amps; aa.item_amp_offset = (const int64_t*)at(L.amp_off);
+  aa.items = items; aa.n_items = b->n_items; aa.static_coef = b->static_coef;
+  aa.ctrl_scale = b->ctrl_scale; aa.n_ctrl = c->nc; aa.n_static = c->ns; aa.order = c->order;
+  aa.hold_foh = c->hold == LMAG_FOH; aa.nb = c->nb; aa.dt = b->dt;
+  aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(L.alpha);
+  aa.n_slices_total = p.total_slices;
+  HIPCHK(launch_alpha(aa, s), "alpha");
+  HIPCHK(launch_fill_int((int*)at(L.counters), 0, 64, s), "fill");
+
+  SliceArgs sa{};
+  sa.basis = c->prec == 32 ? c->basis32 : (const void*)c->basis64;
+  sa.nb = c->nb; sa.alpha = (const double*)at(L.alpha);
+  sa.chunks = (const Chunk*)at(L.chunks); sa.n_chunks = p.total_chunks;
+  sa.counter = (int*)at(L.counters);
+  sa.ws_tiles = grad ? at(L.tiles) : nullptr; sa.store = grad ? 1 : 0;
+  sa.totals = at(L.totals); sa.env = grad ? at(L.env) : nullptr;
+  sa.gtrace = grad ? (double*)at(L.gtrace) : nullptr; sa.ms = (int8_t*)at(L.ms);
+  sa.gscratch = c->prec == 64 ? at(L.gscratch) : nullptr; sa.pade = c->pade;
+  HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward");
+  c->last_ms = (int8_t*)at(L.ms);
+  c->last_total_slices = p.total_slices;
+
+  // inclusive prefix (and suffix) of chunk totals, Hillis-Steele levels
+  const bool want_suf = grad;
+  const void* pre_cur = at(L.totals);
+  const void* suf_cur = at(L.totals);
+  int buf = 0;
+  for (int st = 1; st < p.max_chunks; st <<= 1) {
+    ScanArgs sc{};
+    sc.prec = c->prec; sc.items = items; sc.n_items = b->n_items;
+    sc.n_chunks_total = p.total_chunks; sc.step = st;
+    sc.pre_in = pre_cur; sc.pre_out = at(L.pre[buf]);
+    sc.suf_in = want_suf ? suf_cur : nullptr; sc.suf_out = want_suf ? at(L.suf[buf]) : nullptr;
+    HIPCHK(launch_scan_level(sc, (const int32_t*)at(L.chunk_item), s), "scan");
+    pre_cur = at(L.pre[buf]);
+    if (want_suf) suf_cur = at(L.suf[buf]);
+    buf ^= 1;
+  }
+
+  if (S_out) {
+    ExtractArgs ea{};
+    ea.prec = c->prec; ea.items = items; ea.n_items = b->n_items; ea.pre = pre_cur;
+    ea.out = S_out; ea.n = c->n;
+    HIPCHK(launch_extract(ea, s), "extract");
+  }
+  if (!fidelity) return LMAG_OK;
+
+  TargetArgs ta{};
+  ta.U = (const double*)U_target; ta.n_targets = n_targets; ta.d = c->d;
+  ta.st64 = (double*)at(L.st64);
+  ta.st32 = c->prec == 32 ? (float*)at(L.st) : nullptr;
+  HIPCHK(launch_targets(ta, s), "targets");
+  const void* st_tiles = c->prec == 32 ? at(L.st) : at(L.st64);
+
+  const bool grouped = p.n_groups > 0;
+  double* F_items = grouped ? (double*)at(L.F_items) : F_out;
+  EnvArgs ev{};
+  ev.prec = c->prec; ev.items = items; ev.n_items = b->n_items;
+  ev.chunk_item = (const int32_t*)at(L.chunk_item); ev.n_chunks_total = p.total_chunks;
+  ev.pre = pre_cur; ev.suf = suf_cur; ev.st = st_tiles; ev.st64 = (const double*)at(L.st64);
+  ev.env = grad ? at(L.env) : nullptr; ev.F = F_items; ev.Fim = nullptr; ev.d = c->d;
+  HIPCHK(launch_env(ev, s), "env");
+
+  if (grad) {
+    HIPCHK(launch_fill_int((int*)at(L.counters) + 16, 0, 16, s), "fill");
+    sa.counter = (int*)at(L.counters) + 16;
+    HIPCHK(launch_slice_backward(c->prec, sa, grid, s), "backward");
+  }
+  if (grad || grouped) {
+    GradArgs ga{};
+    ga.prec = c->prec; ga.gtrace = grad ? (const double*)at(L.gtrace) : nullptr;
+    ga.amps = b->amps; ga.item_amp_offset = (const int64_t*)at(L.amp_off); ga.items = items;
+    ga.n_items = b->n_items; ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
+    ga.n_ctrl = c->nc; ga.n_static = c->ns; ga.order = c->order; ga.hold_foh = c->hold == LMAG_FOH;
+    ga.nb = c->nb; ga.dt = b->dt; ga.inv_d2 = 1.0 / ((double)c->d * c->d);
+    ga.grad = grad ? grad_out : nullptr;
+    ga.group_first_item = grouped ? (const int32_t*)at(L.group_first) : nullptr;
+    ga.group_items = grouped ? (const int32_t*)at(L.group_items) : nullptr;
+    ga.n_groups = p.n_groups; ga.F_items = F_items; ga.F_out = grouped ? F_out : nullptr;
+    if (!grad) {
+      // group means of F only: reuse the grad kernel with a null gradient
+      ga.gtrace = nullptr;
+    }
+    HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad");
+  }
+  return LMAG_OK;
+}
+
+lmag_status prepare(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item, int n_targets,
+                    bool grad, bool fidelity, Plan& p, Layout& L, int& grid, hipStream_t s) {
+  lmag_status st = plan_batch(c, b, target_of_item, fidelity ? n_targets : 1, p);
+  if (st != LMAG_OK) return st;
+  grid = std::max(1, std::min(p.total_chunks, c->n_cu));
+  L = layout(c, p, fidelity ? n_targets : 0, grad, grid);
+  st = ensure_ws(c, L.total);
+  if (st != LMAG_OK) return st;
+  return upload_plan(c, p, L, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lmag_version(void) { return "lmag 0.1 (gfx950)"; }
+
+lmag_status lmag_create(lmag_ctx** out, int hip_device) {
+  if (!out) return LMAG_E_INVALID;
+  *out = nullptr;
+  try {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+      (void)hipGetLastError();
+      return LMAG_E_DEVICE;
+    }
+    lmag_ctx* c = new lmag_ctx();
+    c->device = hip_device;
+    DeviceGuard g(hip_device);
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
+        c->n_cu <= 0)
+      c->n_cu = 256;
+    if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess) {
+      delete c;
+      return LMAG_E_DEVICE;
+    }
+    pade_coeffs(3, c->pade.b3);
+    pade_coeffs(5, c->pade.b5);
+    pade_coeffs(7, c->pade.b7);
+    *out = c;
+    return LMAG_OK;
+  } catch (...) {
+    return LMAG_E_NOMEM;
+  }
+}
+
+void lmag_destroy(lmag_ctx* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->basis64) (void)hipFree(c->basis64);
+  if (c->basis32) (void)hipFree(c->basis32);
+  if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  delete c;
+}
+
+const char* lmag_last_error(const lmag_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+static bool finite_array(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
+  if (!c) return LMAG_E_INVALID;
+  try {
+    if (!s) return c->fail(LMAG_E_INVALID, "system descriptor is NULL");
+    const int d = s->d;
+    if (d < 1 || d * d > 64) return c->fail(d * d > 64 && d <= 64 ? LMAG_E_UNSUPPORTED : LMAG_E_INVALID,
+                                            "d must satisfy 1 <= d and d*d <= 64");
+    if (s->n_static < 0 || s->n_ctrl < 0 || s->n_jump < 0)
+      return c->fail(LMAG_E_INVALID, "negative operator count");
+    if (s->n_ctrl > 8 || s->n_static > 8) return c->fail(LMAG_E_UNSUPPORTED, "at most 8 controls and 8 static terms");
+    if ((s->n_static && !s->H_static) || (s->n_ctrl && !s->H_ctrl) || (s->n_jump && !s->L_jump))
+      return c->fail(LMAG_E_INVALID, "operator array is NULL");
+    if (s->precision != LMAG_F32 && s->precision != LMAG_F64)
+      return c->fail(LMAG_E_INVALID, "precision must be LMAG_F32 or LMAG_F64");
+    if (s->magnus_order != 1 && s->magnus_order != 2)
+      return c->fail(LMAG_E_INVALID, "magnus_order must be 1 or 2");
+    if (s->hold != LMAG_ZOH && s->hold != LMAG_FOH) return c->fail(LMAG_E_INVALID, "hold must be ZOH or FOH");
+    if (s->chunk_slices < 0) return c->fail(LMAG_E_INVALID, "chunk_slices < 0");
+    const size_t dd2 = (size_t)d * d * 2;
+    if ((s->n_static && !finite_array(s->H_static, s->n_static * dd2)) ||
+        (s->n_ctrl && !finite_array(s->H_ctrl, s->n_ctrl * dd2)) ||
+        (s->n_jump && !finite_array(s->L_jump, s->n_jump * dd2)))
+      return c->fail(LMAG_E_INVALID, "non-finite operator entry");
+    const int nc = s->n_ctrl, ns = s->n_static;
+    int nb = nc + ns + 1;
+    if (s->magnus_order == 2) nb += nc + nc * ns + nc * (nc - 1) / 2;
+    if (nb > 32) return c->fail(LMAG_E_UNSUPPORTED, "basis larger than 32 tiles");
+
+    DeviceGuard g(c->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return c->hip_fail(e, "hipDeviceSynchronize");
+    if (c->basis64) (void)hipFree(c->basis64);
+    if (c->basis32) (void)hipFree(c->basis32);
+    c->basis64 = nullptr;
+    c->basis32 = nullptr;
+    c->has_sys = false;
+    const size_t tb = (size_t)TILE * 16;
+    double* ops = nullptr;
+    const size_t nops = (size_t)(ns + nc + s->n_jump) * dd2;
+    if (hipMalloc((void**)&c->basis64, nb * tb) != hipSuccess ||
+        hipMalloc(&c->basis32, nb * (size_t)TILE * 8) != hipSuccess ||
+        hipMalloc((void**)&ops, std::max<size_t>(8, nops * 8)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (ops) (void)hipFree(ops);
+      return c->fail(LMAG_E_NOMEM, "basis allocation failed");
+    }
+    std::vector<double> hops(std::max<size_t>(1, nops));
+    size_t o = 0;
+    if (ns) std::memcpy(&hops[o], s->H_static, ns * dd2 * 8), o += ns * dd2;
+    if (nc) std::memcpy(&hops[o], s->H_ctrl, nc * dd2 * 8), o += nc * dd2;
+    if (s->n_jump) std::memcpy(&hops[o], s->L_jump, s->n_jump * dd2 * 8), o += s->n_jump * dd2;
+    hipStream_t st = nullptr;
+    if (nops) HIPCHK(hipMemcpy(ops, hops.data(), nops * 8, hipMemcpyHostToDevice), "hipMemcpy(ops)");
+    const double* Hs = ops;
+    const double* Hc = ops + ns * dd2;
+    const double* Lj = ops + (ns + nc) * dd2;
+    auto tile = [&](int j) { return c->basis64 + (size_t)j * TILE * 2; };
+    // L_c | Z_i | D | [L_c, D] | [L_c, Z_i] | [L_p, L_q]
+    for (int cc = 0; cc < nc; ++cc) HIPCHK(launch_lift(Hc + cc * dd2, d, tile(cc), st), "lift");
+    for (int i = 0; i < ns; ++i) HIPCHK(launch_lift(Hs + i * dd2, d, tile(nc + i), st), "lift");
+    HIPCHK(launch_dissipator(Lj, s->n_jump, d, tile(nc + ns), st), "dissipator");
+    if (s->magnus_order == 2) {
+      int j = nc + ns + 1;
+      for (int cc = 0; cc < nc; ++cc) HIPCHK(launch_commutator(tile(cc), tile(nc + ns), tile(j++), st), "comm");
+      for (int cc = 0; cc < nc; ++cc)
+        for (int i = 0; i < ns; ++i) HIPCHK(launch_commutator(tile(cc), tile(nc + i), tile(j++), st), "comm");
+      for (int p = 0; p < nc; ++p)
+        for (int q = p + 1; q < nc; ++q) HIPCHK(launch_commutator(tile(p), tile(q), tile(j++), st), "comm");
+    }
+    HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * TILE * 2, st), "cast");
+    HIPCHK(hipDeviceSynchronize(), "set_system sync");
+    (void)hipFree(ops);
+    c->d = d; c->n = d * d; c->ns = ns; c->nc = nc; c->nj = s->n_jump;
+    c->prec = s->precision; c->order = s->magnus_order; c->hold = s->hold; c->nb = nb;
+    c->chunk = s->chunk_slices; c->ws_max = s->workspace_bytes_max;
+    c->has_sys = true;
+    return LMAG_OK;
+  } catch (const std::bad_alloc&) {
+    return c->fail(LMAG_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& ex) {
+    return c->fail(LMAG_E_DEVICE, ex.what());
+  } catch (...) {
+    return c->fail(LMAG_E_DEVICE, "unknown error");
+  }
+}
+
+lmag_status lmag_propagate(lmag_ctx* c, const lmag_batch* b, void* S_out, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  try {
+    if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
+    if (!S_out) return c->fail(LMAG_E_INVALID, "S_out is NULL");
+    if (b && b->n_groups) return c->fail(LMAG_E_INVALID, "groups apply to fidelity calls only");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    Plan p;
+    Layout L{};
+    int grid = 0;
+    lmag_status st = prepare(c, b, nullptr, 0, false, false, p, L, grid, s);
+    if (st != LMAG_OK) return st;
+    c->last_stream = s;
+    return run(c, b, p, L, false, false, nullptr, 0, nullptr, nullptr, S_out, s, grid);
+  } catch (const std::bad_alloc&) {
+    return c->fail(LMAG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return c->fail(LMAG_E_DEVICE, "unknown error");
+  }
+}
+
+lmag_status lmag_fidelity_and_grad(lmag_ctx* c, const lmag_batch* b, const void* U_target,
+                                   int n_targets, const int32_t* target_of_item, double* F_out,
+                                   void* grad_out, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  try {
+    if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
+    if (!U_target || n_targets < 1) return c->fail(LMAG_E_INVALID, "U_target NULL or n_targets < 1");
+    if (!F_out) return c->fail(LMAG_E_INVALID, "F_out is NULL");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    Plan p;
+    Layout L{};
+    int grid = 0;
+    const bool grad = grad_out != nullptr;
+    lmag_status st = prepare(c, b, target_of_item, n_targets, grad, true, p, L, grid, s);
+    if (st != LMAG_OK) return st;
+    c->last_stream = s;
+    return run(c, b, p, L, grad, true, U_target, n_targets, F_out, grad_out, nullptr, s, grid);
+  } catch (const std::bad_alloc&) {
+    return c->fail(LMAG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return c->fail(LMAG_E_DEVICE, "unknown error");
+  }
+}
+
+lmag_status lmag_sync(lmag_ctx* c, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  DeviceGuard g(c->device);
+  hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+  if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return c->hip_fail(e, "pending device error");
+  return LMAG_OK;
+}
+
+lmag_status lmag_pade_coefficients(int m, double* b_out) {
+  if (!b_out || (m != 3 && m != 5 && m != 7)) return LMAG_E_INVALID;
+  pade_coeffs(m, b_out);
+  return LMAG_OK;
+}
+
+lmag_status lmag_pade_theta(int precision, int m, double* theta_out) {
+  if (!theta_out) return LMAG_E_INVALID;
+  if (precision == LMAG_F32) {
+    if (m != 3) return LMAG_E_INVALID;
+    *theta_out = kTheta32_3;
+    return LMAG_OK;
+  }
+  if (precision == LMAG_F64) {
+    if (m == 3) *theta_out = kTheta64[0];
+    else if (m == 5) *theta_out = kTheta64[1];
+    else if (m == 7) *theta_out = kTheta64[2];
+    else return LMAG_E_INVALID;
+    return LMAG_OK;
+  }
+  return LMAG_E_INVALID;
+}
+
+lmag_status lmag_last_selection_histogram(lmag_ctx* c, int64_t* counts) {
+  if (!c) return LMAG_E_INVALID;
+  if (!counts) return c->fail(LMAG_E_INVALID, "counts is NULL");
+  DeviceGuard g(c->device);
+  std::memset(counts, 0, sizeof(int64_t) * 3 * 64);
+  if (!c->last_ms || c->last_total_slices <= 0) return LMAG_OK;
+  std::vector<int8_t> h((size_t)c->last_total_slices * 2);
+  hipError_t e = hipStreamSynchronize(c->last_stream);
+  if (e != hipSuccess) return c->hip_fail(e, "hipStreamSynchronize");
+  e = hipMemcpy(h.data(), c->last_ms, h.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return c->hip_fail(e, "hipMemcpy(ms)");
+  for (int i = 0; i < c->last_total_slices; ++i) {
+    const int m = h[2 * i], s = h[2 * i + 1];
+    const int mi = m == 3 ? 0 : (m == 5 ? 1 : (m == 7 ? 2 : -1));
+    if (mi >= 0 && s >= 0 && s < 64) counts[mi * 64 + s]++;
+  }
+  return LMAG_OK;
+}
+
+lmag_status lmag_debug_tile_gemm(lmag_ctx* c, int precision, const void* A, const void* B, void* C,
+                                 int transA, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (!A || !B || !C) return c->fail(LMAG_E_INVALID, "NULL tile");
+  if (precision != LMAG_F32 && precision != LMAG_F64) return c->fail(LMAG_E_INVALID, "precision");
+  DeviceGuard g(c->device);
+  HIPCHK(launch_debug_gemm(precision, A, B, C, transA, (hipStream_t)hip_stream), "debug_gemm");
+  return LMAG_OK;
+}
+
+lmag_status lmag_debug_tile_inverse(lmag_ctx* c, int precision, const void* A, void* C, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (!A || !C) return c->fail(LMAG_E_INVALID, "NULL tile");
+  if (precision != LMAG_F32 && precision != LMAG_F64) return c->fail(LMAG_E_INVALID, "precision");
+  DeviceGuard g(c->device);
+  HIPCHK(launch_debug_inverse(precision, A, C, (hipStream_t)hip_stream), "debug_inverse");
+  return LMAG_OK;
+}
+
+lmag_status lmag_debug_tile_expm(lmag_ctx* c, int precision, const void* A, void* C, int8_t* ms,
+                                 void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (!A || !C || !ms) return c->fail(LMAG_E_INVALID, "NULL pointer");
+  if (precision != LMAG_F32 && precision != LMAG_F64) return c->fail(LMAG_E_INVALID, "precision");
+  DeviceGuard g(c->device);
+  if (!c->dbg_scratch) {
+    hipError_t e = hipMalloc(&c->dbg_scratch, (size_t)2 * SLOT * 16);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c->dbg_scratch = nullptr;
+      return c->fail(LMAG_E_NOMEM, "debug scratch");
+    }
+  }
+  HIPCHK(launch_debug_expm(precision, A, C, ms, c->dbg_scratch, c->pade, (hipStream_t)hip_stream),
+         "debug_expm");
+  return LMAG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+"""Python binding of the C ABI with the same names: lmag.System wraps a context
+and its system; propagate / fidelity_and_grad marshal torch tensors (device
+memory and streams only) into the C calls. Every step of the path runs in the
+library's HIP kernels."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import lib, check, SystemDesc, Batch
+
+_PREC = {"f32": _lib.LMAG_F32, "f64": _lib.LMAG_F64}
+_HOLD = {"zoh": _lib.LMAG_ZOH, "foh": _lib.LMAG_FOH}
+_RDT = {"f32": torch.float32, "f64": torch.float64}
+_CDT = {"f32": torch.complex64, "f64": torch.complex128}
+
+
+def _ops(a, d):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(-1, d, d))
+    return a, a.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class System:
+    """A context bound to one GPU with one installed system."""
+
+    def __init__(self, H_static, H_ctrl, L_jump, precision="f32", magnus_order=2,
+                 hold="foh", device=0, workspace_bytes_max=0, chunk_slices=0):
+        self.d = int(np.asarray(H_ctrl if len(H_ctrl) else H_static).shape[-1])
+        self.n = self.d * self.d
+        self.precision = precision
+        self.rdtype = _RDT[precision]
+        self.cdtype = _CDT[precision]
+        self.device = torch.device("cuda", device)
+        self.n_ctrl = len(H_ctrl)
+        self.n_static = len(H_static)
+        L = lib()
+        self._ctx = ctypes.c_void_p()
+        check(L.lmag_create(ctypes.byref(self._ctx), device))
+        self._keep = []
+        hs, phs = _ops(H_static, self.d) if self.n_static else (None, None)
+        hc, phc = _ops(H_ctrl, self.d) if self.n_ctrl else (None, None)
+        lj, plj = _ops(L_jump, self.d) if len(L_jump) else (None, None)
+        desc = SystemDesc(self.d, self.n_static, phs, self.n_ctrl, phc, len(L_jump), plj,
+                          _PREC[precision], magnus_order, _HOLD[hold],
+                          workspace_bytes_max, chunk_slices)
+        check(L.lmag_set_system(self._ctx, ctypes.byref(desc)), self._ctx)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().lmag_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ marshalling
+    def _batch(self, amps, n_slices, slice_offset, dt, static_coef, ctrl_scale, groups):
+        if not (amps.is_cuda and amps.dtype == self.rdtype and amps.is_contiguous()):
+            raise TypeError(f"amps must be a contiguous {self.rdtype} CUDA tensor")
+        if amps.dim() != 2 or amps.shape[1] != self.n_ctrl:
+            raise ValueError("amps must be [rows, n_ctrl]")
+        n_slices = np.ascontiguousarray(n_slices, dtype=np.int32).reshape(-1)
+        n_items = len(n_slices)
+        if slice_offset is None:
+            slice_offset = np.concatenate([[0], np.cumsum(n_slices)[:-1]])
+        slice_offset = np.ascontiguousarray(slice_offset, dtype=np.int64).reshape(-1)
+        if len(slice_offset) != n_items:
+            raise ValueError("slice_offset length")
+        if np.any(slice_offset + n_slices > amps.shape[0]):
+            raise ValueError("an item reads past the end of amps")
+        keep = [n_slices, slice_offset]
+
+        def dev64(x, cols):
+            if x is None:
+                return None
+            t = torch.as_tensor(x, dtype=torch.float64, device=self.device).reshape(n_items, cols)
+            t = t.contiguous()
+            keep.append(t)
+            return ctypes.c_void_p(t.data_ptr())
+
+        sc = dev64(static_coef, self.n_static) if self.n_static else None
+        cs = dev64(ctrl_scale, self.n_ctrl)
+        gp, ng = None, 0
+        if groups is not None:
+            groups = np.ascontiguousarray(groups, dtype=np.int32).reshape(-1)
+            keep.append(groups)
+            ng = int(groups.max()) + 1
+            gp = groups.ctypes.data_as(_lib.c_int32_p)
+        b = Batch(n_items, n_slices.ctypes.data_as(_lib.c_int32_p),
+                  slice_offset.ctypes.data_as(_lib.c_int64_p), ctypes.c_void_p(amps.data_ptr()),
+                  sc, cs, float(dt), ng, gp)
+        return b, keep, n_items, ng
+
+    def propagate(self, amps, n_slices, dt, slice_offset=None, static_coef=None,
+                  ctrl_scale=None, stream=None):
+        """U of every item: [n_items, n, n] complex tensor (column-stacking)."""
+        b, keep, n_items, _ = self._batch(amps, n_slices, slice_offset, dt, static_coef,
+                                          ctrl_scale, None)
+        out = torch.empty((n_items, self.n, self.n), dtype=self.cdtype, device=self.device)
+        check(lib().lmag_propagate(self._ctx, ctypes.byref(b), ctypes.c_void_p(out.data_ptr()),
+                                   _stream(stream)), self._ctx)
+        return out
+
+    def fidelity_and_grad(self, amps, n_slices, dt, U_target, slice_offset=None,
+                          static_coef=None, ctrl_scale=None, target_of_item=None,
+                          groups=None, want_grad=True, stream=None):
+        """(F [n_items or n_groups] float64, dF/du like amps or None)."""
+        b, keep, n_items, ng = self._batch(amps, n_slices, slice_offset, dt, static_coef,
+                                           ctrl_scale, groups)
+        UT = torch.as_tensor(U_target, dtype=torch.complex128, device=self.device)
+        UT = UT.reshape(-1, self.d, self.d).contiguous()
+        tp = None
+        if target_of_item is not None:
+            toi = np.ascontiguousarray(target_of_item, dtype=np.int32).reshape(-1)
+            keep.append(toi)
+            tp = toi.ctypes.data_as(_lib.c_int32_p)
+        F = torch.empty(ng if ng else n_items, dtype=torch.float64, device=self.device)
+        grad = torch.empty_like(amps) if want_grad else None
+        check(lib().lmag_fidelity_and_grad(
+            self._ctx, ctypes.byref(b), ctypes.c_void_p(UT.data_ptr()), UT.shape[0], tp,
+            ctypes.c_void_p(F.data_ptr()),
+            ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
+            _stream(stream)), self._ctx)
+        return F, grad
+
+    def sync(self, stream=None):
+        check(lib().lmag_sync(self._ctx, _stream(stream)), self._ctx)
+
+    def selection_histogram(self):
+        h = np.zeros(3 * 64, dtype=np.int64)
+        check(lib().lmag_last_selection_histogram(self._ctx, h.ctypes.data_as(_lib.c_int64_p)),
+              self._ctx)
+        return h.reshape(3, 64)
+
+    # --------------------------------------------------------- tile unit ops
+    def debug_tile_gemm(self, A, B, transA=False, precision=None):
+        precision = precision or self.precision
+        C = torch.empty_like(A)
+        check(lib().lmag_debug_tile_gemm(self._ctx, _PREC[precision], ctypes.c_void_p(A.data_ptr()),
+                                         ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                                         int(transA), _stream(None)), self._ctx)
+        return C
+
+    def debug_tile_inverse(self, A, precision=None):
+        precision = precision or self.precision
+        C = torch.empty_like(A)
+        check(lib().lmag_debug_tile_inverse(self._ctx, _PREC[precision], ctypes.c_void_p(A.data_ptr()),
+                                            ctypes.c_void_p(C.data_ptr()), _stream(None)), self._ctx)
+        return C
+
+    def debug_tile_expm(self, A, precision=None):
+        precision = precision or self.precision
+        C = torch.empty_like(A)
+        ms = torch.zeros(2, dtype=torch.int8, device=A.device)
+        check(lib().lmag_debug_tile_expm(self._ctx, _PREC[precision], ctypes.c_void_p(A.data_ptr()),
+                                         ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(ms.data_ptr()),
+                                         _stream(None)), self._ctx)
+        return C, ms
+
+
+def spin_chain_system(n_spins, T1=np.inf, T2=np.inf, **kw):
+    from .spin import chain_operators
+    hs, hc, lj = chain_operators(n_spins, T1, T2)
+    return System(hs, hc, lj, **kw)
+
+
+class PulseFidelity(torch.autograd.Function):
+    """F = fidelity(amps) with dF/du from the library's adjoint kernels.
+
+    forward(amps, system, n_slices, dt, U_target, opts) returns F [n_items]
+    (or [n_groups]); backward scales the fused gradient by the incoming
+    gradient of each item (group)."""
+
+    @staticmethod
+    def forward(ctx, amps, system, n_slices, dt, U_target, opts=None):
+        opts = dict(opts or {})
+        F, grad = system.fidelity_and_grad(amps.detach(), n_slices, dt, U_target,
+                                           want_grad=True, **opts)
+        n_slices = np.asarray(n_slices, dtype=np.int64).reshape(-1)
+        off = opts.get("slice_offset")
+        off = np.concatenate([[0], np.cumsum(n_slices)[:-1]]) if off is None else np.asarray(off)
+        groups = opts.get("groups")
+        # row -> output index (item, or group) for the backward scaling
+        row_of = np.full(amps.shape[0], -1, dtype=np.int64)
+        for i, (o, n) in enumerate(zip(off, n_slices)):
+            row_of[o:o + n] = i if groups is None else int(np.asarray(groups)[i])
+        ctx.save_for_backward(grad)
+        ctx.row_of = torch.as_tensor(row_of, device=amps.device)
+        return F
+
+    @staticmethod
+    def backward(ctx, gF):
+        (grad,) = ctx.saved_tensors
+        idx = ctx.row_of.clamp(min=0)
+        scale = torch.where(ctx.row_of >= 0, gF[idx].to(grad.dtype),
+                            torch.zeros((), dtype=grad.dtype, device=grad.device))
+        return grad * scale[:, None], None, None, None, None, None

@@ -1,0 +1,141 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+Small cases span several chunks with a ragged tail and are compared element by
+element; the full-size configurations compare the whole propagator and F, and
+the gradient on sampled rows."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import oracle_system, lib_system, rounded, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def to_dev(a, sysm):
+    return torch.tensor(np.asarray(a), dtype=sysm.rdtype, device="cuda").contiguous()
+
+
+def lib_fid(sysm, cfg, amps, want_grad=True, **kw):
+    F, g = sysm.fidelity_and_grad(to_dev(amps, sysm), [len(amps)], cfg["dt"], cfg["U_target"],
+                                  static_coef=np.asarray(cfg["B"])[None, :], want_grad=want_grad,
+                                  **kw)
+    return F.cpu().numpy(), (g.cpu().numpy().astype(np.float64) if g is not None else None)
+
+
+# ----------------------------------------------------------- small cases
+@pytest.mark.parametrize("prec,order,hold,chunk", [
+    ("f64", 1, "zoh", 7), ("f64", 2, "foh", 6), ("f32", 2, "foh", 7), ("f32", 1, "zoh", 0)])
+def test_small_propagator_and_fidelity(prec, order, hold, chunk):
+    cfg = synth.small_case(100 + chunk, n_slices=40, dt=2.5e-4 if order == 2 else 1e-3)
+    sysm = lib_system(cfg, prec, order, hold, chunk=chunk)
+    amps = rounded(cfg["amps"], prec)
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], order, hold))
+    U = sysm.propagate(to_dev(amps, sysm), [40], cfg["dt"],
+                       static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert rel(U, U_ref) < tol
+    F_ref, _ = oracle.fidelity(U_ref, cfg["U_target"])
+    F, _ = lib_fid(sysm, cfg, amps, want_grad=False)
+    assert abs(F[0] - F_ref) < (1e-13 if prec == "f64" else 1e-7)
+
+
+@pytest.mark.parametrize("prec,order,hold,chunk", [
+    ("f64", 2, "foh", 7), ("f64", 1, "zoh", 5), ("f32", 2, "foh", 7)])
+def test_small_gradient(prec, order, hold, chunk):
+    cfg = synth.small_case(200 + chunk, n_slices=30, dt=2.5e-4 if order == 2 else 1e-3)
+    sysm = lib_system(cfg, prec, order, hold, chunk=chunk)
+    amps = rounded(cfg["amps"], prec)
+    osys = oracle_system(cfg)
+    F_ref, g_ref = oracle.grad_adjoint(osys, amps, cfg["dt"], order, hold, cfg["U_target"])
+    F, g = lib_fid(sysm, cfg, amps)
+    assert abs(F[0] - F_ref) < (1e-12 if prec == "f64" else 1e-7)
+    assert rel(g, g_ref) < (1e-9 if prec == "f64" else 1e-4)
+
+
+def test_zoh_second_order_equals_first_order():
+    cfg = synth.small_case(7, n_slices=20, dt=1e-3)
+    amps = cfg["amps"]
+    s1 = lib_system(cfg, "f64", 1, "zoh", chunk=6)
+    s2 = lib_system(cfg, "f64", 2, "zoh", chunk=6)
+    b = np.asarray(cfg["B"])[None, :]
+    U1 = s1.propagate(to_dev(amps, s1), [20], 1e-3, static_coef=b).cpu().numpy()
+    U2 = s2.propagate(to_dev(amps, s2), [20], 1e-3, static_coef=b).cpu().numpy()
+    assert rel(U2, U1) < 1e-13
+
+
+# --------------------------------------------------- closed forms on the GPU
+def test_gpu_rabi_single_spin():
+    from paper_2511_13330_amd import System
+    sx = np.array([[0, 1], [1, 0]], complex)
+    sz = np.array([[1, 0], [0, -1]], complex)
+    s = System([sz / 2], [sx / 2], [], precision="f64", magnus_order=1, hold="zoh", chunk_slices=3)
+    W, N, h = 2 * np.pi * 3.0, 10, 0.037
+    U = s.propagate(torch.full((N, 1), W, dtype=torch.float64, device="cuda"), [N], h,
+                    static_coef=[[0.0]]).cpu().numpy()[0]
+    t = N * h
+    V = np.cos(W * t / 2) * np.eye(2) - 1j * np.sin(W * t / 2) * sx
+    assert np.allclose(U, np.kron(V.conj(), V), atol=1e-12)
+
+
+def test_gpu_two_spin_swap():
+    from paper_2511_13330_amd import spin_chain_system
+    SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]], complex)
+    s = spin_chain_system(2, precision="f64", magnus_order=2, hold="foh", chunk_slices=4)
+    J, N = 2 * np.pi * 5.0, 16
+    h = np.pi / J / N
+    F, _ = s.fidelity_and_grad(torch.full((N, 1), J, dtype=torch.float64, device="cuda"), [N], h,
+                               SWAP, static_coef=[[0.0, 0.0]], want_grad=False)
+    assert abs(F.item() - 1.0) < 1e-12
+
+
+# ------------------------------------------------------ full configurations
+def test_config0_full_fp64():
+    cfg = synth.config0()
+    sysm = lib_system(cfg)
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(cfg["amps"], cfg["dt"], 1, "zoh"))
+    U = sysm.propagate(to_dev(cfg["amps"], sysm), [100], cfg["dt"],
+                       static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    assert rel(U, U_ref) < 1e-12
+    F_ref, _ = oracle.fidelity(U_ref, cfg["U_target"])
+    F, _ = lib_fid(sysm, cfg, cfg["amps"], want_grad=False)
+    assert abs(F[0] - F_ref) < 1e-12
+
+
+@pytest.fixture(scope="module")
+def config1_run():
+    cfg = synth.config1()
+    sysm = lib_system(cfg)
+    amps = rounded(cfg["amps"], "f32")
+    F, g = lib_fid(sysm, cfg, amps)
+    U = sysm.propagate(to_dev(amps, sysm), [4096], cfg["dt"],
+                       static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    return cfg, amps, F, g, U, sysm
+
+
+def test_config1_propagator_and_fidelity(config1_run):
+    cfg, amps, F, g, U, sysm = config1_run
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    assert rel(U, U_ref) <= 1e-4
+    F_ref, _ = oracle.fidelity(U_ref, cfg["U_target"])
+    assert abs(F[0] - F_ref) <= 1e-6
+    hist = sysm.selection_histogram()
+    assert hist[0, 0] == 4096     # the propagate call: m = 3, s = 0 for every slice
+
+
+def test_config1_gradient_sampled(config1_run):
+    cfg, amps, F, g, U, sysm = config1_run
+    osys = oracle_system(cfg)
+    coords = np.asarray(cfg["fd_coords"])
+    rows = sorted(set(int(c) // 2 for c in coords))
+    _, g_at = oracle.grad_adjoint_at(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"], rows)
+    ours = np.array([g[int(c) // 2, int(c) % 2] for c in coords])
+    adj = np.array([g_at[int(c) // 2][int(c) % 2] for c in coords])
+    assert rel(ours, adj) <= 1e-3
+    fd = oracle.grad_fd_cached(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"], coords, h=1e-4)
+    assert rel(ours, fd) <= 1e-3

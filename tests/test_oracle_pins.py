@@ -275,3 +275,23 @@ def test_gradient_vanishes_at_reached_target():
     F, g = oracle.grad_adjoint(sysm, cfg["amps"], 1e-3, 1, "zoh", UH)
     assert abs(F - 1) < 1e-12
     assert np.abs(g).max() < 1e-10
+
+
+def test_cached_fd_equals_plain_fd():
+    cfg = synth.small_case(17, n_slices=7)
+    sysm = System.from_cfg(cfg)
+    coords = [0, 3, 6, 9, 13]
+    a = oracle.grad_fd(sysm, cfg["amps"], cfg["dt"], 2, "foh", cfg["U_target"], coords)
+    b = oracle.grad_fd_cached(sysm, cfg["amps"], cfg["dt"], 2, "foh", cfg["U_target"], coords)
+    assert np.allclose(a, b, rtol=1e-7, atol=1e-12)
+
+
+def test_sampled_adjoint_equals_full_adjoint():
+    cfg = synth.small_case(18, n_slices=9)
+    sysm = System.from_cfg(cfg)
+    F, g = oracle.grad_adjoint(sysm, cfg["amps"], cfg["dt"], 2, "foh", cfg["U_target"])
+    F2, g2 = oracle.grad_adjoint_at(sysm, cfg["amps"], cfg["dt"], 2, "foh", cfg["U_target"],
+                                    [0, 4, 8])
+    assert F == F2
+    for k, v in g2.items():
+        assert np.array_equal(v, g[k])
