@@ -1,0 +1,212 @@
+"""Benchmark of the differentiable Lindblad-Magnus hot path on one MI355X.
+
+A step is one forward+gradient evaluation (Magnus coefficients, per-slice
+Liouvillian + Pade exponential, chunked ordered scan, fidelity, adjoint
+Frechet derivative, chain rule) of a batch of synthetic 3-spin pulses of 4096
+slices (superoperator 64 x 64, FP32, FOH second-order Magnus). Inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line: pulse evaluations per second over the whole job, the
+roofline of the dominant kernel (algorithmic MFMA flops per launch over its
+HIP-event duration on the stream it runs on) and the FP64 oracle timed on the
+host cores on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("fwd+grad pulse evals/s (3-spin, 4096 slices) & MFMA util, "
+          "|ΔF|≤1e-6 vs FP64")
+PEAK_FP32_MFMA_TFLOPS = 157.3
+N_SUPER = 64
+M_FLOPS = 8.0 * N_SUPER ** 3          # one complex 64x64x64 product, real flops
+PI_M = {3: 2, 5: 3, 7: 4}             # products to evaluate the Pade-m numerator/denominator
+
+
+def forward_flops_per_slice(m, s):
+    # Pade products + squarings + one n x n solve (4/3) + the ordered product (1)
+    return (PI_M[m] + s + 4.0 / 3.0 + 1.0) * M_FLOPS
+
+
+def backward_flops_per_slice(m, s):
+    # suffix product (1) + environment product (1) + Pade Frechet derivative
+    return (1.0 + 1.0 + 2 * PI_M[m] + 2.0 + 2 * s) * M_FLOPS
+
+
+def flops_from_hist(hist, per_slice):
+    tot = 0.0
+    for mi, m in enumerate((3, 5, 7)):
+        for s in range(hist.shape[1]):
+            if hist[mi, s]:
+                tot += hist[mi, s] * per_slice(m, s)
+    return tot
+
+
+def cpu_baseline(cfg, target_seconds=15.0):
+    """The FP64 oracle's fwd+grad on the first S slices of pulse 0, scaled to
+    one 4096-slice evaluation."""
+    import oracle
+    from threadpoolctl import threadpool_info
+    osys = oracle.System.from_cfg(cfg)
+    amps = cfg["amps"].astype(np.float32).astype(np.float64)
+    # calibrate on 32 slices, then run a sample of ~target_seconds
+    t0 = time.perf_counter()
+    oracle.grad_adjoint(osys, amps[:32], cfg["dt"], 2, "foh", cfg["U_target"])
+    per = (time.perf_counter() - t0) / 32
+    S = int(min(4096, max(32, target_seconds / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.grad_adjoint(osys, amps[:S], cfg["dt"], 2, "foh", cfg["U_target"])
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": 1.0 / (dt * 4096.0 / S), "unit": "pulse evals/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"FP64 oracle fwd+grad (Taylor expm, block-triangular Frechet) on the "
+                      f"first {S} of 4096 slices of pulse 0, {dt:.1f} s, scaled by 4096/{S}",
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        import hashlib
+        with open(path) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for src in rec.get("sources", []):
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec.get("source_sha256"):
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64, help="pulses per step")
+    ap.add_argument("--chunk", type=int, default=0, help="slices per work unit (0 = auto)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2511_13330_amd import spin_chain_system
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(3)
+    dev = torch.device("cuda", 0)
+    B = args.batch
+    cfg = synth.config1_batch(B)
+    sysm = spin_chain_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2,
+                             hold="foh", chunk_slices=args.chunk)
+    amps = torch.tensor(cfg["amps_batch"].reshape(B * 4096, 2), dtype=torch.float32,
+                        device=dev).contiguous()
+    n_slices = np.full(B, 4096, dtype=np.int32)
+    static = np.tile(np.asarray(cfg["B"])[None, :], (B, 1))
+    UT = cfg["U_target"]
+
+    def step(a=amps, ns=n_slices, st=static):
+        return sysm.fidelity_and_grad(a, ns, cfg["dt"], UT, static_coef=st)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sysm.read_profile()                      # drop warm-up records
+    sysm.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F, g = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sysm.set_profiling(False)
+    prof = sysm.read_profile()
+    plan = sysm.last_plan()
+    hist = sysm.selection_histogram()
+    F0 = float(F[0].item())
+
+    value = B * args.steps / elapsed
+    fwd_flops = flops_from_hist(hist, forward_flops_per_slice)
+    bwd_flops = flops_from_hist(hist, backward_flops_per_slice)
+    stage_ms = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
+    kernels = {
+        "k_backward": (bwd_flops, stage_ms["backward"]),
+        "k_forward": (fwd_flops, stage_ms["forward"]),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][1])
+    fl, ms = kernels[dom]
+    achieved = fl / (ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+                "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": read_traffic(dom),
+                "flops_per_launch": fl, "ms_per_launch": ms}
+    other = [k for k in kernels if k != dom][0]
+    fl2, ms2 = kernels[other]
+    total_flops = fwd_flops + bwd_flops
+    out = {
+        "metric": METRIC, "value": value, "unit": "pulse evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded PCG64: U[0, 2pi*20] rad/us amplitudes, U[-2pi*10, 2pi*10] "
+                "fields, Haar target)",
+        "config": {"workload": "3 spins (d=8, superoperator 64x64), 4096 slices of 0.25 ns, "
+                               "FOH second-order Magnus, FP32 forward+adjoint gradient, "
+                               f"batch of {B} pulses per step",
+                   "batch_pulses": B, "n_slices": 4096, "superop_dim": 64,
+                   "chunk_slices": plan["chunk_slices"], "grid": plan["grid"]},
+        "roofline": roofline,
+        "whole_step_tflops": total_flops / (elapsed / args.steps) / 1e12,
+        "other_kernel": {"kernel": other, "achieved_tflops": fl2 / (ms2 * 1e-3) / 1e12,
+                         "ms_per_launch": ms2},
+        "stage_ms_per_launch": stage_ms,
+        "F_pulse0": F0,
+    }
+    if not args.no_latency:
+        a1 = amps[:4096].contiguous()
+        for _ in range(max(1, args.warmup)):
+            step(a1, n_slices[:1], static[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(a1, n_slices[:1], static[:1])
+        torch.cuda.synchronize()
+        out["latency_ms_single_pulse"] = 1e3 * (time.perf_counter() - t0) / args.steps
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

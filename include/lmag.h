@@ -149,6 +149,21 @@ lmag_status lmag_pade_theta(int precision, int m, double *theta_out);
  * stream of the last call). */
 lmag_status lmag_last_selection_histogram(lmag_ctx *ctx, int64_t *counts_out /*[3*64]*/);
 
+/* Per-stage kernel timers measured with HIP events recorded on the caller's
+ * stream around every launch (the stream the kernels run on). Stages:
+ * 0 Magnus coefficients, 1 forward slices (Omega, norm, Pade, chunk product),
+ * 2 chunk scan, 3 environments + fidelity, 4 backward slices (adjoint),
+ * 5 chain rule. enable = 0 turns recording off (default). */
+enum { LMAG_STAGES = 6 };
+lmag_status lmag_set_profiling(lmag_ctx *ctx, int enable);
+/* Sum of stage durations (ms) and launch counts since the previous read; blocks
+ * until the recorded work has finished, then clears the record. */
+lmag_status lmag_read_profile(lmag_ctx *ctx, double *ms_out /*[LMAG_STAGES]*/,
+                              int64_t *count_out /*[LMAG_STAGES]*/);
+/* Plan of the last compute call: total slices, total chunks, slices per chunk,
+ * workgroups of the persistent slice kernels, workspace bytes in use. */
+lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[5]*/);
+
 /* Unit-test kernels on single 64 x 64 complex tiles of the given precision,
  * DEVICE pointers, row-major. C = op(A) B (op = transpose when transA != 0);
  * C = A^{-1} (no pivoting; A must be column diagonally dominant);

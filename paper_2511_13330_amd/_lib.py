@@ -60,6 +60,9 @@ SIGNATURES = {
     "lmag_pade_coefficients": (c_int, [c_int, c_double_p]),
     "lmag_pade_theta": (c_int, [c_int, c_int, c_double_p]),
     "lmag_last_selection_histogram": (c_int, [c_void_p, c_int64_p]),
+    "lmag_set_profiling": (c_int, [c_void_p, c_int]),
+    "lmag_read_profile": (c_int, [c_void_p, c_double_p, c_int64_p]),
+    "lmag_last_plan": (c_int, [c_void_p, c_int64_p]),
     "lmag_debug_tile_gemm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                      c_void_p]),
     "lmag_debug_tile_inverse": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),

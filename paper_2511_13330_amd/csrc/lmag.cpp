@@ -75,6 +75,18 @@ struct lmag_ctx {
   int last_total_slices = 0;
   void* dbg_scratch = nullptr;
   PadeTable pade{};
+  // stage timers
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  int64_t plan_info[5] = {0, 0, 0, 0, 0};
+
+  hipEvent_t ev_get() {
+    if (!ev_pool.empty()) { hipEvent_t e = ev_pool.back(); ev_pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+    return e;
+  }
 
   lmag_status fail(lmag_status c, const std::string& m) {
     err = m;
@@ -285,6 +297,24 @@ lmag_status upload_plan(lmag_ctx* c, const Plan& p, const Layout& L, hipStream_t
 // The common pipeline: alpha, forward slices, chunk scans, (environments,
 // fidelity, backward slices, chain rule). Returns the index (0/1) of the final
 // prefix buffer through *pre_final.
+struct StageTimer {
+  lmag_ctx* c;
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(lmag_ctx* c_, int st, hipStream_t s_) : c(c_), stage(st), s(s_) {
+    if (!c->prof) return;
+    a = c->ev_get();
+    b = c->ev_get();
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    if (!c->prof || !a || !b) return;
+    (void)hipEventRecord(b, s);
+    c->ev_pending.push_back({stage, {a, b}});
+  }
+};
+
 lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L, bool grad,
                 bool fidelity, const void* U_target, int n_targets, double* F_out, void* grad_out,
                 void* S_out, hipStream_t s, int grid) {
@@ -301,7 +331,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   aa.hold_foh = c->hold == LMAG_FOH; aa.nb = c->nb; aa.dt = b->dt;
   aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(L.alpha);
   aa.n_slices_total = p.total_slices;
-  HIPCHK(launch_alpha(aa, s), "alpha");
+  { StageTimer t(c, 0, s); HIPCHK(launch_alpha(aa, s), "alpha"); }
   HIPCHK(launch_fill_int((int*)at(L.counters), 0, 64, s), "fill");
 
   SliceArgs sa{};
@@ -313,7 +343,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   sa.totals = at(L.totals); sa.env = grad ? at(L.env) : nullptr;
   sa.gtrace = grad ? (double*)at(L.gtrace) : nullptr; sa.ms = (int8_t*)at(L.ms);
   sa.gscratch = c->prec == 64 ? at(L.gscratch) : nullptr; sa.pade = c->pade;
-  HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward");
+  { StageTimer t(c, 1, s); HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward"); }
   c->last_ms = (int8_t*)at(L.ms);
   c->last_total_slices = p.total_slices;
 
@@ -328,7 +358,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     sc.n_chunks_total = p.total_chunks; sc.step = st;
     sc.pre_in = pre_cur; sc.pre_out = at(L.pre[buf]);
     sc.suf_in = want_suf ? suf_cur : nullptr; sc.suf_out = want_suf ? at(L.suf[buf]) : nullptr;
-    HIPCHK(launch_scan_level(sc, (const int32_t*)at(L.chunk_item), s), "scan");
+    { StageTimer t(c, 2, s); HIPCHK(launch_scan_level(sc, (const int32_t*)at(L.chunk_item), s), "scan"); }
     pre_cur = at(L.pre[buf]);
     if (want_suf) suf_cur = at(L.suf[buf]);
     buf ^= 1;
@@ -356,12 +386,12 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   ev.chunk_item = (const int32_t*)at(L.chunk_item); ev.n_chunks_total = p.total_chunks;
   ev.pre = pre_cur; ev.suf = suf_cur; ev.st = st_tiles; ev.st64 = (const double*)at(L.st64);
   ev.env = grad ? at(L.env) : nullptr; ev.F = F_items; ev.Fim = nullptr; ev.d = c->d;
-  HIPCHK(launch_env(ev, s), "env");
+  { StageTimer t(c, 3, s); HIPCHK(launch_env(ev, s), "env"); }
 
   if (grad) {
     HIPCHK(launch_fill_int((int*)at(L.counters) + 16, 0, 16, s), "fill");
     sa.counter = (int*)at(L.counters) + 16;
-    HIPCHK(launch_slice_backward(c->prec, sa, grid, s), "backward");
+    { StageTimer t(c, 4, s); HIPCHK(launch_slice_backward(c->prec, sa, grid, s), "backward"); }
   }
   if (grad || grouped) {
     GradArgs ga{};
@@ -378,7 +408,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
       // group means of F only: reuse the grad kernel with a null gradient
       ga.gtrace = nullptr;
     }
-    HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad");
+    { StageTimer t(c, 5, s); HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad"); }
   }
   return LMAG_OK;
 }
@@ -389,6 +419,11 @@ lmag_status prepare(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   if (st != LMAG_OK) return st;
   grid = std::max(1, std::min(p.total_chunks, c->n_cu));
   L = layout(c, p, fidelity ? n_targets : 0, grad, grid);
+  c->plan_info[0] = p.total_slices;
+  c->plan_info[1] = p.total_chunks;
+  c->plan_info[2] = p.chunks.empty() ? 0 : p.chunks[0].count;
+  c->plan_info[3] = grid;
+  c->plan_info[4] = (int64_t)L.total;
   st = ensure_ws(c, L.total);
   if (st != LMAG_OK) return st;
   return upload_plan(c, p, L, s);
@@ -439,6 +474,8 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  for (auto& pe : c->ev_pending) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -635,6 +672,41 @@ lmag_status lmag_last_selection_histogram(lmag_ctx* c, int64_t* counts) {
     const int mi = m == 3 ? 0 : (m == 5 ? 1 : (m == 7 ? 2 : -1));
     if (mi >= 0 && s >= 0 && s < 64) counts[mi * 64 + s]++;
   }
+  return LMAG_OK;
+}
+
+lmag_status lmag_set_profiling(lmag_ctx* c, int enable) {
+  if (!c) return LMAG_E_INVALID;
+  c->prof = enable != 0;
+  return LMAG_OK;
+}
+
+lmag_status lmag_read_profile(lmag_ctx* c, double* ms, int64_t* cnt) {
+  if (!c) return LMAG_E_INVALID;
+  if (!ms || !cnt) return c->fail(LMAG_E_INVALID, "NULL output");
+  DeviceGuard g(c->device);
+  for (int i = 0; i < LMAG_STAGES; ++i) { ms[i] = 0.0; cnt[i] = 0; }
+  lmag_status st = LMAG_OK;
+  for (auto& pe : c->ev_pending) {
+    hipEvent_t a = pe.second.first, b = pe.second.second;
+    if (st == LMAG_OK) {
+      hipError_t e = hipEventSynchronize(b);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+      if (e != hipSuccess) st = c->hip_fail(e, "hipEventElapsedTime");
+      else if (pe.first >= 0 && pe.first < LMAG_STAGES) { ms[pe.first] += t; cnt[pe.first] += 1; }
+    }
+    c->ev_pool.push_back(a);
+    c->ev_pool.push_back(b);
+  }
+  c->ev_pending.clear();
+  return st;
+}
+
+lmag_status lmag_last_plan(lmag_ctx* c, int64_t* out) {
+  if (!c) return LMAG_E_INVALID;
+  if (!out) return c->fail(LMAG_E_INVALID, "NULL output");
+  for (int i = 0; i < 5; ++i) out[i] = c->plan_info[i];
   return LMAG_OK;
 }
 

@@ -142,6 +142,25 @@ class System:
               self._ctx)
         return h.reshape(3, 64)
 
+    STAGES = ("alpha", "forward", "scan", "env", "backward", "grad")
+
+    def set_profiling(self, enable=True):
+        check(lib().lmag_set_profiling(self._ctx, int(bool(enable))), self._ctx)
+
+    def read_profile(self):
+        """{stage: (total ms, launches)} since the previous read (blocks)."""
+        ms = np.zeros(6)
+        cnt = np.zeros(6, dtype=np.int64)
+        check(lib().lmag_read_profile(self._ctx, ms.ctypes.data_as(_lib.c_double_p),
+                                      cnt.ctypes.data_as(_lib.c_int64_p)), self._ctx)
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.STAGES)}
+
+    def last_plan(self):
+        out = np.zeros(5, dtype=np.int64)
+        check(lib().lmag_last_plan(self._ctx, out.ctypes.data_as(_lib.c_int64_p)), self._ctx)
+        return dict(zip(("total_slices", "total_chunks", "chunk_slices", "grid",
+                         "workspace_bytes"), (int(x) for x in out)))
+
     # --------------------------------------------------------- tile unit ops
     def debug_tile_gemm(self, A, B, transA=False, precision=None):
         precision = precision or self.precision

@@ -6,10 +6,10 @@ coordinates. It holds none of the method's arithmetic (no operators, no
 Liouvillian, no exponentials, no products, no fidelity); each side builds those
 itself from the scalars returned here.
 """
-from .configs import (A_MAX, B_RANGE, T1_US, T2_US, haar_unitary, config0,
+from .configs import (A_MAX, B_RANGE, T1_US, T2_US, haar_unitary, config0, config1_batch,
                       config1, config2, config3_four, config3_six, config4_targets,
                       small_case)
 
-__all__ = ["A_MAX", "B_RANGE", "T1_US", "T2_US", "haar_unitary", "config0",
+__all__ = ["A_MAX", "B_RANGE", "T1_US", "T2_US", "haar_unitary", "config0", "config1_batch",
            "config1", "config2", "config3_four", "config3_six",
            "config4_targets", "small_case"]

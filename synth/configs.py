@@ -120,3 +120,13 @@ def small_case(seed, n_spins=3, n_slices=40, dt=2.5e-4, order=2, hold="foh",
     cfg["amps"] = rng.uniform(0.0, amp_max, (n_slices, n_spins - 1))
     cfg["U_target"] = haar_unitary(rng, 2 ** n_spins)
     return cfg
+
+
+def config1_batch(n_pulses, seed=1):
+    """n_pulses config-1 pulses sharing fields and target: pulse 0 is exactly
+    config1(seed)'s pulse, the others are fresh draws of the same distribution."""
+    cfg = config1(seed)
+    rng = np.random.default_rng(seed + 7919)
+    extra = rng.uniform(0.0, A_MAX, (max(0, n_pulses - 1), 4096, 2))
+    cfg["amps_batch"] = np.concatenate([cfg["amps"][None], extra], axis=0)[:n_pulses]
+    return cfg
