@@ -151,10 +151,11 @@ lmag_status lmag_last_selection_histogram(lmag_ctx *ctx, int64_t *counts_out /*[
 
 /* Per-stage kernel timers measured with HIP events recorded on the caller's
  * stream around every launch (the stream the kernels run on). Stages:
- * 0 Magnus coefficients, 1 forward slices (Omega, norm, Pade, chunk product),
- * 2 chunk scan, 3 environments + fidelity, 4 backward slices (adjoint),
- * 5 chain rule. enable = 0 turns recording off (default). */
-enum { LMAG_STAGES = 6 };
+ * 0 Magnus coefficients, 1 slice exponents (Omega, FP64 norm, scaling),
+ * 2 forward slices (Pade, chunk product), 3 chunk scan, 4 environments +
+ * fidelity, 5 backward slices (adjoint), 6 basis traces, 7 chain rule.
+ * enable = 0 turns recording off (default). */
+enum { LMAG_STAGES = 8 };
 lmag_status lmag_set_profiling(lmag_ctx *ctx, int enable);
 /* Sum of stage durations (ms) and launch counts since the previous read; blocks
  * until the recorded work has finished, then clears the record. */
@@ -163,6 +164,12 @@ lmag_status lmag_read_profile(lmag_ctx *ctx, double *ms_out /*[LMAG_STAGES]*/,
 /* Plan of the last compute call: total slices, total chunks, slices per chunk,
  * workgroups of the persistent slice kernels, workspace bytes in use. */
 lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[5]*/);
+
+/* Instrumentation: per-phase shader-clock cycles of workgroup 0 of the slice
+ * kernels, summed over the calls made while enabled. enable = 1 clears and
+ * starts recording, 0 stops, -1 leaves the state; out (if not NULL) receives
+ * 32 counters (0-6 forward phases, 16-25 backward phases). Blocks. */
+lmag_status lmag_debug_phase_cycles(lmag_ctx *ctx, int enable, int64_t *out /*[32]*/);
 
 /* Unit-test kernels on single 64 x 64 complex tiles of the given precision,
  * DEVICE pointers, row-major. C = op(A) B (op = transpose when transA != 0);

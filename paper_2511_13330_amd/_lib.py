@@ -63,6 +63,7 @@ SIGNATURES = {
     "lmag_set_profiling": (c_int, [c_void_p, c_int]),
     "lmag_read_profile": (c_int, [c_void_p, c_double_p, c_int64_p]),
     "lmag_last_plan": (c_int, [c_void_p, c_int64_p]),
+    "lmag_debug_phase_cycles": (c_int, [c_void_p, c_int, c_int64_p]),
     "lmag_debug_tile_gemm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                      c_void_p]),
     "lmag_debug_tile_inverse": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),

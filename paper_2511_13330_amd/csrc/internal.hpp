@@ -46,13 +46,18 @@ struct SliceArgs {
   const void* env;          // [n_chunks][64][64] chunk environments W_c (backward input)
   double* gtrace;           // [n_slices_total][nb] Re Tr(K_n B_j) (backward output)
   int8_t* ms;               // [n_slices_total][2] Pade degree and scaling exponent
+  int8_t* nlev;             // [n_slices_total] Neumann levels of the inverse (0 = Gauss-Jordan)
   void* gscratch;           // per-workgroup global scratch slots (double precision)
+  void* omega;              // [n_slices_total][64][64]: Omega_n / 2^s, then K_n^T (backward)
+  long long* clk;           // [32] per-phase cycle counters of workgroup 0, or null
   PadeTable pade;
 };
 
 // launchers (kernel files)
 hipError_t launch_slice_forward(int prec, const SliceArgs& a, int grid, hipStream_t s);
 hipError_t launch_slice_backward(int prec, const SliceArgs& a, int grid, hipStream_t s);
+hipError_t launch_omega(int prec, const SliceArgs& a, int n_total, hipStream_t s);
+hipError_t launch_traces(int prec, const SliceArgs& a, int n_total, hipStream_t s);
 
 // system set-up (double precision, padded to 64x64 tiles)
 hipError_t launch_lift(const double* H, int d, double* out, hipStream_t s);

@@ -1,13 +1,15 @@
 // Per-slice kernels of the Lindblad-Magnus path on 64x64 superoperator tiles.
 //
-// Forward (one workgroup per chunk of consecutive slices, persistent grid):
+// Exponents (one workgroup per block of slices, bandwidth-parallel):
 //   Omega_n = sum_j alpha_{n,j} B_j                (Eq. 8 lift, Eq. 13 + GL2 term)
-//   ||Omega_n||_1 in FP64 -> Pade degree m, scaling exponent s
-//   S_n = r_m(Omega_n / 2^s)^(2^s), r_m = q_m^{-1} p_m   (Eq. 14)
+//   ||Omega_n||_1 in FP64 -> Pade degree m, scaling exponent s; A_n = Omega_n / 2^s
+// Forward (one workgroup per chunk of consecutive slices, persistent grid):
+//   S_n = r_m(A_n)^(2^s), r_m = q_m^{-1} p_m         (Eq. 14)
 //   P <- S_n P  (chunk-local ordered product, later slices on the left, Eq. 15)
 // Backward (same chunks, slices in reverse order), per slice n:
 //   M_n^T = Z_n^T P_loc,n^T,  K_n^T = L(Omega_n^T, M_n^T) (Pade Frechet derivative),
-//   g_{n,j} = Re Tr(K_n B_j),  Z_{n-1}^T = S_n^T Z_n^T.
+//   Z_{n-1}^T = S_n^T Z_n^T;  K_n^T replaces A_n in memory.
+// Traces (bandwidth-parallel): g_{n,j} = Re Tr(K_n B_j).
 // The backward works with transposed tiles so that every product keeps its
 // running factor in registers as the B operand (see tile.hpp).
 #include "tile.hpp"
@@ -22,6 +24,7 @@ template <> struct Cfg<double> { static constexpr int NLDS = 2; };
 constexpr int SLOT = 64 * PITCH;
 constexpr int TILE = 64 * 64;
 constexpr int MAXNB = 32;
+constexpr int NPHASE = 16;
 
 // theta_m (Higham 2005): largest ||A||_1 with backward error of r_m below the
 // unit roundoff. Single precision uses m = 3 only; double uses m in {3, 5, 7}.
@@ -35,6 +38,7 @@ template <typename T> struct Shared {
   cpx<T> slots[Cfg<T>::NLDS * SLOT];
   cpx<T> colbuf[128];
   double red[4 * MAXNB];
+  long long clk[NPHASE];
   int sidx;
 };
 
@@ -79,19 +83,6 @@ __device__ __forceinline__ void choose_ms(double nrm, int& m, int& s) {
   if (s > 62) s = 62;
 }
 
-template <typename T, bool TRANS>
-__device__ __forceinline__ void build_omega(RT<T>& X, const cpx<T>* __restrict__ basis, int nb,
-                                            const double* __restrict__ alpha) {
-  rt_zero(X);
-  for (int j = 0; j < nb; ++j) {
-    const double aj = alpha[j];
-    if (aj == 0.0) continue;
-    RT<T> B;
-    rt_load<T, TRANS>(B, basis + (size_t)j * TILE, 64);
-    rt_axpy(X, (T)aj, B);
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ const double* pade_b(const PadeTable& pt, int m) {
   return m == 3 ? pt.b3 : (m == 5 ? pt.b5 : pt.b7);
@@ -101,18 +92,166 @@ template <typename T> __device__ __forceinline__ cpx<T>* tile_at(void* base, siz
   return reinterpret_cast<cpx<T>*>(base) + idx * TILE;
 }
 
-// One slice forward; returns S_n in R. A_out-side stores go to the workspace
-// when ws != null.
+// Per-phase cycle counters of workgroup 0 (instrumentation; off when clk is null).
+// Thread 0 accumulates into LDS so that only the last timestamp lives in registers.
+struct Clock {
+  long long t = 0;
+  long long* acc;
+  bool on;
+  __device__ __forceinline__ Clock(const long long* clk, long long* lds) : acc(lds),
+      on(clk && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (on) {
+      for (int i = 0; i < NPHASE; ++i) acc[i] = 0;
+      t = clock64();
+    }
+  }
+  __device__ __forceinline__ void mark(int p) {
+    if (on) { const long long now = clock64(); acc[p] += now - t; t = now; }
+  }
+  __device__ __forceinline__ void flush(long long* clk) {
+    if (on)
+      for (int i = 0; i < NPHASE; ++i) clk[i] += acc[i];
+  }
+};
+
+// Levels K of the binary Neumann product Q^{-1} = (I+E)(I+E^2)...(I+E^{2^{K-1}}),
+// E = I - q_m(A), from the bound ||E||_1 <= e = sum_{j>=1} b_j ||A||_1^j: the
+// smallest K with e^{2^K} <= u (1 - e). 0 selects the Gauss-Jordan inverse.
 template <typename T>
-__device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n) {
-  const Lane L;
+__device__ __forceinline__ int neumann_levels(double nA, const double* b, int m) {
+  double e = 0.0, p = 1.0;
+  for (int j = 1; j <= m; ++j) { p *= nA; e += b[j] * p; }
+  const double u = sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
+  const int kmax = sizeof(T) == 4 ? 4 : 5;
+  if (!(e < 0.5)) return 0;
+  double pe = e;   // e^(2^K)
+  for (int K = 1; K <= kmax; ++K) {
+    pe *= pe;
+    if (pe <= u * (1.0 - e)) return K;
+  }
+  return 0;
+}
+
+// Omega_n / 2^s for a block of slices; FP64 column 1-norm selects (m, s).
+// Thread t owns column t % 64 and rows 16 (t / 64) .. +15 of every slice.
+constexpr int OMEGA_SLICES = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
+  __shared__ double colpart[4][64];
+  __shared__ int ms_sh[2];
+  const int tid = threadIdx.x, col = tid & 63, rb = (tid >> 6) * 16;
+  const int n0 = blockIdx.x * OMEGA_SLICES;
+  const cpx<T>* basis = (const cpx<T>*)a.basis;
+  cpx<T> acc[OMEGA_SLICES][16];
+#pragma unroll
+  for (int s = 0; s < OMEGA_SLICES; ++s)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) { acc[s][e].re = T(0); acc[s][e].im = T(0); }
+  for (int j = 0; j < a.nb; ++j) {
+    cpx<T> bj[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bj[e] = basis[(size_t)j * TILE + (rb + e) * 64 + col];
+#pragma unroll
+    for (int s = 0; s < OMEGA_SLICES; ++s) {
+      const int n = n0 + s;
+      const T al = n < n_total ? (T)a.alpha[(size_t)n * a.nb + j] : T(0);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { acc[s][e].re += al * bj[e].re; acc[s][e].im += al * bj[e].im; }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < OMEGA_SLICES; ++s) {
+    const int n = n0 + s;
+    if (n >= n_total) break;   // uniform
+    double cs = 0.0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const double x = (double)acc[s][e].re, y = (double)acc[s][e].im;
+      cs += sqrt(x * x + y * y);
+    }
+    __syncthreads();
+    colpart[tid >> 6][col] = cs;
+    __syncthreads();
+    if (tid < 64) {
+      double v = (colpart[0][tid] + colpart[1][tid]) + (colpart[2][tid] + colpart[3][tid]);
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+      if (tid == 0) {
+        int m, sc;
+        choose_ms<T>(v, m, sc);
+        ms_sh[0] = m; ms_sh[1] = sc;
+        a.ms[2 * (size_t)n] = (int8_t)m;
+        a.ms[2 * (size_t)n + 1] = (int8_t)sc;
+        if (a.nlev) a.nlev[n] = (int8_t)neumann_levels<T>(ldexp(v, -sc), pade_b<T>(a.pade, m), m);
+      }
+    }
+    __syncthreads();
+    const T f = (T)ldexp(1.0, -ms_sh[1]);
+    cpx<T>* out = tile_at<T>(a.omega, (size_t)n);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      cpx<T> v; v.re = acc[s][e].re * f; v.im = acc[s][e].im * f;
+      out[(rb + e) * 64 + col] = v;
+    }
+  }
+}
+
+// g_{n,j} = Re sum_x K^T_n[x] B_j[x] over flat positions x (K^T stored where A_n was).
+// Each thread sums its 16 positions in FP32; lanes and waves are combined in FP64.
+constexpr int TRACE_SLICES = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_traces(SliceArgs a, int n_total) {
+  __shared__ double red[4][TRACE_SLICES][MAXNB];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n0 = blockIdx.x * TRACE_SLICES;
+  const cpx<T>* basis = (const cpx<T>*)a.basis;
+  cpx<T> k[TRACE_SLICES][16];
+#pragma unroll
+  for (int s = 0; s < TRACE_SLICES; ++s) {
+    const int n = n0 + s < n_total ? n0 + s : n_total - 1;
+    const cpx<T>* Kt = tile_at<T>(a.omega, (size_t)n);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) k[s][e] = Kt[tid * 16 + e];
+  }
+  for (int j = 0; j < a.nb; ++j) {
+    cpx<T> bj[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bj[e] = basis[(size_t)j * TILE + tid * 16 + e];
+    double acc[TRACE_SLICES];
+#pragma unroll
+    for (int s = 0; s < TRACE_SLICES; ++s) {
+      T t = T(0);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) t += k[s][e].re * bj[e].re - k[s][e].im * bj[e].im;
+      acc[s] = (double)t;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+      for (int s = 0; s < TRACE_SLICES; ++s) acc[s] += __shfl_xor(acc[s], off);
+    if (lane == 0)
+#pragma unroll
+      for (int s = 0; s < TRACE_SLICES; ++s) red[w][s][j] = acc[s];
+  }
+  __syncthreads();
+  for (int i = tid; i < TRACE_SLICES * a.nb; i += WG) {
+    const int s = i / a.nb, j = i % a.nb, n = n0 + s;
+    if (n < n_total)
+      a.gtrace[(size_t)n * a.nb + j] = (red[0][s][j] + red[1][s][j]) + (red[2][s][j] + red[3][s][j]);
+  }
+}
+
+// One slice forward; returns S_n in R. Stores go to the workspace when requested.
+template <typename T>
+__device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
+                          Clock& ck) {
   RT<T> A;
-  build_omega<T, false>(A, (const cpx<T>*)a.basis, a.nb, a.alpha + (size_t)n * a.nb);
-  const double nrm = rt_norm1(A, sh.red);
-  int m, s;
-  choose_ms<T>(nrm, m, s);
-  if (s) rt_scale(A, (T)ldexp(1.0, -s));
+  rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)n), 64);
+  const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
   const double* b = pade_b<T>(a.pade, m);
+  ck.mark(0);
   const bool st = a.store && a.ws_tiles;
   cpx<T>* ws = st ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
 
@@ -122,11 +261,12 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   RT<T> A2;
   rt_zero(A2);
   mm(A2, slot<T, 0>(sh, gs), A);
+  ck.mark(1);
   if (st) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
   RT<T> W, V;
   rt_poly1(W, A2, (T)b[3], (T)b[1]);
   rt_poly1(V, A2, (T)b[2], (T)b[0]);
-  if (m >= 5) {
+  if (sizeof(T) == 8 && m >= 5) {   // single precision uses m = 3 only
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
     RT<T> A4;
@@ -152,13 +292,43 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     V.re[q] = vr - U.re[q]; V.im[q] = vi - U.im[q];
     U.re[q] = vr + U.re[q]; U.im[q] = vi + U.im[q];
   }
-  rt_gj_inverse(V, sh.colbuf);
+  ck.mark(2);
+  const int K = a.nlev ? a.nlev[n] : 0;
+  if (K > 0) {
+    // binary Neumann product on MFMA: X = (I + E)(I + E^2)...; E = I - Q
+    RT<T> F;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { F.re[q] = -V.re[q]; F.im[q] = -V.im[q]; }
+    rt_add_diag(F, T(1));
+    rt_copy(V, F);
+    rt_add_diag(V, T(1));
+    for (int k = 1; k < K; ++k) {
+      __syncthreads();
+      put<T, false>(F, slot<T, 2>(sh, gs));
+      __syncthreads();
+      RT<T> F2;
+      rt_zero(F2);
+      mm(F2, slot<T, 2>(sh, gs), F);
+      __syncthreads();
+      put<T, false>(F2, slot<T, 2>(sh, gs));
+      __syncthreads();
+      RT<T> T1;
+      rt_zero(T1);
+      mm(T1, slot<T, 2>(sh, gs), V);
+      rt_axpy(V, T(1), T1);
+      rt_copy(F, F2);
+    }
+  } else {
+    rt_gj_inverse(V, sh.colbuf);
+  }
+  ck.mark(3);
   if (st) rt_store<T, false>(V, ws + WS_QINV * TILE, 64);
   put<T, false>(V, slot<T, 1>(sh, gs));
   __syncthreads();
   rt_zero(R);
   mm(R, slot<T, 1>(sh, gs), U);
   if (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
+  ck.mark(4);
   for (int k = 0; k < s; ++k) {
     __syncthreads();
     put<T, false>(R, slot<T, 2>(sh, gs));
@@ -168,10 +338,7 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     mm(R2, slot<T, 2>(sh, gs), R);
     rt_copy(R, R2);
   }
-  if (a.ms && L.w == 0 && L.l == 0) {
-    a.ms[2 * (size_t)n] = (int8_t)m;
-    a.ms[2 * (size_t)n + 1] = (int8_t)s;
-  }
+  ck.mark(5);
 }
 
 template <typename T>
@@ -187,6 +354,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
   __shared__ Shared<T> sh;
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
                           : nullptr;
+  Clock ck(a.clk, sh.clk);
   for (;;) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
@@ -198,7 +366,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
       if (a.store && a.ws_tiles)
         rt_store<T, false>(P, tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES + WS_PLOC), 64);
       RT<T> S;
-      fwd_slice<T>(S, sh, gs, a, n);
+      fwd_slice<T>(S, sh, gs, a, n, ck);
       __syncthreads();
       put<T, false>(S, slot<T, 3>(sh, gs));
       __syncthreads();
@@ -206,16 +374,18 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
       rt_zero(Pn);
       mm(Pn, slot<T, 3>(sh, gs), P);
       rt_copy(P, Pn);
+      ck.mark(6);
     }
     rt_store<T, false>(P, tile_at<T>(a.totals, (size_t)ch.chunk), 64);
   }
+  ck.flush(a.clk);
 }
 
 // One slice backward in the transposed frame. Z holds Z_n^T on entry and
 // Z_{n-1}^T on exit.
 template <typename T>
-__device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n) {
-  const Lane L;
+__device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
+                          Clock& ck) {
   const cpx<T>* ws = tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES);
   const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
   const double* b = pade_b<T>(a.pade, m);
@@ -233,17 +403,19 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     mm(E, slot<T, 0>(sh, gs), Pl);
   }
   if (s) rt_scale(E, sc);
+  ck.mark(1);
   RT<T> A;
-  build_omega<T, true>(A, (const cpx<T>*)a.basis, a.nb, a.alpha + (size_t)n * a.nb);
-  if (s) rt_scale(A, sc);
+  rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);   // (Omega_n / 2^s)^T
   __syncthreads();
   put<T, false>(A, slot<T, 0>(sh, gs));
   put<T, false>(E, slot<T, 1>(sh, gs));
   __syncthreads();
+  ck.mark(2);
   RT<T> L2;
   rt_zero(L2);
   mm(L2, slot<T, 0>(sh, gs), E);
   mm(L2, slot<T, 1>(sh, gs), A);
+  ck.mark(3);
   RT<T> W, LW, LV;
   {
     RT<T> A2;
@@ -251,7 +423,7 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     rt_poly1(W, A2, (T)b[3], (T)b[1]);
     rt_poly1(LW, L2, (T)b[3], T(0));
     rt_poly1(LV, L2, (T)b[2], T(0));
-    if (m >= 5) {
+    if (sizeof(T) == 8 && m >= 5) {   // single precision uses m = 3 only
       put<T, false>(A2, slot<T, 2>(sh, gs));
       put<T, false>(L2, slot<T, 3>(sh, gs));
       __syncthreads();
@@ -278,10 +450,12 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     }
   }
   // L_U = A L_W + E W
+  ck.mark(4);
   RT<T> LU;
   rt_zero(LU);
   mm(LU, slot<T, 0>(sh, gs), LW);
   mm(LU, slot<T, 1>(sh, gs), W);
+  ck.mark(5);
   // L_Q = L_V - L_U (into LW), L_P = L_V + L_U (into LU)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -299,6 +473,7 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     put<T, false>(Qi, slot<T, 2>(sh, gs));
   }
   __syncthreads();
+  ck.mark(6);
   // X = L_P - L_Q R ; L = Q^{-1} X
   {
     RT<T> Tm;
@@ -324,29 +499,10 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     rt_copy(K, Kn);
     rt_copy(R, Rn);
   }
-  // traces Re Tr(K B_j) = Re sum K^T o B_j (elementwise, same positions)
-  {
-    const cpx<T>* basis = (const cpx<T>*)a.basis;
-    for (int j = 0; j < a.nb; ++j) {
-      RT<T> B;
-      rt_load<T, false>(B, basis + (size_t)j * TILE, 64);
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc += (double)K.re[q][r] * (double)B.re[q][r] - (double)K.im[q][r] * (double)B.im[q][r];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-      if (L.l == 0) sh.red[L.w * MAXNB + j] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)a.nb) {
-      const int j = threadIdx.x;
-      a.gtrace[(size_t)n * a.nb + j] =
-          (sh.red[j] + sh.red[MAXNB + j]) + (sh.red[2 * MAXNB + j] + sh.red[3 * MAXNB + j]);
-    }
-  }
+  ck.mark(7);
+  // K_n^T replaces A_n; the traces Re Tr(K_n B_j) are taken by k_traces
+  rt_store<T, false>(K, tile_at<T>(a.omega, (size_t)n), 64);
+  ck.mark(8);
   // Z_{n-1}^T = S_n^T Z_n^T
   __syncthreads();
   put<T, false>(R, slot<T, 0>(sh, gs));
@@ -355,6 +511,7 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   rt_zero(Zn);
   mm(Zn, slot<T, 0>(sh, gs), Z);
   rt_copy(Z, Zn);
+  ck.mark(9);
 }
 
 template <typename T>
@@ -362,19 +519,38 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
   __shared__ Shared<T> sh;
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
                           : nullptr;
+  Clock ck(a.clk ? a.clk + 16 : nullptr, sh.clk);
   for (;;) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
     const Chunk ch = a.chunks[idx];
     RT<T> Z;
     rt_load<T, true>(Z, tile_at<T>((void*)a.env, (size_t)ch.chunk), 64);
-    for (int k = ch.count - 1; k >= 0; --k) bwd_slice<T>(Z, sh, gs, a, ch.first + k);
+    ck.mark(0);
+    for (int k = ch.count - 1; k >= 0; --k) bwd_slice<T>(Z, sh, gs, a, ch.first + k, ck);
   }
+  ck.flush(a.clk ? a.clk + 16 : nullptr);
 }
 
 hipError_t launch_slice_forward(int prec, const SliceArgs& a, int grid, hipStream_t s) {
   if (prec == 32) hipLaunchKernelGGL(k_forward<float>, dim3(grid), dim3(WG), 0, s, a);
   else hipLaunchKernelGGL(k_forward<double>, dim3(grid), dim3(WG), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega(int prec, const SliceArgs& a, int n_total, hipStream_t s) {
+  if (n_total <= 0) return hipSuccess;
+  const dim3 g((n_total + OMEGA_SLICES - 1) / OMEGA_SLICES);
+  if (prec == 32) hipLaunchKernelGGL(k_omega<float>, g, dim3(WG), 0, s, a, n_total);
+  else hipLaunchKernelGGL(k_omega<double>, g, dim3(WG), 0, s, a, n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_traces(int prec, const SliceArgs& a, int n_total, hipStream_t s) {
+  if (n_total <= 0) return hipSuccess;
+  const dim3 g((n_total + TRACE_SLICES - 1) / TRACE_SLICES);
+  if (prec == 32) hipLaunchKernelGGL(k_traces<float>, g, dim3(WG), 0, s, a, n_total);
+  else hipLaunchKernelGGL(k_traces<double>, g, dim3(WG), 0, s, a, n_total);
   return hipGetLastError();
 }
 
@@ -410,15 +586,14 @@ __global__ void __launch_bounds__(WG, 1) k_debug_inverse(const cpx<T>* A, cpx<T>
 }
 
 // exp of one 64x64 tile through the forward slice routine (basis = A, alpha = 1)
+// exp of one tile: k_omega (basis = A, alpha = 1, writes A / 2^s into gs and
+// (m, s)) followed by the forward slice routine.
 template <typename T>
-__global__ void __launch_bounds__(WG, 1) k_debug_expm(const cpx<T>* A, cpx<T>* C, int8_t* ms,
-                                                      const double* one, cpx<T>* gs, PadeTable pt) {
+__global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, SliceArgs a) {
   __shared__ Shared<T> sh;
-  SliceArgs a{};
-  a.basis = A; a.nb = 1; a.alpha = one; a.ms = ms; a.pade = pt;
-  a.store = 0; a.ws_tiles = nullptr;
+  Clock ck(nullptr, sh.clk);
   RT<T> R;
-  fwd_slice<T>(R, sh, gs, a, 0);
+  fwd_slice<T>(R, sh, gs + 2 * SLOT, a, 0, ck);
   rt_store<T, false>(R, C, 64);
 }
 
@@ -444,16 +619,24 @@ hipError_t launch_debug_inverse(int prec, const void* A, void* C, hipStream_t s)
 
 __device__ double g_one_alpha[1] = {1.0};
 
+// gscratch holds 4 slots of 16-byte elements: [0, SLOT) the scaled tile, [2 SLOT, 4 SLOT)
+// the double-precision scratch slots.
 hipError_t launch_debug_expm(int prec, const void* A, void* C, int8_t* ms, void* gscratch, PadeTable pt, hipStream_t s) {
   double* one = nullptr;
   hipError_t e = hipGetSymbolAddress((void**)&one, HIP_SYMBOL(g_one_alpha));
   if (e != hipSuccess) return e;
+  SliceArgs a{};
+  a.basis = A; a.nb = 1; a.alpha = one; a.ms = ms; a.pade = pt; a.omega = gscratch;
+  a.nlev = (int8_t*)gscratch + 65536;   // past the 64x64 tile, inside slot 0
+  a.store = 0; a.ws_tiles = nullptr;
+  e = launch_omega(prec, a, 1, s);
+  if (e != hipSuccess) return e;
   if (prec == 32)
-    hipLaunchKernelGGL(k_debug_expm<float>, dim3(1), dim3(WG), 0, s, (const cpx<float>*)A,
-                       (cpx<float>*)C, ms, (const double*)one, (cpx<float>*)gscratch, pt);
+    hipLaunchKernelGGL(k_debug_expm2<float>, dim3(1), dim3(WG), 0, s, (cpx<float>*)C,
+                       (cpx<float>*)gscratch, a);
   else
-    hipLaunchKernelGGL(k_debug_expm<double>, dim3(1), dim3(WG), 0, s, (const cpx<double>*)A,
-                       (cpx<double>*)C, ms, (const double*)one, (cpx<double>*)gscratch, pt);
+    hipLaunchKernelGGL(k_debug_expm2<double>, dim3(1), dim3(WG), 0, s, (cpx<double>*)C,
+                       (cpx<double>*)gscratch, a);
   return hipGetLastError();
 }
 

@@ -80,6 +80,8 @@ struct lmag_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   int64_t plan_info[5] = {0, 0, 0, 0, 0};
+  bool clk_on = false;
+  long long* clk_dev = nullptr;
 
   hipEvent_t ev_get() {
     if (!ev_pool.empty()) { hipEvent_t e = ev_pool.back(); ev_pool.pop_back(); return e; }
@@ -111,8 +113,8 @@ struct Plan {
 
 struct Layout {
   size_t items, chunks, chunk_item, slice_item, amp_off, group_first, group_items, meta_end;
-  size_t counters, alpha, gtrace, ms, F_items, st64, st, totals, pre[2], suf[2], env, gscratch,
-      tiles, total;
+  size_t counters, alpha, gtrace, ms, nlev, F_items, st64, st, totals, pre[2], suf[2], env, gscratch,
+      omega, tiles, total;
 };
 
 lmag_status plan_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
@@ -211,6 +213,7 @@ Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int gr
   L.alpha = take((size_t)p.total_slices * c->nb * 8);
   L.gtrace = grad ? take((size_t)p.total_slices * c->nb * 8) : 0;
   L.ms = take((size_t)p.total_slices * 2);
+  L.nlev = take((size_t)p.total_slices);
   L.F_items = take(p.items.size() * 8);
   L.st64 = take((size_t)std::max(1, n_targets) * TILE * 16);
   L.st = take((size_t)std::max(1, n_targets) * tile);
@@ -221,6 +224,7 @@ Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int gr
   L.suf[1] = grad ? take((size_t)p.total_chunks * tile) : 0;
   L.env = grad ? take((size_t)p.total_chunks * tile) : 0;
   L.gscratch = c->prec == 64 ? take((size_t)grid * 2 * SLOT * es) : 0;
+  L.omega = take((size_t)p.total_slices * tile);
   L.tiles = grad ? take((size_t)p.total_slices * WS_TILES * tile) : 0;
   L.total = o;
   return L;
@@ -342,8 +346,11 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   sa.ws_tiles = grad ? at(L.tiles) : nullptr; sa.store = grad ? 1 : 0;
   sa.totals = at(L.totals); sa.env = grad ? at(L.env) : nullptr;
   sa.gtrace = grad ? (double*)at(L.gtrace) : nullptr; sa.ms = (int8_t*)at(L.ms);
+  sa.nlev = (int8_t*)at(L.nlev);
   sa.gscratch = c->prec == 64 ? at(L.gscratch) : nullptr; sa.pade = c->pade;
-  { StageTimer t(c, 1, s); HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward"); }
+  sa.omega = at(L.omega); sa.clk = c->clk_on ? c->clk_dev : nullptr;
+  { StageTimer t(c, 1, s); HIPCHK(launch_omega(c->prec, sa, p.total_slices, s), "omega"); }
+  { StageTimer t(c, 2, s); HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward"); }
   c->last_ms = (int8_t*)at(L.ms);
   c->last_total_slices = p.total_slices;
 
@@ -358,7 +365,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     sc.n_chunks_total = p.total_chunks; sc.step = st;
     sc.pre_in = pre_cur; sc.pre_out = at(L.pre[buf]);
     sc.suf_in = want_suf ? suf_cur : nullptr; sc.suf_out = want_suf ? at(L.suf[buf]) : nullptr;
-    { StageTimer t(c, 2, s); HIPCHK(launch_scan_level(sc, (const int32_t*)at(L.chunk_item), s), "scan"); }
+    { StageTimer t(c, 3, s); HIPCHK(launch_scan_level(sc, (const int32_t*)at(L.chunk_item), s), "scan"); }
     pre_cur = at(L.pre[buf]);
     if (want_suf) suf_cur = at(L.suf[buf]);
     buf ^= 1;
@@ -386,12 +393,13 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   ev.chunk_item = (const int32_t*)at(L.chunk_item); ev.n_chunks_total = p.total_chunks;
   ev.pre = pre_cur; ev.suf = suf_cur; ev.st = st_tiles; ev.st64 = (const double*)at(L.st64);
   ev.env = grad ? at(L.env) : nullptr; ev.F = F_items; ev.Fim = nullptr; ev.d = c->d;
-  { StageTimer t(c, 3, s); HIPCHK(launch_env(ev, s), "env"); }
+  { StageTimer t(c, 4, s); HIPCHK(launch_env(ev, s), "env"); }
 
   if (grad) {
     HIPCHK(launch_fill_int((int*)at(L.counters) + 16, 0, 16, s), "fill");
     sa.counter = (int*)at(L.counters) + 16;
-    { StageTimer t(c, 4, s); HIPCHK(launch_slice_backward(c->prec, sa, grid, s), "backward"); }
+    { StageTimer t(c, 5, s); HIPCHK(launch_slice_backward(c->prec, sa, grid, s), "backward"); }
+    { StageTimer t(c, 6, s); HIPCHK(launch_traces(c->prec, sa, p.total_slices, s), "traces"); }
   }
   if (grad || grouped) {
     GradArgs ga{};
@@ -408,7 +416,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
       // group means of F only: reuse the grad kernel with a null gradient
       ga.gtrace = nullptr;
     }
-    { StageTimer t(c, 5, s); HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad"); }
+    { StageTimer t(c, 7, s); HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad"); }
   }
   return LMAG_OK;
 }
@@ -472,6 +480,7 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->basis64) (void)hipFree(c->basis64);
   if (c->basis32) (void)hipFree(c->basis32);
   if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
+  if (c->clk_dev) (void)hipFree(c->clk_dev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
   for (auto& pe : c->ev_pending) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
@@ -703,6 +712,32 @@ lmag_status lmag_read_profile(lmag_ctx* c, double* ms, int64_t* cnt) {
   return st;
 }
 
+lmag_status lmag_debug_phase_cycles(lmag_ctx* c, int enable, int64_t* out) {
+  if (!c) return LMAG_E_INVALID;
+  DeviceGuard g(c->device);
+  if (enable >= 0) {
+    if (enable && !c->clk_dev) {
+      hipError_t e = hipMalloc((void**)&c->clk_dev, 32 * sizeof(long long));
+      if (e != hipSuccess) { (void)hipGetLastError(); c->clk_dev = nullptr; return c->fail(LMAG_E_NOMEM, "clock buffer"); }
+    }
+    if (enable) {
+      HIPCHK(hipDeviceSynchronize(), "sync");
+      HIPCHK(hipMemset(c->clk_dev, 0, 32 * sizeof(long long)), "memset");
+    }
+    c->clk_on = enable != 0;
+  }
+  if (out) {
+    for (int i = 0; i < 32; ++i) out[i] = 0;
+    if (c->clk_dev) {
+      HIPCHK(hipDeviceSynchronize(), "sync");
+      long long h[32];
+      HIPCHK(hipMemcpy(h, c->clk_dev, sizeof(h), hipMemcpyDeviceToHost), "memcpy");
+      for (int i = 0; i < 32; ++i) out[i] = h[i];
+    }
+  }
+  return LMAG_OK;
+}
+
 lmag_status lmag_last_plan(lmag_ctx* c, int64_t* out) {
   if (!c) return LMAG_E_INVALID;
   if (!out) return c->fail(LMAG_E_INVALID, "NULL output");
@@ -736,7 +771,7 @@ lmag_status lmag_debug_tile_expm(lmag_ctx* c, int precision, const void* A, void
   if (precision != LMAG_F32 && precision != LMAG_F64) return c->fail(LMAG_E_INVALID, "precision");
   DeviceGuard g(c->device);
   if (!c->dbg_scratch) {
-    hipError_t e = hipMalloc(&c->dbg_scratch, (size_t)2 * SLOT * 16);
+    hipError_t e = hipMalloc(&c->dbg_scratch, (size_t)4 * SLOT * 16);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       c->dbg_scratch = nullptr;

@@ -142,18 +142,25 @@ class System:
               self._ctx)
         return h.reshape(3, 64)
 
-    STAGES = ("alpha", "forward", "scan", "env", "backward", "grad")
+    STAGES = ("alpha", "omega", "forward", "scan", "env", "backward", "traces", "grad")
 
     def set_profiling(self, enable=True):
         check(lib().lmag_set_profiling(self._ctx, int(bool(enable))), self._ctx)
 
     def read_profile(self):
         """{stage: (total ms, launches)} since the previous read (blocks)."""
-        ms = np.zeros(6)
-        cnt = np.zeros(6, dtype=np.int64)
+        ms = np.zeros(8)
+        cnt = np.zeros(8, dtype=np.int64)
         check(lib().lmag_read_profile(self._ctx, ms.ctypes.data_as(_lib.c_double_p),
                                       cnt.ctypes.data_as(_lib.c_int64_p)), self._ctx)
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.STAGES)}
+
+    def phase_cycles(self, enable=-1):
+        """Per-phase cycle counters of workgroup 0 of the slice kernels."""
+        out = np.zeros(32, dtype=np.int64)
+        check(lib().lmag_debug_phase_cycles(self._ctx, int(enable),
+                                            out.ctypes.data_as(_lib.c_int64_p)), self._ctx)
+        return out
 
     def last_plan(self):
         out = np.zeros(5, dtype=np.int64)
