@@ -137,6 +137,20 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx *ctx, const lmag_batch *batch,
 /* Wait for the stream and report any pending device error. */
 lmag_status lmag_sync(lmag_ctx *ctx, void *hip_stream);
 
+/* Optimiser step on pulse amplitudes (the paper's Adam step, Sec. III-C,
+ * Kingma & Ba 2015 Alg. 1) followed by projection onto [lo, hi]:
+ *   g <- grad_scale * grad;  m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2
+ *   amps <- clip(amps - lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps), lo, hi)
+ * amps, grad, m_state, v_state: DEVICE [rows][n_ctrl] of the compute type of
+ * `precision` (m, v zero before step 1); step >= 1. row_active: DEVICE
+ * uint8 [rows] or NULL; rows with 0 are left unchanged (state included).
+ * grad_scale = -1 ascends F (descends 1 - F). */
+lmag_status lmag_adam_project(lmag_ctx *ctx, int precision, int64_t rows, int n_ctrl,
+                              void *amps, const void *grad, void *m_state, void *v_state,
+                              int step, double lr, double beta1, double beta2, double eps,
+                              double grad_scale, double lo, double hi,
+                              const uint8_t *row_active, void *hip_stream);
+
 /* Host-only queries (no device needed). */
 /* Pade coefficients b_0..b_m of r_m = p_m / p_m(-x), m in {3, 5, 7}. */
 lmag_status lmag_pade_coefficients(int m, double *b_out);

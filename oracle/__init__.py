@@ -22,6 +22,7 @@ from .model import (pauli, spin_op, exchange_terms, zeeman_terms, jump_ops,
 from .liouville import vec, unvec, liouvillian, lift_hamiltonian
 from .magnus import gl2_nodes, slice_omegas, slice_omega
 from .expm import expm_taylor, frechet_block
+from .optim import adam_project
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
                          grad_adjoint, grad_adjoint_at, grad_fd, grad_fd_cached, rk4_propagator,
                          slice_products)

@@ -148,6 +148,15 @@ struct GradArgs {
 };
 hipError_t launch_grad(const GradArgs& a, int max_slices, hipStream_t s);
 
+struct AdamArgs {
+  int64_t n;                // number of parameters
+  int64_t row_len;          // parameters per row (row_active granularity)
+  void* theta; const void* grad; void* m; void* v;   // compute type
+  double lr, beta1, beta2, eps, bc1, bc2, grad_scale, lo, hi;
+  const uint8_t* row_active;  // [n / row_len] or null
+};
+hipError_t launch_adam_project(int prec, const AdamArgs& a, hipStream_t s);
+
 // debug / unit-test kernels (single 64x64 tiles)
 hipError_t launch_debug_gemm(int prec, const void* A, const void* B, void* C, int transA, hipStream_t s);
 hipError_t launch_debug_inverse(int prec, const void* A, void* C, hipStream_t s);

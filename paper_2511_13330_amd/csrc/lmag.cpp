@@ -632,6 +632,29 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx* c, const lmag_batch* b, const void*
   }
 }
 
+lmag_status lmag_adam_project(lmag_ctx* c, int precision, int64_t rows, int n_ctrl, void* amps,
+                              const void* grad, void* m_state, void* v_state, int step, double lr,
+                              double beta1, double beta2, double eps, double grad_scale, double lo,
+                              double hi, const uint8_t* row_active, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (precision != LMAG_F32 && precision != LMAG_F64) return c->fail(LMAG_E_INVALID, "precision");
+  if (rows < 0 || n_ctrl < 1) return c->fail(LMAG_E_INVALID, "rows < 0 or n_ctrl < 1");
+  if (rows > 0 && (!amps || !grad || !m_state || !v_state)) return c->fail(LMAG_E_INVALID, "NULL array");
+  if (step < 1) return c->fail(LMAG_E_INVALID, "step must be >= 1");
+  if (!(lr >= 0.0) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0) ||
+      !std::isfinite(grad_scale) || !(lo <= hi))
+    return c->fail(LMAG_E_INVALID, "bad hyper-parameters");
+  DeviceGuard g(c->device);
+  AdamArgs a{};
+  a.n = rows * (int64_t)n_ctrl; a.row_len = n_ctrl;
+  a.theta = amps; a.grad = grad; a.m = m_state; a.v = v_state;
+  a.lr = lr; a.beta1 = beta1; a.beta2 = beta2; a.eps = eps;
+  a.bc1 = 1.0 - std::pow(beta1, (double)step); a.bc2 = 1.0 - std::pow(beta2, (double)step);
+  a.grad_scale = grad_scale; a.lo = lo; a.hi = hi; a.row_active = row_active;
+  HIPCHK(launch_adam_project(precision, a, (hipStream_t)hip_stream), "adam");
+  return LMAG_OK;
+}
+
 lmag_status lmag_sync(lmag_ctx* c, void* hip_stream) {
   if (!c) return LMAG_E_INVALID;
   DeviceGuard g(c->device);

@@ -133,6 +133,26 @@ class System:
             _stream(stream)), self._ctx)
         return F, grad
 
+    def adam_project(self, amps, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                     grad_scale=-1.0, lo=0.0, hi=float("inf"), row_active=None, stream=None):
+        """In-place Adam + projection step of the library (lmag_adam_project)."""
+        for t in (amps, grad, m, v):
+            if not (t.is_cuda and t.dtype == self.rdtype and t.is_contiguous()
+                    and t.shape == amps.shape):
+                raise TypeError("amps/grad/m/v must be contiguous same-shape CUDA tensors")
+        ra = None
+        if row_active is not None:
+            if not (row_active.is_cuda and row_active.dtype == torch.uint8
+                    and row_active.numel() == amps.shape[0]):
+                raise TypeError("row_active must be a uint8 CUDA tensor [rows]")
+            ra = ctypes.c_void_p(row_active.data_ptr())
+        check(lib().lmag_adam_project(
+            self._ctx, _PREC[self.precision], amps.shape[0], amps.shape[1],
+            ctypes.c_void_p(amps.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+            ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(step), float(lr),
+            float(beta1), float(beta2), float(eps), float(grad_scale), float(lo), float(hi), ra,
+            _stream(stream)), self._ctx)
+
     def sync(self, stream=None):
         check(lib().lmag_sync(self._ctx, _stream(stream)), self._ctx)
 

@@ -295,3 +295,24 @@ def test_sampled_adjoint_equals_full_adjoint():
     assert F == F2
     for k, v in g2.items():
         assert np.array_equal(v, g[k])
+
+
+# ----------------------------------------------------------------- Adam pins
+def test_adam_constant_gradient_closed_form():
+    # constant g: bias-corrected mhat = g, vhat = g^2 at every step, so each
+    # step moves by lr * g / (|g| + eps)
+    g = np.array([[0.3, -2.0], [1e-3, 5.0]])
+    th = np.zeros_like(g); m = np.zeros_like(g); v = np.zeros_like(g)
+    lr, eps = 0.01, 1e-8
+    for t in range(1, 8):
+        th, m, v = oracle.adam_project(th, g, m, v, t, lr, eps=eps)
+    assert np.allclose(th, -7 * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_projection_and_mask():
+    th = np.array([[0.5, 0.5], [0.5, 0.5]])
+    g = np.array([[-1.0, 1.0], [-1.0, 1.0]])
+    out, m, v = oracle.adam_project(th, g, 0 * g, 0 * g, 1, 2.0, lo=0.0, hi=1.0,
+                                    active=[True, False])
+    assert np.array_equal(out[0], [1.0, 0.0])      # clipped both ways
+    assert np.array_equal(out[1], th[1]) and np.array_equal(m[1], [0, 0])
