@@ -175,9 +175,12 @@ lmag_status lmag_set_profiling(lmag_ctx *ctx, int enable);
  * until the recorded work has finished, then clears the record. */
 lmag_status lmag_read_profile(lmag_ctx *ctx, double *ms_out /*[LMAG_STAGES]*/,
                               int64_t *count_out /*[LMAG_STAGES]*/);
-/* Plan of the last compute call: total slices, total chunks, slices per chunk,
- * workgroups of the persistent slice kernels, workspace bytes in use. */
-lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[5]*/);
+/* Plan of the last wave of the last compute call: total slices, total chunks,
+ * slices per chunk, workgroups of the persistent slice kernels, workspace bytes
+ * in use, recompute mode (1 = the backward re-ran each chunk's forward instead of
+ * reading stored per-slice tiles), number of waves the call was split into to
+ * fit workspace_bytes_max (or 85 % of free device memory). */
+lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[7]*/);
 
 /* Instrumentation: per-phase shader-clock cycles of workgroup 0 of the slice
  * kernels, summed over the calls made while enabled. enable = 1 clears and

@@ -28,6 +28,7 @@ struct Item {
   int32_t n_slices;
   int32_t target;      // target index (fidelity calls)
   int32_t group;       // group index or -1
+  int32_t src;         // index of the item in the caller's batch
 };
 
 // Per-slice workspace tiles (row-major 64x64 complex of the compute type).
@@ -50,6 +51,9 @@ struct SliceArgs {
   void* gscratch;           // per-workgroup global scratch slots (double precision)
   void* omega;              // [n_slices_total][64][64]: Omega_n / 2^s, then K_n^T (backward)
   long long* clk;           // [32] per-phase cycle counters of workgroup 0, or null
+  int recompute;            // backward recomputes each chunk's forward tiles
+  void* rscratch;           // [grid][max_chunk][WS_TILES] tiles (recompute mode)
+  int max_chunk;            // slices per chunk (scratch stride)
   PadeTable pade;
 };
 
@@ -112,8 +116,9 @@ struct EnvArgs {
   const void* st;           // S_T^dagger tiles [n_targets][64][64] compute type
   const double* st64;       // same in double
   void* env;                // out W_c [n_chunks][64][64]
-  double* F;                // out [n_items] (Re), may be null
-  double* Fim;              // out [n_items] (Im), may be null
+  double* F;                // out (Re), may be null
+  double* Fim;              // out (Im), may be null
+  int f_by_src;             // index F / Fim by the caller's item index
   int d;
 };
 hipError_t launch_env(const EnvArgs& a, hipStream_t s);
@@ -145,6 +150,7 @@ struct GradArgs {
   int n_groups;
   double* F_items;          // [n_items] per-item fidelity (group mean input)
   double* F_out;            // [n_groups] group means (grouped calls)
+  const int32_t* group_global;      // [n_groups] caller's group index of each local group
 };
 hipError_t launch_grad(const GradArgs& a, int max_slices, hipStream_t s);
 

@@ -134,7 +134,7 @@ __device__ void node_values(const AlphaArgs& a, int it, int k, int N, double* a1
   const double l1 = 0.5 - LMAG_SQ3 / 6.0, l2 = 0.5 + LMAG_SQ3 / 6.0;
   for (int c = 0; c < a.n_ctrl; ++c) {
     const double u0 = (double)amps[c], u1 = (double)nxt[c];
-    const double eps = a.ctrl_scale ? ((const double*)a.ctrl_scale)[(size_t)it * a.n_ctrl + c] : 1.0;
+    const double eps = a.ctrl_scale ? ((const double*)a.ctrl_scale)[(size_t)a.items[it].src * a.n_ctrl + c] : 1.0;
     a1[c] = eps * (u0 + l1 * (u1 - u0));
     a2[c] = eps * (u0 + l2 * (u1 - u0));
   }
@@ -151,7 +151,7 @@ template <typename T> __global__ void k_alpha(AlphaArgs a) {
   const BasisIdx B{a.n_ctrl, a.n_static};
   double* al = a.alpha + (size_t)n * a.nb;
   const double h = a.dt, kap = LMAG_SQ3 * h * h / 12.0;
-  const double* bc = a.static_coef ? (const double*)a.static_coef + (size_t)it * a.n_static : nullptr;
+  const double* bc = a.static_coef ? (const double*)a.static_coef + (size_t)item.src * a.n_static : nullptr;
   for (int c = 0; c < a.n_ctrl; ++c) al[B.L(c)] = 0.5 * h * (a1[c] + a2[c]);
   for (int i = 0; i < a.n_static; ++i) al[B.Z(i)] = h * (bc ? bc[i] : 0.0);
   al[B.D()] = h;
@@ -279,8 +279,9 @@ template <typename T> __global__ void __launch_bounds__(WG) k_env(EnvArgs a) {
     im = wg_sum(im, sh.red);
     const double inv = 1.0 / ((double)a.d * (double)a.d);
     if (threadIdx.x == 0) {
-      if (a.F) a.F[itn] = re * inv;
-      if (a.Fim) a.Fim[itn] = im * inv;
+      const int fi = a.f_by_src ? it.src : itn;
+      if (a.F) a.F[fi] = re * inv;
+      if (a.Fim) a.Fim[fi] = im * inv;
     }
   }
   if (!a.env) return;
@@ -327,7 +328,7 @@ template <typename T> __global__ void k_extract(ExtractArgs a) {
   const int itn = blockIdx.y;
   const Item it = a.items[itn];
   const cpx<T>* U = (const cpx<T>*)a.pre + (size_t)(it.first_chunk + it.n_chunks - 1) * TILE;
-  cpx<T>* out = (cpx<T>*)a.out + (size_t)itn * a.n * a.n;
+  cpx<T>* out = (cpx<T>*)a.out + (size_t)it.src * a.n * a.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n * a.n; i += gridDim.x * blockDim.x) {
     const int r = i / a.n, c = i % a.n;
     out[i] = U[r * 64 + c];
@@ -353,7 +354,7 @@ __device__ void slice_dA(const GradArgs& g, const AlphaArgs& aa, int it, int k, 
   const BasisIdx B{g.n_ctrl, g.n_static};
   const double* G = g.gtrace + (size_t)n * g.nb;
   const double h = g.dt, kap = LMAG_SQ3 * h * h / 12.0;
-  const double* bc = g.static_coef ? (const double*)g.static_coef + (size_t)it * g.n_static : nullptr;
+  const double* bc = g.static_coef ? (const double*)g.static_coef + (size_t)g.items[it].src * g.n_static : nullptr;
   for (int c = 0; c < g.n_ctrl; ++c) {
     const double base = 0.5 * h * G[B.L(c)];
     double comm = 0.0;
@@ -382,6 +383,7 @@ template <typename T>
 __device__ void item_grad(const GradArgs& g, int it, int k, double* out) {
   AlphaArgs aa{};
   aa.amps = g.amps; aa.item_amp_offset = g.item_amp_offset; aa.ctrl_scale = g.ctrl_scale;
+  aa.items = g.items;
   aa.n_ctrl = g.n_ctrl; aa.hold_foh = g.hold_foh;
   const Item item = g.items[it];
   const int N = item.n_slices;
@@ -397,7 +399,7 @@ __device__ void item_grad(const GradArgs& g, int it, int k, double* out) {
     for (int c = 0; c < g.n_ctrl; ++c) out[c] += l1 * dA1[c] + l2 * dA2[c];
   }
   for (int c = 0; c < g.n_ctrl; ++c) {
-    const double eps = g.ctrl_scale ? ((const double*)g.ctrl_scale)[(size_t)it * g.n_ctrl + c] : 1.0;
+    const double eps = g.ctrl_scale ? ((const double*)g.ctrl_scale)[(size_t)item.src * g.n_ctrl + c] : 1.0;
     out[c] *= eps * g.inv_d2;
   }
 }
@@ -417,7 +419,7 @@ template <typename T> __global__ void k_grad(GradArgs g, int n_units, int max_sl
     if (k == 0 && threadIdx.x == 0 && g.F_out) {
       double f = 0.0;
       for (int i = b; i < e; ++i) f += g.F_items[g.group_items[i]];
-      g.F_out[unit] = cnt ? f / cnt : 0.0;
+      g.F_out[g.group_global ? g.group_global[unit] : unit] = cnt ? f / cnt : 0.0;
     }
     if (!g.grad || !g.gtrace || k >= g.items[it0].n_slices) return;
     for (int i = b; i < e; ++i) {

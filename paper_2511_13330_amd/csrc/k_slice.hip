@@ -246,14 +246,13 @@ __global__ void __launch_bounds__(WG) k_traces(SliceArgs a, int n_total) {
 // One slice forward; returns S_n in R. Stores go to the workspace when requested.
 template <typename T>
 __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
-                          Clock& ck) {
+                          cpx<T>* ws, Clock& ck) {
   RT<T> A;
   rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)n), 64);
   const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
   const double* b = pade_b<T>(a.pade, m);
   ck.mark(0);
-  const bool st = a.store && a.ws_tiles;
-  cpx<T>* ws = st ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
+  const bool st = ws != nullptr;
 
   __syncthreads();
   put<T, false>(A, slot<T, 0>(sh, gs));
@@ -363,10 +362,10 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     rt_identity(P);
     for (int k = 0; k < ch.count; ++k) {
       const int n = ch.first + k;
-      if (a.store && a.ws_tiles)
-        rt_store<T, false>(P, tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES + WS_PLOC), 64);
+      cpx<T>* ws = (a.store && a.ws_tiles) ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
+      if (ws) rt_store<T, false>(P, ws + WS_PLOC * TILE, 64);
       RT<T> S;
-      fwd_slice<T>(S, sh, gs, a, n, ck);
+      fwd_slice<T>(S, sh, gs, a, n, ws, ck);
       __syncthreads();
       put<T, false>(S, slot<T, 3>(sh, gs));
       __syncthreads();
@@ -385,8 +384,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
 // Z_{n-1}^T on exit.
 template <typename T>
 __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
-                          Clock& ck) {
-  const cpx<T>* ws = tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES);
+                          const cpx<T>* ws, Clock& ck) {
   const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
@@ -524,10 +522,37 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
     const Chunk ch = a.chunks[idx];
+    cpx<T>* rs = a.recompute ? tile_at<T>(a.rscratch, (size_t)blockIdx.x * a.max_chunk * WS_TILES)
+                             : nullptr;
+    if (rs) {
+      // recompute the chunk's forward into this workgroup's scratch tiles
+      RT<T> P;
+      rt_identity(P);
+      for (int k = 0; k < ch.count; ++k) {
+        cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
+        rt_store<T, false>(P, ws + WS_PLOC * TILE, 64);
+        RT<T> S;
+        fwd_slice<T>(S, sh, gs, a, ch.first + k, ws, ck);
+        if (k + 1 < ch.count) {
+          __syncthreads();
+          put<T, false>(S, slot<T, 3>(sh, gs));
+          __syncthreads();
+          RT<T> Pn;
+          rt_zero(Pn);
+          mm(Pn, slot<T, 3>(sh, gs), P);
+          rt_copy(P, Pn);
+        }
+      }
+    }
     RT<T> Z;
     rt_load<T, true>(Z, tile_at<T>((void*)a.env, (size_t)ch.chunk), 64);
     ck.mark(0);
-    for (int k = ch.count - 1; k >= 0; --k) bwd_slice<T>(Z, sh, gs, a, ch.first + k, ck);
+    for (int k = ch.count - 1; k >= 0; --k) {
+      const int n = ch.first + k;
+      const cpx<T>* ws = rs ? rs + (size_t)k * WS_TILES * TILE
+                            : tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES);
+      bwd_slice<T>(Z, sh, gs, a, n, ws, ck);
+    }
   }
   ck.flush(a.clk ? a.clk + 16 : nullptr);
 }
@@ -593,7 +618,7 @@ __global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, Sl
   __shared__ Shared<T> sh;
   Clock ck(nullptr, sh.clk);
   RT<T> R;
-  fwd_slice<T>(R, sh, gs + 2 * SLOT, a, 0, ck);
+  fwd_slice<T>(R, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
   rt_store<T, false>(R, C, 64);
 }
 

@@ -80,6 +80,8 @@ struct lmag_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
   int64_t plan_info[5] = {0, 0, 0, 0, 0};
+  bool plan_recompute = false;
+  int plan_waves = 0;
   bool clk_on = false;
   long long* clk_dev = nullptr;
 
@@ -107,22 +109,26 @@ struct Plan {
   std::vector<Chunk> chunks;
   std::vector<int32_t> chunk_item, slice_item;
   std::vector<int64_t> amp_off;
-  std::vector<int32_t> group_first, group_items;
+  std::vector<int32_t> group_first, group_items, group_global;
   int total_slices = 0, total_chunks = 0, max_slices = 0, max_chunks = 0, n_groups = 0;
+  int chunk_size = 0;
+  bool recompute = false;
 };
 
 struct Layout {
-  size_t items, chunks, chunk_item, slice_item, amp_off, group_first, group_items, meta_end;
-  size_t counters, alpha, gtrace, ms, nlev, F_items, st64, st, totals, pre[2], suf[2], env, gscratch,
-      omega, tiles, total;
+  size_t items, chunks, chunk_item, slice_item, amp_off, group_first, group_items, group_global,
+      meta_end;
+  size_t counters, alpha, gtrace, ms, nlev, F_items, st64, st, totals, pre[2], suf[2], env,
+      gscratch, omega, tiles, rscratch, total;
 };
 
-lmag_status plan_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
-                       int n_targets, Plan& p) {
+// Checks every argument of a compute call on the host before anything runs.
+lmag_status validate_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+                           int n_targets) {
   if (!b) return c->fail(LMAG_E_INVALID, "batch is NULL");
   if (b->n_items < 1) return c->fail(LMAG_E_INVALID, "n_items must be >= 1");
   if (!b->n_slices || !b->slice_offset) return c->fail(LMAG_E_INVALID, "n_slices/slice_offset NULL");
-  if (!b->amps) return c->fail(LMAG_E_INVALID, "amps is NULL");
+  if (!b->amps && c->nc > 0) return c->fail(LMAG_E_INVALID, "amps is NULL");
   if (!(b->dt > 0.0) || !std::isfinite(b->dt)) return c->fail(LMAG_E_INVALID, "dt must be finite and > 0");
   if (b->n_groups < 0) return c->fail(LMAG_E_INVALID, "n_groups < 0");
   if (b->n_groups > 0 && !b->group_of_item) return c->fail(LMAG_E_INVALID, "group_of_item NULL");
@@ -132,36 +138,69 @@ lmag_status plan_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_o
     if (b->slice_offset[i] < 0) return c->fail(LMAG_E_INVALID, "slice_offset[i] < 0");
     total += b->n_slices[i];
   }
-  if (total > (1LL << 30)) return c->fail(LMAG_E_UNSUPPORTED, "too many slices in one call");
+  if (total > (1LL << 34)) return c->fail(LMAG_E_UNSUPPORTED, "too many slices in one call");
   if (target_of_item)
     for (int i = 0; i < b->n_items; ++i)
       if (target_of_item[i] < 0 || target_of_item[i] >= n_targets)
         return c->fail(LMAG_E_INVALID, "target_of_item out of range");
-  // chunk size
-  int C = c->chunk;
-  if (C <= 0) {
-    long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
-    C = (int)std::min<long long>(64, std::max<long long>(1, per));
+  if (b->n_groups > 0) {
+    std::vector<int> first(b->n_groups, -1);
+    for (int i = 0; i < b->n_items; ++i) {
+      const int gi = b->group_of_item[i];
+      if (gi < 0 || gi >= b->n_groups) return c->fail(LMAG_E_INVALID, "group_of_item out of range");
+      if (first[gi] < 0) first[gi] = i;
+      else if (b->slice_offset[i] != b->slice_offset[first[gi]] || b->n_slices[i] != b->n_slices[first[gi]])
+        return c->fail(LMAG_E_INVALID, "items of a group must share amplitudes and length");
+    }
+    for (int gi = 0; gi < b->n_groups; ++gi)
+      if (first[gi] < 0) return c->fail(LMAG_E_INVALID, "empty group");
   }
-  p.items.resize(b->n_items);
-  p.amp_off.resize(b->n_items);
+  return LMAG_OK;
+}
+
+int auto_chunk(const lmag_ctx* c, long long total) {
+  if (c->chunk > 0) return c->chunk;
+  const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
+  return (int)std::min<long long>(64, std::max<long long>(1, per));
+}
+
+// Plan of one wave: the caller's items `idx` (grouped calls: whole groups,
+// with wave-local group numbers).
+void plan_wave(const lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+               const std::vector<int>& idx, Plan& p) {
+  long long total = 0;
+  for (int i : idx) total += b->n_slices[i];
+  const int C = auto_chunk(c, total);
+  p.chunk_size = C;
+  const int n = (int)idx.size();
+  p.items.resize(n);
+  p.amp_off.resize(n);
+  std::vector<int> gmap;
+  if (b->n_groups > 0) gmap.assign(b->n_groups, -1);
   int slice = 0, chunk = 0;
-  for (int i = 0; i < b->n_items; ++i) {
+  for (int li = 0; li < n; ++li) {
+    const int i = idx[li];
     const int N = b->n_slices[i];
     const int L = (N + C - 1) / C;
     Item it{};
     it.first_chunk = chunk; it.n_chunks = L; it.first_slice = slice; it.n_slices = N;
     it.target = target_of_item ? target_of_item[i] : 0;
-    it.group = b->n_groups > 0 ? b->group_of_item[i] : -1;
-    p.items[i] = it;
-    p.amp_off[i] = b->slice_offset[i];
+    it.src = i;
+    it.group = -1;
+    if (b->n_groups > 0) {
+      const int g = b->group_of_item[i];
+      if (gmap[g] < 0) { gmap[g] = (int)p.group_global.size(); p.group_global.push_back(g); }
+      it.group = gmap[g];
+    }
+    p.items[li] = it;
+    p.amp_off[li] = b->slice_offset[i];
     for (int k = 0; k < L; ++k) {
       Chunk ch{};
-      ch.item = i; ch.first = slice + k * C; ch.count = std::min(C, N - k * C); ch.chunk = chunk + k;
+      ch.item = li; ch.first = slice + k * C; ch.count = std::min(C, N - k * C); ch.chunk = chunk + k;
       p.chunks.push_back(ch);
-      p.chunk_item.push_back(i);
+      p.chunk_item.push_back(li);
     }
-    for (int k = 0; k < N; ++k) p.slice_item.push_back(i);
+    for (int k = 0; k < N; ++k) p.slice_item.push_back(li);
     slice += N;
     chunk += L;
     p.max_slices = std::max(p.max_slices, N);
@@ -173,26 +212,15 @@ lmag_status plan_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_o
   std::stable_sort(p.chunks.begin(), p.chunks.end(),
                    [](const Chunk& a, const Chunk& b2) { return a.count > b2.count; });
   if (b->n_groups > 0) {
-    p.n_groups = b->n_groups;
-    std::vector<std::vector<int32_t>> g(b->n_groups);
-    for (int i = 0; i < b->n_items; ++i) {
-      const int gi = b->group_of_item[i];
-      if (gi < 0 || gi >= b->n_groups) return c->fail(LMAG_E_INVALID, "group_of_item out of range");
-      g[gi].push_back(i);
-    }
+    p.n_groups = (int)p.group_global.size();
+    std::vector<std::vector<int32_t>> g(p.n_groups);
+    for (int li = 0; li < n; ++li) g[p.items[li].group].push_back(li);
     p.group_first.push_back(0);
-    for (int gi = 0; gi < b->n_groups; ++gi) {
-      if (g[gi].empty()) return c->fail(LMAG_E_INVALID, "empty group");
-      const int i0 = g[gi][0];
-      for (int i : g[gi]) {
-        if (b->slice_offset[i] != b->slice_offset[i0] || b->n_slices[i] != b->n_slices[i0])
-          return c->fail(LMAG_E_INVALID, "items of a group must share amplitudes and length");
-        p.group_items.push_back(i);
-      }
+    for (auto& v : g) {
+      for (int li : v) p.group_items.push_back(li);
       p.group_first.push_back((int32_t)p.group_items.size());
     }
   }
-  return LMAG_OK;
 }
 
 Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int grid) {
@@ -208,6 +236,7 @@ Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int gr
   L.amp_off = take(p.amp_off.size() * 8);
   L.group_first = take(p.group_first.size() * 4);
   L.group_items = take(p.group_items.size() * 4);
+  L.group_global = take(p.group_global.size() * 4);
   L.meta_end = o;
   L.counters = take(256);
   L.alpha = take((size_t)p.total_slices * c->nb * 8);
@@ -225,7 +254,8 @@ Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int gr
   L.env = grad ? take((size_t)p.total_chunks * tile) : 0;
   L.gscratch = c->prec == 64 ? take((size_t)grid * 2 * SLOT * es) : 0;
   L.omega = take((size_t)p.total_slices * tile);
-  L.tiles = grad ? take((size_t)p.total_slices * WS_TILES * tile) : 0;
+  L.tiles = grad && !p.recompute ? take((size_t)p.total_slices * WS_TILES * tile) : 0;
+  L.rscratch = grad && p.recompute ? take((size_t)grid * p.chunk_size * WS_TILES * tile) : 0;
   L.total = o;
   return L;
 }
@@ -284,6 +314,7 @@ lmag_status upload_plan(lmag_ctx* c, const Plan& p, const Layout& L, hipStream_t
   put(L.amp_off, p.amp_off.data(), p.amp_off.size() * 8);
   put(L.group_first, p.group_first.data(), p.group_first.size() * 4);
   put(L.group_items, p.group_items.data(), p.group_items.size() * 4);
+  put(L.group_global, p.group_global.data(), p.group_global.size() * 4);
   hipError_t e = hipMemcpyAsync(c->ws, h, L.meta_end, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(plan)");
   e = hipEventRecord(c->upload_done, s);
@@ -330,7 +361,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
 
   AlphaArgs aa{};
   aa.prec = c->prec; aa.amps = b->amps; aa.item_amp_offset = (const int64_t*)at(L.amp_off);
-  aa.items = items; aa.n_items = b->n_items; aa.static_coef = b->static_coef;
+  aa.items = items; aa.n_items = (int)p.items.size(); aa.static_coef = b->static_coef;
   aa.ctrl_scale = b->ctrl_scale; aa.n_ctrl = c->nc; aa.n_static = c->ns; aa.order = c->order;
   aa.hold_foh = c->hold == LMAG_FOH; aa.nb = c->nb; aa.dt = b->dt;
   aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(L.alpha);
@@ -349,6 +380,9 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   sa.nlev = (int8_t*)at(L.nlev);
   sa.gscratch = c->prec == 64 ? at(L.gscratch) : nullptr; sa.pade = c->pade;
   sa.omega = at(L.omega); sa.clk = c->clk_on ? c->clk_dev : nullptr;
+  sa.recompute = grad && p.recompute; sa.rscratch = sa.recompute ? at(L.rscratch) : nullptr;
+  sa.max_chunk = p.chunk_size;
+  if (sa.recompute) { sa.store = 0; sa.ws_tiles = nullptr; }
   { StageTimer t(c, 1, s); HIPCHK(launch_omega(c->prec, sa, p.total_slices, s), "omega"); }
   { StageTimer t(c, 2, s); HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward"); }
   c->last_ms = (int8_t*)at(L.ms);
@@ -361,7 +395,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   int buf = 0;
   for (int st = 1; st < p.max_chunks; st <<= 1) {
     ScanArgs sc{};
-    sc.prec = c->prec; sc.items = items; sc.n_items = b->n_items;
+    sc.prec = c->prec; sc.items = items; sc.n_items = (int)p.items.size();
     sc.n_chunks_total = p.total_chunks; sc.step = st;
     sc.pre_in = pre_cur; sc.pre_out = at(L.pre[buf]);
     sc.suf_in = want_suf ? suf_cur : nullptr; sc.suf_out = want_suf ? at(L.suf[buf]) : nullptr;
@@ -373,7 +407,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
 
   if (S_out) {
     ExtractArgs ea{};
-    ea.prec = c->prec; ea.items = items; ea.n_items = b->n_items; ea.pre = pre_cur;
+    ea.prec = c->prec; ea.items = items; ea.n_items = (int)p.items.size(); ea.pre = pre_cur;
     ea.out = S_out; ea.n = c->n;
     HIPCHK(launch_extract(ea, s), "extract");
   }
@@ -389,10 +423,11 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   const bool grouped = p.n_groups > 0;
   double* F_items = grouped ? (double*)at(L.F_items) : F_out;
   EnvArgs ev{};
-  ev.prec = c->prec; ev.items = items; ev.n_items = b->n_items;
+  ev.prec = c->prec; ev.items = items; ev.n_items = (int)p.items.size();
   ev.chunk_item = (const int32_t*)at(L.chunk_item); ev.n_chunks_total = p.total_chunks;
   ev.pre = pre_cur; ev.suf = suf_cur; ev.st = st_tiles; ev.st64 = (const double*)at(L.st64);
   ev.env = grad ? at(L.env) : nullptr; ev.F = F_items; ev.Fim = nullptr; ev.d = c->d;
+  ev.f_by_src = grouped ? 0 : 1;
   { StageTimer t(c, 4, s); HIPCHK(launch_env(ev, s), "env"); }
 
   if (grad) {
@@ -405,13 +440,14 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     GradArgs ga{};
     ga.prec = c->prec; ga.gtrace = grad ? (const double*)at(L.gtrace) : nullptr;
     ga.amps = b->amps; ga.item_amp_offset = (const int64_t*)at(L.amp_off); ga.items = items;
-    ga.n_items = b->n_items; ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
+    ga.n_items = (int)p.items.size(); ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
     ga.n_ctrl = c->nc; ga.n_static = c->ns; ga.order = c->order; ga.hold_foh = c->hold == LMAG_FOH;
     ga.nb = c->nb; ga.dt = b->dt; ga.inv_d2 = 1.0 / ((double)c->d * c->d);
     ga.grad = grad ? grad_out : nullptr;
     ga.group_first_item = grouped ? (const int32_t*)at(L.group_first) : nullptr;
     ga.group_items = grouped ? (const int32_t*)at(L.group_items) : nullptr;
     ga.n_groups = p.n_groups; ga.F_items = F_items; ga.F_out = grouped ? F_out : nullptr;
+    ga.group_global = grouped ? (const int32_t*)at(L.group_global) : nullptr;
     if (!grad) {
       // group means of F only: reuse the grad kernel with a null gradient
       ga.gtrace = nullptr;
@@ -421,20 +457,106 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   return LMAG_OK;
 }
 
-lmag_status prepare(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item, int n_targets,
-                    bool grad, bool fidelity, Plan& p, Layout& L, int& grid, hipStream_t s) {
-  lmag_status st = plan_batch(c, b, target_of_item, fidelity ? n_targets : 1, p);
+size_t device_budget(lmag_ctx* c) {
+  if (c->ws_max) return c->ws_max;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) { (void)hipGetLastError(); return (size_t)64 << 30; }
+  return (size_t)((double)(fr + c->ws_size) * 0.85);
+}
+
+// Splits the batch into waves that fit the workspace budget (groups stay
+// whole). A wave whose stored per-slice tiles do not fit runs in recompute
+// mode; a unit that does not fit even then is LMAG_E_NOMEM.
+lmag_status run_waves(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+                      int n_targets, bool grad, bool fidelity, const void* U_target,
+                      double* F_out, void* grad_out, void* S_out, hipStream_t s) {
+  lmag_status st = validate_batch(c, b, target_of_item, fidelity ? n_targets : 1);
   if (st != LMAG_OK) return st;
-  grid = std::max(1, std::min(p.total_chunks, c->n_cu));
-  L = layout(c, p, fidelity ? n_targets : 0, grad, grid);
-  c->plan_info[0] = p.total_slices;
-  c->plan_info[1] = p.total_chunks;
-  c->plan_info[2] = p.chunks.empty() ? 0 : p.chunks[0].count;
-  c->plan_info[3] = grid;
-  c->plan_info[4] = (int64_t)L.total;
-  st = ensure_ws(c, L.total);
-  if (st != LMAG_OK) return st;
-  return upload_plan(c, p, L, s);
+  // units: whole groups (grouped calls) or single items, in order
+  std::vector<std::vector<int>> units;
+  if (b->n_groups > 0) {
+    units.resize(b->n_groups);
+    for (int i = 0; i < b->n_items; ++i) units[b->group_of_item[i]].push_back(i);
+  } else {
+    units.resize(b->n_items);
+    for (int i = 0; i < b->n_items; ++i) units[i].push_back(i);
+  }
+  const size_t budget = device_budget(c);
+  const int nt = fidelity ? n_targets : 0;
+  auto fits = [&](const std::vector<int>& idx, bool recompute, Plan& p, Layout& L, int& grid) {
+    p = Plan();
+    plan_wave(c, b, target_of_item, idx, p);
+    p.recompute = recompute;
+    grid = std::max(1, std::min(p.total_chunks, c->n_cu));
+    L = layout(c, p, nt, grad, grid);
+    if (recompute && L.total > budget) {
+      // fewer persistent workgroups need less recompute scratch
+      const size_t es = (c->prec == 32 ? 8 : 16);
+      const size_t per_wg = (size_t)p.chunk_size * WS_TILES * TILE * es +
+                            (c->prec == 64 ? (size_t)2 * SLOT * es : 0) + 512;
+      const size_t over = L.total - budget;
+      const int cut = (int)((over + per_wg - 1) / per_wg);
+      if (cut >= grid) return false;
+      grid -= cut;
+      L = layout(c, p, nt, grad, grid);
+    }
+    return L.total <= budget;
+  };
+  size_t u = 0;
+  int waves = 0;
+  while (u < units.size()) {
+    std::vector<int> idx = units[u];
+    Plan p;
+    Layout L{};
+    int grid = 0;
+    bool recompute = false;
+    if (!fits(idx, false, p, L, grid)) {
+      if (!grad || !fits(idx, true, p, L, grid))
+        return c->fail(LMAG_E_NOMEM, "one item (group) needs " + std::to_string(L.total) +
+                                         " bytes of workspace, over the budget of " +
+                                         std::to_string(budget));
+      recompute = true;
+    }
+    size_t v = u + 1;
+    if (!recompute) {
+      // grow the wave by doubling, then by single units
+      size_t step = 1;
+      while (v < units.size()) {
+        std::vector<int> trial = idx;
+        const size_t end = std::min(units.size(), v + step);
+        for (size_t k = v; k < end; ++k) trial.insert(trial.end(), units[k].begin(), units[k].end());
+        Plan p2;
+        Layout L2{};
+        int g2 = 0;
+        if (fits(trial, false, p2, L2, g2)) {
+          idx.swap(trial);
+          p = std::move(p2); L = L2; grid = g2;
+          v = end;
+          step *= 2;
+        } else if (step > 1) {
+          step = 1;
+        } else {
+          break;
+        }
+      }
+    }
+    st = ensure_ws(c, L.total);
+    if (st != LMAG_OK) return st;
+    st = upload_plan(c, p, L, s);
+    if (st != LMAG_OK) return st;
+    c->plan_info[0] = p.total_slices;
+    c->plan_info[1] = p.total_chunks;
+    c->plan_info[2] = p.chunk_size;
+    c->plan_info[3] = grid;
+    c->plan_info[4] = (int64_t)L.total;
+    c->plan_recompute = p.recompute;
+    st = run(c, b, p, L, grad, fidelity, U_target, n_targets, F_out, grad_out, S_out, s, grid);
+    if (st != LMAG_OK) return st;
+    u = v;
+    ++waves;
+  }
+  c->plan_waves = waves;
+  return LMAG_OK;
 }
 
 }  // namespace
@@ -593,13 +715,8 @@ lmag_status lmag_propagate(lmag_ctx* c, const lmag_batch* b, void* S_out, void* 
     if (b && b->n_groups) return c->fail(LMAG_E_INVALID, "groups apply to fidelity calls only");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    Plan p;
-    Layout L{};
-    int grid = 0;
-    lmag_status st = prepare(c, b, nullptr, 0, false, false, p, L, grid, s);
-    if (st != LMAG_OK) return st;
     c->last_stream = s;
-    return run(c, b, p, L, false, false, nullptr, 0, nullptr, nullptr, S_out, s, grid);
+    return run_waves(c, b, nullptr, 0, false, false, nullptr, nullptr, nullptr, S_out, s);
   } catch (const std::bad_alloc&) {
     return c->fail(LMAG_E_NOMEM, "host allocation failed");
   } catch (...) {
@@ -617,14 +734,9 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx* c, const lmag_batch* b, const void*
     if (!F_out) return c->fail(LMAG_E_INVALID, "F_out is NULL");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    Plan p;
-    Layout L{};
-    int grid = 0;
-    const bool grad = grad_out != nullptr;
-    lmag_status st = prepare(c, b, target_of_item, n_targets, grad, true, p, L, grid, s);
-    if (st != LMAG_OK) return st;
     c->last_stream = s;
-    return run(c, b, p, L, grad, true, U_target, n_targets, F_out, grad_out, nullptr, s, grid);
+    return run_waves(c, b, target_of_item, n_targets, grad_out != nullptr, true, U_target, F_out,
+                     grad_out, nullptr, s);
   } catch (const std::bad_alloc&) {
     return c->fail(LMAG_E_NOMEM, "host allocation failed");
   } catch (...) {
@@ -765,6 +877,8 @@ lmag_status lmag_last_plan(lmag_ctx* c, int64_t* out) {
   if (!c) return LMAG_E_INVALID;
   if (!out) return c->fail(LMAG_E_INVALID, "NULL output");
   for (int i = 0; i < 5; ++i) out[i] = c->plan_info[i];
+  out[5] = c->plan_recompute ? 1 : 0;
+  out[6] = c->plan_waves;
   return LMAG_OK;
 }
 
