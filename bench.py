@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="slices per work unit (0 = auto)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune chunk length and inverse variant before the timed steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -140,6 +142,9 @@ def main():
     def step(a=amps, ns=n_slices, st=static):
         return sysm.fidelity_and_grad(a, ns, cfg["dt"], UT, static_coef=st)
 
+    tuned = None
+    if args.autotune and args.chunk == 0:
+        tuned = sysm.autotune(amps, n_slices, cfg["dt"], UT, static_coef=static, reps=1)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -185,7 +190,9 @@ def main():
                                "FOH second-order Magnus, FP32 forward+adjoint gradient, "
                                f"batch of {B} pulses per step",
                    "batch_pulses": B, "n_slices": 4096, "superop_dim": 64,
-                   "chunk_slices": plan["chunk_slices"], "grid": plan["grid"]},
+                   "chunk_slices": plan["chunk_slices"], "grid": plan["grid"],
+                   "inverse": "autotuned" if tuned else "auto (MFMA Neumann where bounded)",
+                   "autotune": list(tuned) if tuned else None},
         "roofline": roofline,
         "whole_step_tflops": total_flops / (elapsed / args.steps) / 1e12,
         "other_kernel": {"kernel": other, "achieved_tflops": fl2 / (ms2 * 1e-3) / 1e12,

@@ -134,6 +134,23 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx *ctx, const lmag_batch *batch,
                                    const int32_t *target_of_item, double *F_out,
                                    void *grad_out, void *hip_stream);
 
+/* Autotuner of the persistent slice kernels: times lmag_fidelity_and_grad on
+ * this batch (reps timed calls after one warm-up, HIP events on the stream) for
+ * every candidate chunk length (slices per work unit) and both inverse variants
+ * of the Pade denominator (0: MFMA binary-Neumann product where its norm bound
+ * allows, else Gauss-Jordan; 1: Gauss-Jordan always). The fastest pair is kept
+ * for calls with chunk_slices = 0 whose precision, order, d and total slice
+ * count (power-of-two bucket) match, and appended as one JSON line to the file
+ * named by the environment variable LMAG_TUNE_CACHE if it is set.
+ * best_out: HOST int32 [2] (chunk, inverse) or NULL; best_ms_out: HOST or NULL.
+ * Blocks. Outputs of the timed calls go to internal buffers. */
+lmag_status lmag_autotune(lmag_ctx *ctx, const lmag_batch *batch, const void *U_target,
+                          int n_targets, const int32_t *target_of_item, int reps,
+                          int32_t *best_out, double *best_ms_out, void *hip_stream);
+/* Load tuning lines written by lmag_autotune (path: HOST string). Lines that
+ * do not parse are skipped. */
+lmag_status lmag_load_tuning(lmag_ctx *ctx, const char *path);
+
 /* Wait for the stream and report any pending device error. */
 lmag_status lmag_sync(lmag_ctx *ctx, void *hip_stream);
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -82,6 +83,9 @@ struct lmag_ctx {
   int64_t plan_info[5] = {0, 0, 0, 0, 0};
   bool plan_recompute = false;
   int plan_waves = 0;
+  // tuning: chosen (chunk, inverse variant) per key; inv_variant 0 auto, 1 Gauss-Jordan
+  int inv_variant = 0;
+  std::vector<std::pair<std::string, std::pair<int, int>>> tuned;
   bool clk_on = false;
   long long* clk_dev = nullptr;
 
@@ -158,8 +162,23 @@ lmag_status validate_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* targ
   return LMAG_OK;
 }
 
+std::string tune_key(const lmag_ctx* c, long long total) {
+  int b = 0;
+  while ((1LL << (b + 1)) <= total) ++b;
+  return "p" + std::to_string(c->prec) + "_o" + std::to_string(c->order) + "_d" +
+         std::to_string(c->d) + "_s" + std::to_string(b);
+}
+
+const std::pair<int, int>* tuned_for(const lmag_ctx* c, long long total) {
+  const std::string k = tune_key(c, total);
+  for (auto& t : c->tuned)
+    if (t.first == k) return &t.second;
+  return nullptr;
+}
+
 int auto_chunk(const lmag_ctx* c, long long total) {
   if (c->chunk > 0) return c->chunk;
+  if (const auto* t = tuned_for(c, total)) return t->first;
   const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
   return (int)std::min<long long>(64, std::max<long long>(1, per));
 }
@@ -378,6 +397,12 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   sa.totals = at(L.totals); sa.env = grad ? at(L.env) : nullptr;
   sa.gtrace = grad ? (double*)at(L.gtrace) : nullptr; sa.ms = (int8_t*)at(L.ms);
   sa.nlev = (int8_t*)at(L.nlev);
+  {
+    int inv = c->inv_variant;
+    if (inv == 0 && c->chunk <= 0)
+      if (const auto* t = tuned_for(c, p.total_slices)) inv = t->second;
+    if (inv == 1) sa.nlev = nullptr;   // Gauss-Jordan for every slice
+  }
   sa.gscratch = c->prec == 64 ? at(L.gscratch) : nullptr; sa.pade = c->pade;
   sa.omega = at(L.omega); sa.clk = c->clk_on ? c->clk_dev : nullptr;
   sa.recompute = grad && p.recompute; sa.rscratch = sa.recompute ? at(L.rscratch) : nullptr;
@@ -764,6 +789,121 @@ lmag_status lmag_adam_project(lmag_ctx* c, int precision, int64_t rows, int n_ct
   a.bc1 = 1.0 - std::pow(beta1, (double)step); a.bc2 = 1.0 - std::pow(beta2, (double)step);
   a.grad_scale = grad_scale; a.lo = lo; a.hi = hi; a.row_active = row_active;
   HIPCHK(launch_adam_project(precision, a, (hipStream_t)hip_stream), "adam");
+  return LMAG_OK;
+}
+
+lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target, int n_targets,
+                          const int32_t* target_of_item, int reps, int32_t* best_out,
+                          double* best_ms_out, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  try {
+    if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
+    if (!U_target || n_targets < 1) return c->fail(LMAG_E_INVALID, "U_target NULL or n_targets < 1");
+    if (reps < 1) return c->fail(LMAG_E_INVALID, "reps must be >= 1");
+    lmag_status st = validate_batch(c, b, target_of_item, n_targets);
+    if (st != LMAG_OK) return st;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    long long total = 0;
+    int64_t rows = 0;
+    for (int i = 0; i < b->n_items; ++i) {
+      total += b->n_slices[i];
+      rows = std::max<int64_t>(rows, b->slice_offset[i] + b->n_slices[i]);
+    }
+    const size_t es = c->prec == 32 ? 4 : 8;
+    void* Fd = nullptr;
+    void* Gd = nullptr;
+    const int nf = b->n_groups > 0 ? b->n_groups : b->n_items;
+    if (hipMalloc(&Fd, (size_t)nf * 8) != hipSuccess ||
+        hipMalloc(&Gd, std::max<size_t>(8, (size_t)rows * c->nc * es)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (Fd) (void)hipFree(Fd);
+      return c->fail(LMAG_E_NOMEM, "autotune output buffers");
+    }
+    const int saved_chunk = c->chunk, saved_inv = c->inv_variant;
+    const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
+    std::vector<int> chunks;
+    for (int C : {2, 4, 8, 16, 32, 64, 128, 256})
+      if (C <= std::max<long long>(2, 4 * per) && C >= std::min<long long>(per / 4, 64)) chunks.push_back(C);
+    if (chunks.empty()) chunks.push_back(auto_chunk(c, total));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e300;
+    int bestC = chunks[0], bestInv = 0;
+    for (int inv : {0, 1}) {
+      for (int C : chunks) {
+        c->chunk = C;
+        c->inv_variant = inv;
+        st = run_waves(c, b, target_of_item, n_targets, true, true, U_target, (double*)Fd, Gd,
+                       nullptr, s);   // warm-up (also sizes the workspace)
+        if (st != LMAG_OK) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == LMAG_OK; ++r)
+          st = run_waves(c, b, target_of_item, n_targets, true, true, U_target, (double*)Fd, Gd,
+                         nullptr, s);
+        (void)hipEventRecord(e1, s);
+        if (st != LMAG_OK) break;
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = c->hip_fail(hipGetLastError(), "autotune timing");
+          break;
+        }
+        const double per_call = ms / reps;
+        if (per_call < best) { best = per_call; bestC = C; bestInv = inv; }
+      }
+      if (st != LMAG_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(Fd);
+    (void)hipFree(Gd);
+    c->chunk = saved_chunk;
+    c->inv_variant = saved_inv;
+    if (st != LMAG_OK) return st;
+    const std::string k = tune_key(c, total);
+    bool found = false;
+    for (auto& t : c->tuned)
+      if (t.first == k) { t.second = {bestC, bestInv}; found = true; }
+    if (!found) c->tuned.push_back({k, {bestC, bestInv}});
+    if (const char* path = std::getenv("LMAG_TUNE_CACHE")) {
+      if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "{\"key\": \"%s\", \"chunk\": %d, \"inverse\": %d, \"ms\": %.4f}\n",
+                     k.c_str(), bestC, bestInv, best);
+        std::fclose(f);
+      }
+    }
+    if (best_out) { best_out[0] = bestC; best_out[1] = bestInv; }
+    if (best_ms_out) *best_ms_out = best;
+    return LMAG_OK;
+  } catch (const std::bad_alloc&) {
+    return c->fail(LMAG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return c->fail(LMAG_E_DEVICE, "unknown error");
+  }
+}
+
+lmag_status lmag_load_tuning(lmag_ctx* c, const char* path) {
+  if (!c) return LMAG_E_INVALID;
+  if (!path) return c->fail(LMAG_E_INVALID, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return c->fail(LMAG_E_INVALID, std::string("cannot open ") + path);
+  char line[512];
+  int n = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    char key[128];
+    int C = 0, inv = 0;
+    if (std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"inverse\": %d", key, &C, &inv) == 3 &&
+        C > 0 && (inv == 0 || inv == 1)) {
+      bool found = false;
+      for (auto& t : c->tuned)
+        if (t.first == key) { t.second = {C, inv}; found = true; }
+      if (!found) c->tuned.push_back({key, {C, inv}});
+      ++n;
+    }
+  }
+  std::fclose(f);
   return LMAG_OK;
 }
 

@@ -153,6 +153,29 @@ class System:
             float(beta1), float(beta2), float(eps), float(grad_scale), float(lo), float(hi), ra,
             _stream(stream)), self._ctx)
 
+    def autotune(self, amps, n_slices, dt, U_target, slice_offset=None, static_coef=None,
+                 ctrl_scale=None, target_of_item=None, groups=None, reps=2, stream=None):
+        """Time the pipeline over chunk lengths and inverse variants; returns
+        (chunk, inverse_variant, ms per call) of the fastest."""
+        b, keep, n_items, ng = self._batch(amps, n_slices, slice_offset, dt, static_coef,
+                                           ctrl_scale, groups)
+        UT = torch.as_tensor(U_target, dtype=torch.complex128, device=self.device)
+        UT = UT.reshape(-1, self.d, self.d).contiguous()
+        tp = None
+        if target_of_item is not None:
+            toi = np.ascontiguousarray(target_of_item, dtype=np.int32).reshape(-1)
+            keep.append(toi)
+            tp = toi.ctypes.data_as(_lib.c_int32_p)
+        best = np.zeros(2, dtype=np.int32)
+        ms = ctypes.c_double()
+        check(lib().lmag_autotune(self._ctx, ctypes.byref(b), ctypes.c_void_p(UT.data_ptr()),
+                                  UT.shape[0], tp, int(reps), best.ctypes.data_as(_lib.c_int32_p),
+                                  ctypes.byref(ms), _stream(stream)), self._ctx)
+        return int(best[0]), int(best[1]), ms.value
+
+    def load_tuning(self, path):
+        check(lib().lmag_load_tuning(self._ctx, str(path).encode()), self._ctx)
+
     def sync(self, stream=None):
         check(lib().lmag_sync(self._ctx, _stream(stream)), self._ctx)
 
