@@ -23,6 +23,7 @@ from .liouville import vec, unvec, liouvillian, lift_hamiltonian
 from .magnus import gl2_nodes, slice_omegas, slice_omega
 from .expm import expm_taylor, frechet_block
 from .optim import adam_project
+from . import mlp
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
                          grad_adjoint, grad_adjoint_at, grad_fd, grad_fd_cached, rk4_propagator,
                          slice_products)

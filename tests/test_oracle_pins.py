@@ -316,3 +316,61 @@ def test_adam_projection_and_mask():
                                     active=[True, False])
     assert np.array_equal(out[0], [1.0, 0.0])      # clipped both ways
     assert np.array_equal(out[1], th[1]) and np.array_equal(m[1], [0, 0])
+
+
+# ------------------------------------------------------------------ MLP pins
+def test_bf16_rounding_bit_patterns():
+    from oracle.mlp import bf16_round
+    one = 1.0
+    assert bf16_round(one) == 1.0
+    assert bf16_round(1.0 + 2.0 ** -8) == 1.0                    # tie -> even (down)
+    assert bf16_round(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6    # tie -> even (up)
+    assert bf16_round(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert bf16_round(-2.5) == -2.5
+    x = np.random.default_rng(0).standard_normal(1000)
+    r = bf16_round(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x))          # half an ulp of 8 bits
+
+
+def test_gelu_closed_forms():
+    from oracle.mlp import gelu, gelu_grad
+    assert gelu(0.0) == 0.0 and gelu_grad(0.0) == 0.5
+    assert abs(gelu(10.0) - 10.0) < 1e-12 and abs(gelu(-10.0)) < 1e-12
+    # 0.5 x (1 + erf(x/sqrt2)) at x = 1: Phi(1) = 0.8413447460685429
+    assert abs(gelu(1.0) - 0.8413447460685429) < 1e-15
+    x = np.linspace(-4, 4, 41)
+    h = 1e-6
+    assert np.allclose(gelu_grad(x), (gelu(x + h) - gelu(x - h)) / (2 * h), atol=1e-8)
+
+
+def test_mlp_backward_matches_finite_differences():
+    from oracle.mlp import forward, mse_loss, backward
+    rng = np.random.default_rng(4)
+    sizes = [7, 11, 9, 5]
+    params = [(rng.standard_normal((o, i)) / np.sqrt(i), rng.standard_normal(o) * 0.1)
+              for i, o in zip(sizes[:-1], sizes[1:])]
+    X = rng.standard_normal((6, 7))
+    Y = rng.uniform(0, 1, (6, 5))
+
+    def loss(ps):
+        pre, acts = forward(ps, X, round_bf16=False)
+        return mse_loss(pre[-1], Y)[0]
+
+    pre, acts = forward(params, X, round_bf16=False)
+    _, dz = mse_loss(pre[-1], Y)
+    grads = backward(params, pre, acts, dz, round_bf16=False)
+    h = 1e-6
+    for li, (W, b) in enumerate(params):
+        for (i, j) in [(0, 0), (W.shape[0] - 1, W.shape[1] - 1), (1, 2)]:
+            Wp = W.copy(); Wp[i, j] += h
+            Wm = W.copy(); Wm[i, j] -= h
+            pp = list(params); pp[li] = (Wp, b)
+            pm = list(params); pm[li] = (Wm, b)
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            assert abs(fd - grads[li][0][i, j]) < 1e-7 * max(1.0, abs(fd)) + 1e-10
+        bp = b.copy(); bp[0] += h
+        bm = b.copy(); bm[0] -= h
+        pp = list(params); pp[li] = (W, bp)
+        pm = list(params); pm[li] = (W, bm)
+        fd = (loss(pp) - loss(pm)) / (2 * h)
+        assert abs(fd - grads[li][1][0]) < 1e-7 * max(1.0, abs(fd)) + 1e-10
