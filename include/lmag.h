@@ -168,6 +168,41 @@ lmag_status lmag_adam_project(lmag_ctx *ctx, int precision, int64_t rows, int n_
                               double grad_scale, double lo, double hi,
                               const uint8_t *row_active, void *hip_stream);
 
+/* ---- Learned pulse proposal: multilayer perceptron kernels ----------------
+ * bfloat16 operands (uint16_t storage, round to nearest even), FP32
+ * accumulation on MFMA. All arrays are DEVICE, row-major. */
+enum { LMAG_ACT_GELU = 1, LMAG_ACT_SIGMOID = 2 };
+
+/* Forward of one Linear layer: pre = X W^T + b.
+ * X: bf16 [rows][n_in]; W: bf16 [n_out][n_in]; b: fp32 [n_out].
+ * pre_out: fp32 [rows][n_out] (needed by the backward) or NULL.
+ * act = LMAG_ACT_GELU:    Y = bf16 [rows][n_out] = bf16(gelu(pre)), gelu exact (erf).
+ * act = LMAG_ACT_SIGMOID: Y = fp32 [rows][n_out] = scale * sigmoid(pre). */
+lmag_status lmag_mlp_forward(lmag_ctx *ctx, int rows, int n_in, int n_out, const uint16_t *X,
+                             const uint16_t *W, const float *b, int act, float scale,
+                             float *pre_out, void *Y, void *hip_stream);
+
+/* Backward of one Linear layer given G = dL/dpre: bf16 G16 [rows][n_out] for
+ * the products and fp32 G32 [rows][n_out] for the bias sum.
+ * dW: fp32 [n_out][n_in] = G^T X;  db: fp32 [n_out] = column sums of G32.
+ * If dprev16 != NULL: the gradient of the previous layer's pre-activation,
+ * (G W) * gelu'(pre_prev), with pre_prev fp32 [rows][n_in], is written as
+ * bf16 dprev16 and fp32 dprev32 [rows][n_in]. */
+lmag_status lmag_mlp_backward(lmag_ctx *ctx, int rows, int n_in, int n_out, const uint16_t *X,
+                              const uint16_t *W, const uint16_t *G16, const float *G32,
+                              float *dW, float *db, const float *pre_prev, uint16_t *dprev16,
+                              float *dprev32, void *hip_stream);
+
+/* Mean squared error of sigmoid(z) against targets y in [0, 1] (z, y fp32 [n]):
+ * loss (DEVICE double [1]) = mean((sigmoid(z) - y)^2); dz = dloss/dz as fp32
+ * dz32 and bf16 dz16 [n] (either may be NULL). Deterministic. */
+lmag_status lmag_mlp_mse(lmag_ctx *ctx, int64_t n, const float *z, const float *y, float *dz32,
+                         uint16_t *dz16, double *loss, void *hip_stream);
+
+/* out[i] = bf16(in[i]), round to nearest even; n elements. */
+lmag_status lmag_cast_bf16(lmag_ctx *ctx, const float *in, uint16_t *out, int64_t n,
+                           void *hip_stream);
+
 /* Host-only queries (no device needed). */
 /* Pade coefficients b_0..b_m of r_m = p_m / p_m(-x), m in {3, 5, 7}. */
 lmag_status lmag_pade_coefficients(int m, double *b_out);

@@ -57,6 +57,14 @@ SIGNATURES = {
     "lmag_fidelity_and_grad": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_int,
                                        c_int32_p, c_void_p, c_void_p, c_void_p]),
     "lmag_sync": (c_int, [c_void_p, c_void_p]),
+    "lmag_mlp_forward": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                 c_int, ctypes.c_float, c_void_p, c_void_p, c_void_p]),
+    "lmag_mlp_backward": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p]),
+    "lmag_mlp_mse": (c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                             c_void_p, c_void_p]),
+    "lmag_cast_bf16": (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_int64, c_void_p]),
     "lmag_autotune": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_int, c_int32_p, c_int,
                               c_int32_p, c_double_p, c_void_p]),
     "lmag_load_tuning": (c_int, [c_void_p, ctypes.c_char_p]),

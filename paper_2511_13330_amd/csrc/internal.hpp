@@ -163,6 +163,26 @@ struct AdamArgs {
 };
 hipError_t launch_adam_project(int prec, const AdamArgs& a, hipStream_t s);
 
+// learned proposal (MLP) kernels
+enum { MLP_STORE = 0, MLP_BIAS_GELU = 1, MLP_BIAS_SIGMOID = 2, MLP_GELU_GRAD = 3 };
+struct MlpGemmArgs {
+  int M, N, K;
+  const uint16_t* A; int64_t lda_r, lda_c;   // A(i,k) = A[i*lda_r + k*lda_c] (bf16)
+  const uint16_t* B; int64_t ldb_r, ldb_c;   // B(k,j) = B[k*ldb_r + j*ldb_c] (bf16)
+  int mode;
+  const float* bias;        // [N]
+  const float* aux;         // [M][N] pre-activation of the previous layer (GELU_GRAD)
+  float scale;              // head scale
+  float* C32;               // [M][N] fp32 output (pre-activation / gradient), may be null
+  uint16_t* C16;            // [M][N] bf16 output
+  float* Y32;               // [M][N] head output
+};
+hipError_t launch_mlp_gemm(const MlpGemmArgs& a, hipStream_t s);
+hipError_t launch_colsum(const float* G, int rows, int cols, float* out, hipStream_t s);
+hipError_t launch_mse(const float* z, const float* y, int64_t n, float* dz32, uint16_t* dz16,
+                      double* part, double* loss, hipStream_t s);
+hipError_t launch_cast_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
+
 // debug / unit-test kernels (single 64x64 tiles)
 hipError_t launch_debug_gemm(int prec, const void* A, const void* B, void* C, int transA, hipStream_t s);
 hipError_t launch_debug_inverse(int prec, const void* A, void* C, hipStream_t s);

@@ -75,6 +75,7 @@ struct lmag_ctx {
   int8_t* last_ms = nullptr;
   int last_total_slices = 0;
   void* dbg_scratch = nullptr;
+  double* mse_part = nullptr;
   PadeTable pade{};
   // stage timers
   bool prof = false;
@@ -628,6 +629,7 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->basis32) (void)hipFree(c->basis32);
   if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
   if (c->clk_dev) (void)hipFree(c->clk_dev);
+  if (c->mse_part) (void)hipFree(c->mse_part);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
   for (auto& pe : c->ev_pending) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
@@ -904,6 +906,79 @@ lmag_status lmag_load_tuning(lmag_ctx* c, const char* path) {
     }
   }
   std::fclose(f);
+  return LMAG_OK;
+}
+
+lmag_status lmag_mlp_forward(lmag_ctx* c, int rows, int n_in, int n_out, const uint16_t* X,
+                             const uint16_t* W, const float* b, int act, float scale, float* pre_out,
+                             void* Y, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (rows < 0 || n_in < 1 || n_out < 1) return c->fail(LMAG_E_INVALID, "bad layer shape");
+  if (rows > 0 && (!X || !W || !b || !Y)) return c->fail(LMAG_E_INVALID, "NULL array");
+  if (act != LMAG_ACT_GELU && act != LMAG_ACT_SIGMOID) return c->fail(LMAG_E_INVALID, "act");
+  DeviceGuard g(c->device);
+  MlpGemmArgs a{};
+  a.M = rows; a.N = n_out; a.K = n_in;
+  a.A = X; a.lda_r = n_in; a.lda_c = 1;
+  a.B = W; a.ldb_r = 1; a.ldb_c = n_in;      // B(k, j) = W[j][k]
+  a.bias = b; a.scale = scale; a.C32 = pre_out;
+  if (act == LMAG_ACT_GELU) { a.mode = MLP_BIAS_GELU; a.C16 = (uint16_t*)Y; }
+  else { a.mode = MLP_BIAS_SIGMOID; a.Y32 = (float*)Y; }
+  HIPCHK(launch_mlp_gemm(a, (hipStream_t)hip_stream), "mlp_forward");
+  return LMAG_OK;
+}
+
+lmag_status lmag_mlp_backward(lmag_ctx* c, int rows, int n_in, int n_out, const uint16_t* X,
+                              const uint16_t* W, const uint16_t* G16, const float* G32, float* dW,
+                              float* db, const float* pre_prev, uint16_t* dprev16, float* dprev32,
+                              void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (rows < 1 || n_in < 1 || n_out < 1) return c->fail(LMAG_E_INVALID, "bad layer shape");
+  if (!X || !W || !G16 || !G32 || !dW || !db) return c->fail(LMAG_E_INVALID, "NULL array");
+  if (dprev16 && !pre_prev) return c->fail(LMAG_E_INVALID, "pre_prev NULL");
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  MlpGemmArgs a{};
+  // dW[j][k] = sum_i G[i][j] X[i][k]
+  a.M = n_out; a.N = n_in; a.K = rows;
+  a.A = G16; a.lda_r = 1; a.lda_c = n_out;
+  a.B = X; a.ldb_r = n_in; a.ldb_c = 1;
+  a.mode = MLP_STORE; a.C32 = dW;
+  HIPCHK(launch_mlp_gemm(a, s), "mlp_dW");
+  HIPCHK(launch_colsum(G32, rows, n_out, db, s), "mlp_db");
+  if (dprev16) {
+    MlpGemmArgs d{};
+    // dX[i][k] = sum_j G[i][j] W[j][k], times gelu'(pre_prev[i][k])
+    d.M = rows; d.N = n_in; d.K = n_out;
+    d.A = G16; d.lda_r = n_out; d.lda_c = 1;
+    d.B = W; d.ldb_r = n_in; d.ldb_c = 1;
+    d.mode = MLP_GELU_GRAD; d.aux = pre_prev; d.C16 = dprev16; d.C32 = dprev32;
+    HIPCHK(launch_mlp_gemm(d, s), "mlp_dX");
+  }
+  return LMAG_OK;
+}
+
+lmag_status lmag_mlp_mse(lmag_ctx* c, int64_t n, const float* z, const float* y, float* dz32,
+                         uint16_t* dz16, double* loss, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (n < 1 || !z || !y || !loss) return c->fail(LMAG_E_INVALID, "bad MSE arguments");
+  DeviceGuard g(c->device);
+  if (!c->mse_part) {
+    if (hipMalloc((void**)&c->mse_part, 256 * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      c->mse_part = nullptr;
+      return c->fail(LMAG_E_NOMEM, "mse scratch");
+    }
+  }
+  HIPCHK(launch_mse(z, y, n, dz32, dz16, c->mse_part, loss, (hipStream_t)hip_stream), "mlp_mse");
+  return LMAG_OK;
+}
+
+lmag_status lmag_cast_bf16(lmag_ctx* c, const float* in, uint16_t* out, int64_t n, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (n < 0 || (n > 0 && (!in || !out))) return c->fail(LMAG_E_INVALID, "bad cast arguments");
+  DeviceGuard g(c->device);
+  HIPCHK(launch_cast_bf16(in, out, n, (hipStream_t)hip_stream), "cast_bf16");
   return LMAG_OK;
 }
 
