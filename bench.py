@@ -104,6 +104,50 @@ def read_traffic(kernel):
         return None
 
 
+def robust_sweep(args):
+    """Candidates x quasi-static noise samples with uneven slice counts in one
+    call per sweep: per-candidate mean fidelity and mean gradient."""
+    import torch
+    import synth
+    from paper_2511_13330_amd import spin_chain_system
+    n_cand = int(os.environ.get("LMAG_ROBUST_CANDIDATES", "256"))
+    cfg = synth.config2(2, n_cand=n_cand)
+    sysm = spin_chain_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2,
+                             hold="foh", chunk_slices=args.chunk)
+    amps = np.concatenate(cfg["amps_per_cand"])
+    ns_c = np.asarray(cfg["n_slices_per_cand"])
+    off_c = np.concatenate([[0], np.cumsum(ns_c)[:-1]])
+    S = cfg["dB"].shape[0]
+    ns = np.repeat(ns_c, S)
+    off = np.repeat(off_c, S)
+    groups = np.repeat(np.arange(n_cand), S)
+    static = (np.asarray(cfg["B"])[None, None, :] + cfg["dB"][None, :, :]).reshape(-1, 3)
+    scale = np.tile(cfg["eps"], (n_cand, 1))
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    kw = dict(slice_offset=off, static_coef=static, ctrl_scale=scale, groups=groups)
+    F, g = sysm.fidelity_and_grad(a, ns, cfg["dt"], cfg["U_target"], **kw)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = max(1, min(args.steps, 3))
+    for _ in range(steps):
+        F, g = sysm.fidelity_and_grad(a, ns, cfg["dt"], cfg["U_target"], **kw)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    plan = sysm.last_plan()
+    slices = int(ns.sum())
+    flops = slices * (forward_flops_per_slice(3, 0) + backward_flops_per_slice(3, 0))
+    return {"metric": "robust sweep: candidates x noise samples fwd+grad, seconds per sweep",
+            "value": dt, "unit": "s/sweep", "n_gpus": 1, "higher_is_better": False,
+            "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (config-2 distributions: N ~ U{512..4096}, dB ~ N(0, 2pi), "
+                    "eps ~ N(1, 0.01))",
+            "config": {"workload": f"{n_cand} candidates x {S} noise samples, uneven N, "
+                                   "3-spin FOH 2nd order", "items": int(len(ns)),
+                       "slice_evaluations": slices, "waves": plan["waves"]},
+            "slice_evals_per_s": slices / dt, "tflops_algorithmic": flops / dt / 1e12,
+            "F_mean_first_candidates": [float(x) for x in F[:4].cpu().numpy()]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +159,9 @@ def main():
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
     ap.add_argument("--autotune", action="store_true",
                     help="tune chunk length and inverse variant before the timed steps")
+    ap.add_argument("--workload", default="pulse", choices=["pulse", "proposal", "robust"],
+                    help="pulse: the headline metric (default); proposal: learned proposal + "
+                         "refine vs cold start; robust: candidates x noise samples, uneven N")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -128,6 +175,23 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
+    if args.workload == "proposal":
+        from paper_2511_13330_amd.proposal import run_experiment
+        r = run_experiment(log=lambda s: print(s, file=sys.stderr, flush=True))
+        p = r["proposal_refine"]
+        print(json.dumps({
+            "metric": "fraction of held-out targets reaching F >= 0.999 within 50 refine steps",
+            "value": p["fraction_F_ge_0999"], "unit": "fraction", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "bf16 MLP / f32 propagator",
+            "data": "synthetic reachable targets (closed-system propagators of smooth seeded pulses)",
+            "config": {"workload": "learned proposal: 133-512-512-512-512 MLP, 256 slices of "
+                                   "0.25 ns, batch 4096 inference, <= 50 refine steps",
+                       "n_train": r["n_train"], "n_test": r["n_test"]},
+            "result": r}), flush=True)
+        return
+    if args.workload == "robust":
+        print(json.dumps(robust_sweep(args)), flush=True)
+        return
     dev = torch.device("cuda", 0)
     B = args.batch
     cfg = synth.config1_batch(B)

@@ -90,22 +90,26 @@ def config3_six(seed=3):
     return cfg
 
 
-def config4_targets(seed=4, n=4096, n_slices=256, smooth=8):
+def config4_targets(seed=4, n=4096, n_slices=256, modes=4):
     """Learned-proposal workload: per target a nominal field vector, quasi-static
-    noise scales and a smooth reference pulse. The target unitary itself is the
-    closed-system propagator of that reference pulse (reachable by construction);
-    it is computed by whichever side consumes these draws."""
+    noise scales (network inputs only) and a smooth reference pulse: for each
+    control, A_MAX/2 (1 + sum_k a_k sin(pi k t / T + phi_k)) with
+    sum_k |a_k| <= 1, so the pulse stays in [0, A_MAX]. The target unitary is
+    the closed-system propagator of that pulse (reachable by construction); it
+    is computed by whichever side consumes these draws."""
     rng = np.random.default_rng(seed)
     B = rng.uniform(-B_RANGE, B_RANGE, (n, 3))
     sigB = rng.uniform(0.0, TWO_PI * 1.0, n)
     sigJ = rng.uniform(0.0, 0.01, n)
-    raw = rng.uniform(0.0, A_MAX, (n, n_slices + smooth - 1, 2))
-    # moving average keeps the pulse in [0, A_MAX] and makes it smooth
-    k = np.ones(smooth) / smooth
-    ref = np.stack([np.stack([np.convolve(raw[i, :, c], k, mode="valid")
-                              for c in range(2)], axis=-1) for i in range(n)])
-    return dict(B=B, sigB=sigB, sigJ=sigJ, ref_amps=ref, n_slices=n_slices,
-                dt=2.5e-4, d=8, n_spins=3, n_ctrl=2, order=2, hold="foh",
+    a = rng.uniform(-1.0, 1.0, (n, 2, modes))
+    a /= np.maximum(1.0, np.abs(a).sum(axis=2, keepdims=True))
+    phi = rng.uniform(0.0, TWO_PI, (n, 2, modes))
+    t = (np.arange(n_slices) + 0.5) / n_slices
+    k = np.arange(1, modes + 1)
+    wave = np.sin(np.pi * k[None, None, :, None] * t[None, None, None, :] + phi[..., None])
+    ref = 0.5 * A_MAX * (1.0 + np.einsum("ncm,ncmt->nct", a, wave))
+    return dict(B=B, sigB=sigB, sigJ=sigJ, ref_amps=np.transpose(ref, (0, 2, 1)).copy(),
+                n_slices=n_slices, dt=2.5e-4, d=8, n_spins=3, n_ctrl=2, order=2, hold="foh",
                 precision="f32")
 
 
