@@ -121,7 +121,7 @@ def robust_sweep(args):
     ns = np.repeat(ns_c, S)
     off = np.repeat(off_c, S)
     groups = np.repeat(np.arange(n_cand), S)
-    static = (np.asarray(cfg["B"])[None, None, :] + cfg["dB"][None, :, :]).reshape(-1, 3)
+    static = np.tile(np.asarray(cfg["B"])[None, :] + cfg["dB"], (n_cand, 1))
     scale = np.tile(cfg["eps"], (n_cand, 1))
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     kw = dict(slice_offset=off, static_coef=static, ctrl_scale=scale, groups=groups)
