@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
     ap.add_argument("--autotune", action="store_true",
                     help="tune chunk length and inverse variant before the timed steps")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--workload", default="pulse", choices=["pulse", "proposal", "robust"],
                     help="pulse: the headline metric (default); proposal: learned proposal + "
                          "refine vs cold start; robust: candidates x noise samples, uneven N")
@@ -193,6 +195,13 @@ def main():
         print(json.dumps(robust_sweep(args)), flush=True)
         return
     dev = torch.device("cuda", 0)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     B = args.batch
     cfg = synth.config1_batch(B)
     sysm = spin_chain_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2,
