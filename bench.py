@@ -83,9 +83,10 @@ def _cpu_model():
     return "unknown"
 
 
-def read_traffic(kernel):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+def read_traffic(kernel, slices):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE per slice from
+    committed rocprofv3 counter runs, times the slices of one launch), if the
+    counters were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(path):
         return None
@@ -99,7 +100,7 @@ def read_traffic(kernel):
                 h.update(f.read())
         if h.hexdigest() != rec.get("source_sha256"):
             return None
-        return rec.get("bytes_per_launch")
+        return rec["bytes_per_slice"] * slices
     except Exception:
         return None
 
@@ -248,7 +249,8 @@ def main():
     achieved = fl / (ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved,
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA_TFLOPS, "traffic": read_traffic(dom),
+                "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                "traffic": read_traffic(dom, plan["total_slices"]),
                 "flops_per_launch": fl, "ms_per_launch": ms}
     other = [k for k in kernels if k != dom][0]
     fl2, ms2 = kernels[other]
