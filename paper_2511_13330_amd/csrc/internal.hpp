@@ -183,6 +183,53 @@ hipError_t launch_mse(const float* z, const float* y, int64_t n, float* dz32, ui
                       double* part, double* loss, hipStream_t s);
 hipError_t launch_cast_bf16(const float* in, uint16_t* out, int64_t n, hipStream_t s);
 
+// block-tiled path (n = 64 T)
+constexpr int MAX_BIG_NB = 64;
+struct BigGemmArgs {
+  int n, batch;
+  const void* A; const int32_t* Ai;
+  const void* B; const int32_t* Bi;
+  const void* C; const int32_t* Ci;      // output
+  const void* D; const int32_t* Di;      // epilogue addend (may alias C)
+  double alpha, beta, gamma;
+  int transA, transB;
+  const int8_t* pred; int pred_stride; int pred_thresh;   // active if pred[i*stride] > thresh
+};
+struct BigAxpbyArgs {
+  int n, batch;
+  const void* X; const int32_t* Xi;
+  const void* Z; const int32_t* Zi;
+  void* Y; const int32_t* Yi;
+  double a, c, d;
+  const int8_t* ms;         // if set: a *= 2^-s of entry Yi[b] (ms[2 i + 1])
+};
+struct BigOmegaArgs {
+  int n, n_slices, nb;
+  const void* basis; const double* alpha;
+  void* omega; double* part;
+  int8_t* ms; int8_t* nlev;
+  double b3[4];
+};
+struct BigTraceArgs {
+  int n, n_slices, nb, first_slice, trans_basis;
+  const void* K; const void* basis;
+  double* part; double* gtrace;
+};
+struct BigFidArgs {
+  int n, n_items, d;
+  const void* U; const int32_t* U_index;
+  const double* st64; const int32_t* target;
+  double* F; const int32_t* F_index;
+};
+hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s);
+hipError_t launch_baxpby(int prec, const BigAxpbyArgs& g, hipStream_t s);
+hipError_t launch_bomega(int prec, const BigOmegaArgs& g, hipStream_t s);
+hipError_t launch_btraces(int prec, const BigTraceArgs& g, hipStream_t s);
+hipError_t launch_bfidelity(int prec, const BigFidArgs& g, hipStream_t s);
+hipError_t launch_blift(const double* H, int d, double* out, hipStream_t s);
+hipError_t launch_bdissipator(const double* Ls, int n_jump, int d, double* ldl, double* out, hipStream_t s);
+hipError_t launch_btargets(const double* U, int n_targets, int d, double* st64, float* st32, hipStream_t s);
+
 // debug / unit-test kernels (single 64x64 tiles)
 hipError_t launch_debug_gemm(int prec, const void* A, const void* B, void* C, int transA, hipStream_t s);
 hipError_t launch_debug_inverse(int prec, const void* A, void* C, hipStream_t s);

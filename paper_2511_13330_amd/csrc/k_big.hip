@@ -1,0 +1,392 @@
+// Block-tiled kernels for superoperators larger than one 64x64 tile
+// (n = 64 T, T = n / 64 tiles per side; 4 spins: n = 256, 6 spins: n = 4096).
+//
+// Every per-slice step of the Pade / Frechet pipeline is a batched operation
+// over many n x n matrices (all slices, or all chunks for the ordered
+// products). The product kernel assigns one 64 x 64 output tile of one matrix
+// to a workgroup, which accumulates over the T tiles of the contraction with
+// the register-tile MFMA product of tile.hpp (A tile staged through LDS, B tile
+// in registers). Matrices are row-major n x n, interleaved complex.
+#include "tile.hpp"
+#include "internal.hpp"
+#include "pade.hpp"
+
+#include <algorithm>
+
+namespace lmag {
+
+template <typename T> struct BigShared {
+  cpx<T> slot[64 * PITCH];
+  double red[8];
+};
+
+template <typename T>
+__device__ __forceinline__ const cpx<T>* mat(const void* base, const int32_t* idx, int b, size_t nn) {
+  return reinterpret_cast<const cpx<T>*>(base) + (size_t)(idx ? idx[b] : b) * nn;
+}
+
+// C_b = alpha * op(A_b) op(B_b) + beta * D_b + gamma * I, for every batch entry
+// b with (pred == null or pred[b] != 0); other entries copy D_b (or A_b when
+// D is null) into C_b. op = transpose when the flag is set.
+template <typename T, bool TA, bool TB>
+__global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
+  __shared__ BigShared<T> sh;
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  const int b = blockIdx.y;
+  const int ti = blockIdx.x / Tn, tj = blockIdx.x % Tn;
+  cpx<T>* C = const_cast<cpx<T>*>(mat<T>(g.C, g.Ci, b, nn));
+  const cpx<T>* D = g.D ? mat<T>(g.D, g.Di, b, nn) : nullptr;
+  const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
+  if (!active) {
+    const cpx<T>* src = D ? D : mat<T>(g.A, g.Ai, b, nn);
+    RT<T> X;
+    rt_load<T, false>(X, src + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    rt_store<T, false>(X, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    return;
+  }
+  const cpx<T>* A = mat<T>(g.A, g.Ai, b, nn);
+  const cpx<T>* B = mat<T>(g.B, g.Bi, b, nn);
+  RT<T> acc;
+  rt_zero(acc);
+  for (int tk = 0; tk < Tn; ++tk) {
+    // A tile (ti, tk) of op(A): op(A)[ti][tk] = TA ? A[tk][ti]^T : A[ti][tk]
+    RT<T> At, Bt;
+    if (TA) rt_load<T, true>(At, A + (size_t)tk * 64 * g.n + ti * 64, g.n);
+    else rt_load<T, false>(At, A + (size_t)ti * 64 * g.n + tk * 64, g.n);
+    if (TB) rt_load<T, true>(Bt, B + (size_t)tj * 64 * g.n + tk * 64, g.n);
+    else rt_load<T, false>(Bt, B + (size_t)tk * 64 * g.n + tj * 64, g.n);
+    __syncthreads();
+    rt_store<T, false>(At, sh.slot, PITCH);
+    __syncthreads();
+    gemm_acc<T, false, PITCH>(acc, sh.slot, Bt);
+  }
+  const T al = (T)g.alpha;
+  rt_scale(acc, al);
+  if (D && g.beta != 0.0) {
+    RT<T> Dt;
+    rt_load<T, false>(Dt, D + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    rt_axpy(acc, (T)g.beta, Dt);
+  }
+  if (g.gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.gamma);
+  rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
+}
+
+hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s) {
+  if (g.batch <= 0) return hipSuccess;
+  const int Tn = g.n / 64;
+  const dim3 grid(Tn * Tn, g.batch);
+#define LMAG_BG(T, a, b) hipLaunchKernelGGL((k_bgemm<T, a, b>), grid, dim3(WG), 0, s, g)
+  if (prec == 32) {
+    if (g.transA && g.transB) LMAG_BG(float, true, true);
+    else if (g.transA) LMAG_BG(float, true, false);
+    else if (g.transB) LMAG_BG(float, false, true);
+    else LMAG_BG(float, false, false);
+  } else {
+    if (g.transA && g.transB) LMAG_BG(double, true, true);
+    else if (g.transA) LMAG_BG(double, true, false);
+    else if (g.transB) LMAG_BG(double, false, true);
+    else LMAG_BG(double, false, false);
+  }
+#undef LMAG_BG
+  return hipGetLastError();
+}
+
+// Y_b = a X_b + c Z_b + d I (elementwise, batched; Z may be null).
+template <typename T>
+__global__ void k_baxpby(BigAxpbyArgs g) {
+  const size_t nn = (size_t)g.n * g.n;
+  const int b = blockIdx.y;
+  const cpx<T>* X = mat<T>(g.X, g.Xi, b, nn);
+  const cpx<T>* Z = g.Z ? mat<T>(g.Z, g.Zi, b, nn) : nullptr;
+  cpx<T>* Y = const_cast<cpx<T>*>(mat<T>(g.Y, g.Yi, b, nn));
+  double a = g.a;
+  if (g.ms) a = ldexp(a, -(int)g.ms[2 * (size_t)(g.Yi ? g.Yi[b] : b) + 1]);
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x) {
+    cpx<T> y;
+    y.re = T(0);
+    y.im = T(0);
+    if (a != 0.0) { const cpx<T> x = X[e]; y.re = (T)a * x.re; y.im = (T)a * x.im; }
+    if (Z) { const cpx<T> z = Z[e]; y.re += (T)g.c * z.re; y.im += (T)g.c * z.im; }
+    if (g.d != 0.0 && (e / g.n) == (e % g.n)) y.re += (T)g.d;
+    Y[e] = y;
+  }
+}
+
+hipError_t launch_baxpby(int prec, const BigAxpbyArgs& g, hipStream_t s) {
+  if (g.batch <= 0) return hipSuccess;
+  const size_t nn = (size_t)g.n * g.n;
+  const dim3 grid((unsigned)std::min<size_t>((nn + 255) / 256, 1024), g.batch);
+  if (prec == 32) hipLaunchKernelGGL(k_baxpby<float>, grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(k_baxpby<double>, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// Omega_n = sum_j alpha_{n,j} B_j tile by tile; partial FP64 column 1-norms of
+// every 64-row block: part[slice][tile_row][col].
+template <typename T>
+__global__ void __launch_bounds__(WG) k_bomega(BigOmegaArgs g) {
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  const int slice = blockIdx.y;
+  const int ti = blockIdx.x / Tn, tj = blockIdx.x % Tn;
+  const cpx<T>* basis = (const cpx<T>*)g.basis;
+  const double* al = g.alpha + (size_t)slice * g.nb;
+  RT<T> X;
+  rt_zero(X);
+  for (int j = 0; j < g.nb; ++j) {
+    const double aj = al[j];
+    if (aj == 0.0) continue;
+    RT<T> Bt;
+    rt_load<T, false>(Bt, basis + (size_t)j * nn + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    rt_axpy(X, (T)aj, Bt);
+  }
+  cpx<T>* out = (cpx<T>*)g.omega + (size_t)slice * nn;
+  rt_store<T, false>(X, out + (size_t)ti * 64 * g.n + tj * 64, g.n);
+  // column sums of |X| over this tile's 64 rows
+  const Lane L;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double a = (double)X.re[q][r], b = (double)X.im[q][r];
+      s += sqrt(a * a + b * b);
+    }
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  if (L.g == 0) g.part[((size_t)slice * Tn + ti) * g.n + tj * 64 + L.col] = s;
+}
+
+// Per slice: ||Omega||_1 from the partial column sums, (m, s) and Neumann
+// levels; then Omega <- Omega / 2^s.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bnorm(BigOmegaArgs g) {
+  __shared__ double red[256];
+  __shared__ int sc_sh;
+  const int Tn = g.n / 64;
+  const int slice = blockIdx.x;
+  double mx = 0.0;
+  for (int col = threadIdx.x; col < g.n; col += 256) {
+    double cs = 0.0;
+    for (int ti = 0; ti < Tn; ++ti) cs += g.part[((size_t)slice * Tn + ti) * g.n + col];
+    mx = fmax(mx, cs);
+    if (!(cs == cs)) mx = cs;   // NaN propagates
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const double o = red[threadIdx.x + off];
+      red[threadIdx.x] = (o == o) ? fmax(red[threadIdx.x], o) : o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = red[0];
+    int m, s;
+    big_choose_ms<T>(v, m, s);
+    g.ms[2 * (size_t)slice] = (int8_t)m;
+    g.ms[2 * (size_t)slice + 1] = (int8_t)s;
+    if (g.nlev) g.nlev[slice] = (int8_t)big_neumann_levels<T>(ldexp(v, -s), g.b3);
+    sc_sh = s;
+  }
+  __syncthreads();
+  const int s = sc_sh;
+  if (s == 0) return;
+  const T f = (T)ldexp(1.0, -s);
+  const size_t nn = (size_t)g.n * g.n;
+  cpx<T>* X = (cpx<T>*)g.omega + (size_t)slice * nn;
+  for (size_t e = threadIdx.x; e < nn; e += 256) { X[e].re *= f; X[e].im *= f; }
+}
+
+hipError_t launch_bomega(int prec, const BigOmegaArgs& g, hipStream_t s) {
+  if (g.n_slices <= 0) return hipSuccess;
+  const int Tn = g.n / 64;
+  if (prec == 32) {
+    hipLaunchKernelGGL(k_bomega<float>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+    hipLaunchKernelGGL(k_bnorm<float>, dim3(g.n_slices), dim3(256), 0, s, g);
+  } else {
+    hipLaunchKernelGGL(k_bomega<double>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+    hipLaunchKernelGGL(k_bnorm<double>, dim3(g.n_slices), dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+// g[slice][j] = Re sum_x K^T[x] B_j[x]: partial sums per (slice, tile) in
+// part[slice][tile][j], then a fixed-order reduction over tiles.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_btraces_part(BigTraceArgs g) {
+  __shared__ double red[4][MAX_BIG_NB];
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  const int slice = blockIdx.y, tile = blockIdx.x;
+  const int ti = tile / Tn, tj = tile % Tn;
+  const cpx<T>* K = (const cpx<T>*)g.K + (size_t)slice * nn;
+  const cpx<T>* basis = (const cpx<T>*)g.basis;
+  const Lane L;
+  RT<T> Kt;
+  rt_load<T, false>(Kt, K + (size_t)ti * 64 * g.n + tj * 64, g.n);
+  for (int j = 0; j < g.nb; ++j) {
+    RT<T> Bt;
+    // same positions as K^T; with trans_basis the basis is read transposed
+    // (Re Tr(K B_j) = Re sum_{a,b} K[a][b] B_j[b][a] for a K stored untransposed)
+    if (g.trans_basis) rt_load<T, true>(Bt, basis + (size_t)j * nn + (size_t)tj * 64 * g.n + ti * 64, g.n);
+    else rt_load<T, false>(Bt, basis + (size_t)j * nn + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc += (double)Kt.re[q][r] * (double)Bt.re[q][r] - (double)Kt.im[q][r] * (double)Bt.im[q][r];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (L.l == 0) red[L.w][j] = acc;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < g.nb; j += WG)
+    g.part[((size_t)slice * Tn * Tn + tile) * g.nb + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+}
+
+__global__ void k_btraces_sum(BigTraceArgs g) {
+  const int slice = blockIdx.x;
+  const int Tn = g.n / 64;
+  for (int j = threadIdx.x; j < g.nb; j += blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < Tn * Tn; ++t) s += g.part[((size_t)slice * Tn * Tn + t) * g.nb + j];
+    g.gtrace[(size_t)(g.first_slice + slice) * g.nb + j] = s;
+  }
+}
+
+hipError_t launch_btraces(int prec, const BigTraceArgs& g, hipStream_t s) {
+  if (g.n_slices <= 0) return hipSuccess;
+  const int Tn = g.n / 64;
+  if (prec == 32) hipLaunchKernelGGL(k_btraces_part<float>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+  else hipLaunchKernelGGL(k_btraces_part<double>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+  hipLaunchKernelGGL(k_btraces_sum, dim3(g.n_slices), dim3(64), 0, s, g);
+  return hipGetLastError();
+}
+
+// F_item = Re Tr(S_T^dag U) / d^2 = Re sum_{a,b} S_T^dag[a][b] U[b][a] / d^2 in FP64.
+template <typename T>
+__global__ void k_bfidelity(BigFidArgs g) {
+  __shared__ double red[2][256];
+  const int item = blockIdx.x;
+  const size_t nn = (size_t)g.n * g.n;
+  const cpx<T>* U = (const cpx<T>*)g.U + (size_t)g.U_index[item] * nn;
+  const cpx<double>* S = (const cpx<double>*)g.st64 + (size_t)g.target[item] * nn;
+  double re = 0.0, im = 0.0;
+  for (size_t e = threadIdx.x; e < nn; e += 256) {
+    const size_t a = e / g.n, c = e % g.n;
+    const cpx<double> x = S[e];
+    const cpx<T> y = U[c * g.n + a];
+    re += x.re * (double)y.re - x.im * (double)y.im;
+    im += x.re * (double)y.im + x.im * (double)y.re;
+  }
+  red[0][threadIdx.x] = re;
+  red[1][threadIdx.x] = im;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double inv = 1.0 / ((double)g.d * g.d);
+    g.F[g.F_index ? g.F_index[item] : item] = red[0][0] * inv;
+  }
+}
+
+hipError_t launch_bfidelity(int prec, const BigFidArgs& g, hipStream_t s) {
+  if (g.n_items <= 0) return hipSuccess;
+  if (prec == 32) hipLaunchKernelGGL(k_bfidelity<float>, dim3(g.n_items), dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(k_bfidelity<double>, dim3(g.n_items), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// Superoperator lift, dissipator and target for general n = d^2 (double).
+__global__ void k_blift(const cpx<double>* H, int d, cpx<double>* out) {
+  const int n = d * d;
+  const size_t nn = (size_t)n * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(idx / n), b = (int)(idx % n);
+    const int i = a % d, j = a / d, k = b % d, l = b / d;
+    double zr = 0.0, zi = 0.0;
+    if (j == l) { zr += H[i * d + k].re; zi += H[i * d + k].im; }
+    if (i == k) { zr -= H[l * d + j].re; zi -= H[l * d + j].im; }
+    out[idx] = cpx<double>{zi, -zr};
+  }
+}
+
+__global__ void k_bdissipator(const cpx<double>* Ls, int n_jump, int d, const cpx<double>* LdL,
+                              cpx<double>* out) {
+  const int n = d * d;
+  const size_t nn = (size_t)n * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(idx / n), b = (int)(idx % n);
+    const int i = a % d, j = a / d, k = b % d, l = b / d;
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < n_jump; ++q) {
+      const cpx<double>* L = Ls + (size_t)q * d * d;
+      const cpx<double>* M = LdL + (size_t)q * d * d;
+      const cpx<double> x = L[j * d + l], y = L[i * d + k];
+      re += x.re * y.re + x.im * y.im;
+      im += x.re * y.im - x.im * y.re;
+      if (j == l) { re -= 0.5 * M[i * d + k].re; im -= 0.5 * M[i * d + k].im; }
+      if (i == k) { re -= 0.5 * M[l * d + j].re; im -= 0.5 * M[l * d + j].im; }
+    }
+    out[idx] = cpx<double>{re, im};
+  }
+}
+
+// M_q = L_q^dag L_q (d x d, one thread per entry)
+__global__ void k_ldl(const cpx<double>* Ls, int n_jump, int d, cpx<double>* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_jump * d * d) return;
+  const int q = idx / (d * d), x = (idx / d) % d, y = idx % d;
+  const cpx<double>* L = Ls + (size_t)q * d * d;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < d; ++z) {
+    const cpx<double> p = L[z * d + x], r = L[z * d + y];
+    re += p.re * r.re + p.im * r.im;
+    im += p.re * r.im - p.im * r.re;
+  }
+  out[idx] = cpx<double>{re, im};
+}
+
+__global__ void k_btargets(const cpx<double>* U, int n_targets, int d, cpx<double>* st64, cpx<float>* st32) {
+  const int n = d * d;
+  const size_t nn = (size_t)n * n;
+  const int t = blockIdx.y;
+  const cpx<double>* Ut = U + (size_t)t * d * d;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < nn; idx += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(idx / n), c = (int)(idx % n);
+    const int k = r % d, l = r / d, i = c % d, j = c / d;
+    const cpx<double> x = Ut[j * d + l], y = Ut[i * d + k];
+    const cpx<double> o{x.re * y.re + x.im * y.im, x.im * y.re - x.re * y.im};
+    st64[(size_t)t * nn + idx] = o;
+    if (st32) st32[(size_t)t * nn + idx] = cpx<float>{(float)o.re, (float)o.im};
+  }
+}
+
+hipError_t launch_blift(const double* H, int d, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_blift, dim3(1024), dim3(256), 0, s, (const cpx<double>*)H, d, (cpx<double>*)out);
+  return hipGetLastError();
+}
+hipError_t launch_bdissipator(const double* Ls, int n_jump, int d, double* ldl, double* out, hipStream_t s) {
+  if (n_jump > 0)
+    hipLaunchKernelGGL(k_ldl, dim3((n_jump * d * d + 255) / 256), dim3(256), 0, s, (const cpx<double>*)Ls,
+                       n_jump, d, (cpx<double>*)ldl);
+  hipLaunchKernelGGL(k_bdissipator, dim3(1024), dim3(256), 0, s, (const cpx<double>*)Ls, n_jump, d,
+                     (const cpx<double>*)ldl, (cpx<double>*)out);
+  return hipGetLastError();
+}
+hipError_t launch_btargets(const double* U, int n_targets, int d, double* st64, float* st32, hipStream_t s) {
+  hipLaunchKernelGGL(k_btargets, dim3(256, n_targets), dim3(256), 0, s, (const cpx<double>*)U, n_targets, d,
+                     (cpx<double>*)st64, (cpx<float>*)st32);
+  return hipGetLastError();
+}
+
+}  // namespace lmag

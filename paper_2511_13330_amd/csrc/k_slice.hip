@@ -14,6 +14,7 @@
 // running factor in registers as the B operand (see tile.hpp).
 #include "tile.hpp"
 #include "internal.hpp"
+#include "pade.hpp"
 
 namespace lmag {
 
@@ -25,14 +26,6 @@ constexpr int SLOT = 64 * PITCH;
 constexpr int TILE = 64 * 64;
 constexpr int MAXNB = 32;
 constexpr int NPHASE = 16;
-
-// theta_m (Higham 2005): largest ||A||_1 with backward error of r_m below the
-// unit roundoff. Single precision uses m = 3 only; double uses m in {3, 5, 7}.
-// For these (m, theta) the denominator q_m(A) is column diagonally dominant
-// (sum_j>=1 b_j theta^j < 1), so Gauss-Jordan needs no pivoting.
-__constant__ double c_theta32_3 = 4.258730016922831e-1;
-__constant__ double c_theta64[3] = {1.495585217958292e-2, 2.539398330063230e-1,
-                                     9.504178996162932e-1};
 
 template <typename T> struct Shared {
   cpx<T> slots[Cfg<T>::NLDS * SLOT];
@@ -54,33 +47,6 @@ __device__ __forceinline__ void put(const RT<T>& X, cpx<T>* S) { rt_store<T, TRA
 template <typename T>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) {
   gemm_acc<T, false, PITCH>(acc, A, B);
-}
-
-template <typename T>
-__device__ __forceinline__ void choose_ms(double nrm, int& m, int& s) {
-  s = 0;
-  if constexpr (sizeof(T) == 4) {
-    m = 3;
-    const double th = c_theta32_3;
-    if (nrm > th) {
-      s = (int)ceil(log2(nrm / th));
-      while (s < 62 && ldexp(nrm, -s) > th) ++s;
-    }
-  } else {
-    if (nrm <= c_theta64[0]) m = 3;
-    else if (nrm <= c_theta64[1]) m = 5;
-    else {
-      m = 7;
-      const double th = c_theta64[2];
-      if (nrm > th) {
-        s = (int)ceil(log2(nrm / th));
-        while (s < 62 && ldexp(nrm, -s) > th) ++s;
-      }
-    }
-  }
-  if (!(nrm == nrm)) { m = 3; s = 0; }  // NaN input: propagate NaN, no scaling loop
-  if (s < 0) s = 0;
-  if (s > 62) s = 62;
 }
 
 template <typename T>
@@ -113,24 +79,6 @@ struct Clock {
       for (int i = 0; i < NPHASE; ++i) clk[i] += acc[i];
   }
 };
-
-// Levels K of the binary Neumann product Q^{-1} = (I+E)(I+E^2)...(I+E^{2^{K-1}}),
-// E = I - q_m(A), from the bound ||E||_1 <= e = sum_{j>=1} b_j ||A||_1^j: the
-// smallest K with e^{2^K} <= u (1 - e). 0 selects the Gauss-Jordan inverse.
-template <typename T>
-__device__ __forceinline__ int neumann_levels(double nA, const double* b, int m) {
-  double e = 0.0, p = 1.0;
-  for (int j = 1; j <= m; ++j) { p *= nA; e += b[j] * p; }
-  const double u = sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
-  const int kmax = sizeof(T) == 4 ? 4 : 5;
-  if (!(e < 0.5)) return 0;
-  double pe = e;   // e^(2^K)
-  for (int K = 1; K <= kmax; ++K) {
-    pe *= pe;
-    if (pe <= u * (1.0 - e)) return K;
-  }
-  return 0;
-}
 
 // Omega_n / 2^s for a block of slices; FP64 column 1-norm selects (m, s).
 // Thread t owns column t % 64 and rows 16 (t / 64) .. +15 of every slice.

@@ -490,6 +490,388 @@ size_t device_budget(lmag_ctx* c) {
   return (size_t)((double)(fr + c->ws_size) * 0.85);
 }
 
+// ---------------------------------------------------------------------------
+// Block-tiled path (n = 64 T > 64): every per-slice stage is one batched launch
+// over all slices (or over the active chunks of an ordered product step).
+struct BigPlan {
+  std::vector<int32_t> chain_slice, chain_chunk, chain_off;      // forward step k: [off[k], off[k+1])
+  std::vector<int32_t> scan_a, scan_b, scan_c, scan_off;         // per level, prefix then suffix
+  std::vector<int32_t> copy_c, copy_off;                         // inactive entries per level
+  std::vector<int32_t> env_suf_c, env_suf_next, env_nosuf_c;     // S_T^dag Suf_excl / S_T^dag
+  std::vector<int32_t> env_suf_t, env_nosuf_t;                   // their targets
+  std::vector<int32_t> env_pre_c, env_pre_prev, env_nopre_c;     // Pre_excl X / X
+  std::vector<int32_t> item_last_chunk, item_target, item_src;
+  std::vector<int32_t> ident;                                    // 0, 1, 2, ...
+  int C = 0, levels = 0;
+};
+
+lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+                    int n_targets, bool grad, bool fidelity, const void* U_target, double* F_out,
+                    void* grad_out, void* S_out, hipStream_t s) {
+  const int n = c->n, Tn = n / 64;
+  const size_t nn = (size_t)n * n, es = 8, mb = nn * es;   // FP32 complex matrices
+  std::vector<int> all(b->n_items);
+  for (int i = 0; i < b->n_items; ++i) all[i] = i;
+  Plan p;
+  // chunk length: enough independent chunks to fill the device in the chains
+  long long total = 0;
+  int maxN = 0;
+  for (int i = 0; i < b->n_items; ++i) { total += b->n_slices[i]; maxN = std::max(maxN, b->n_slices[i]); }
+  const int saved_chunk = c->chunk;
+  if (c->chunk <= 0) {
+    const long long want_chunks = std::max<long long>(1, 2048 / ((long long)Tn * Tn));
+    c->chunk = (int)std::max<long long>(1, (total + want_chunks - 1) / want_chunks);
+  }
+  plan_wave(c, b, target_of_item, all, p);
+  c->chunk = saved_chunk;
+  const int Ns = p.total_slices, Lc = p.total_chunks, C = p.chunk_size;
+  BigPlan q;
+  q.C = C;
+  // forward chain lists (chunks in original order, not the persistent sort)
+  std::vector<Chunk> chs(Lc);
+  for (const Chunk& ch : p.chunks) chs[ch.chunk] = ch;
+  q.chain_off.push_back(0);
+  for (int k = 0; k < C; ++k) {
+    for (const Chunk& ch : chs)
+      if (ch.count > k) { q.chain_slice.push_back(ch.first + k); q.chain_chunk.push_back(ch.chunk); }
+    q.chain_off.push_back((int32_t)q.chain_slice.size());
+  }
+  // scan levels: inclusive prefix P[c] = P[c] P[c - st]; suffix S[c] = S[c + st] S[c]
+  q.scan_off.push_back(0);
+  q.copy_off.push_back(0);
+  for (int st = 1; st < p.max_chunks; st <<= 1, ++q.levels) {
+    for (int dir = 0; dir < 2; ++dir) {
+      for (int cidx = 0; cidx < Lc; ++cidx) {
+        const Item& it = p.items[p.chunk_item[cidx]];
+        const int lc = cidx - it.first_chunk;
+        if (dir == 0 && lc >= st) { q.scan_a.push_back(cidx); q.scan_b.push_back(cidx - st); q.scan_c.push_back(cidx); }
+        else if (dir == 1 && lc + st < it.n_chunks) { q.scan_a.push_back(cidx + st); q.scan_b.push_back(cidx); q.scan_c.push_back(cidx); }
+        else q.copy_c.push_back(cidx);
+      }
+      q.scan_off.push_back((int32_t)q.scan_a.size());
+      q.copy_off.push_back((int32_t)q.copy_c.size());
+    }
+  }
+  for (int cidx = 0; cidx < Lc; ++cidx) {
+    const Item& it = p.items[p.chunk_item[cidx]];
+    const int lc = cidx - it.first_chunk;
+    if (lc + 1 < it.n_chunks) {
+      q.env_suf_c.push_back(cidx); q.env_suf_next.push_back(cidx + 1); q.env_suf_t.push_back(it.target);
+    } else {
+      q.env_nosuf_c.push_back(cidx); q.env_nosuf_t.push_back(it.target);
+    }
+    if (lc > 0) { q.env_pre_c.push_back(cidx); q.env_pre_prev.push_back(cidx - 1); }
+    else q.env_nopre_c.push_back(cidx);
+  }
+  for (const Item& it : p.items) {
+    q.item_last_chunk.push_back(it.first_chunk + it.n_chunks - 1);
+    q.item_target.push_back(it.target);
+    q.item_src.push_back(it.src);
+  }
+  for (int i = 0; i < std::max(Ns, Lc); ++i) q.ident.push_back(i);
+
+  // ---- workspace: metadata, int lists, then matrices
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  Layout L{};
+  L.items = take(p.items.size() * sizeof(Item));
+  L.chunks = take(p.chunks.size() * sizeof(Chunk));
+  L.chunk_item = take(p.chunk_item.size() * 4);
+  L.slice_item = take(p.slice_item.size() * 4);
+  L.amp_off = take(p.amp_off.size() * 8);
+  L.group_first = take(p.group_first.size() * 4);
+  L.group_items = take(p.group_items.size() * 4);
+  L.group_global = take(p.group_global.size() * 4);
+  std::vector<std::pair<size_t, const std::vector<int32_t>*>> lists;
+  auto list = [&](const std::vector<int32_t>& v) { size_t r = take(v.size() * 4 + 4); lists.push_back({r, &v}); return r; };
+  const size_t o_cs = list(q.chain_slice), o_cc = list(q.chain_chunk), o_sa = list(q.scan_a),
+               o_sb = list(q.scan_b), o_sc = list(q.scan_c), o_cp = list(q.copy_c),
+               o_es = list(q.env_suf_c), o_en = list(q.env_suf_next), o_ens = list(q.env_nosuf_c),
+               o_ep = list(q.env_pre_c), o_epp = list(q.env_pre_prev), o_enp = list(q.env_nopre_c),
+               o_est = list(q.env_suf_t), o_ent = list(q.env_nosuf_t),
+               o_il = list(q.item_last_chunk), o_it = list(q.item_target),
+               o_is = list(q.item_src), o_id = list(q.ident);
+  L.meta_end = o;
+  L.alpha = take((size_t)Ns * c->nb * 8);
+  L.gtrace = take((size_t)Ns * c->nb * 8);
+  L.ms = take((size_t)Ns * 2);
+  L.nlev = take((size_t)Ns);
+  L.F_items = take(p.items.size() * 8);
+  const size_t o_part = take(std::max((size_t)Ns * Tn * n * 8, (size_t)Ns * Tn * Tn * c->nb * 8));
+  L.st64 = take((size_t)std::max(1, n_targets) * nn * 16);
+  L.st = take((size_t)std::max(1, n_targets) * mb);
+  const size_t o_sq = take((size_t)Ns * 64 * 4 + 4);   // slices with s > k, per k
+  const int nslice_mats = grad ? 11 : 7;
+  const size_t o_mats = take((size_t)nslice_mats * Ns * mb);
+  const size_t o_cmats = take((size_t)8 * Lc * mb);
+  L.total = o;
+  if (L.total > device_budget(c))
+    return c->fail(LMAG_E_NOMEM, "block-tiled call needs " + std::to_string(L.total) +
+                                     " bytes of workspace, over the budget");
+  lmag_status st = ensure_ws(c, L.total);
+  if (st != LMAG_OK) return st;
+  // upload metadata + lists in one copy
+  st = ensure_pinned(c, L.meta_end);
+  if (st != LMAG_OK) return st;
+  std::memset(c->pinned, 0, L.meta_end);
+  auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(c->pinned + off, src, bytes); };
+  put(L.items, p.items.data(), p.items.size() * sizeof(Item));
+  put(L.chunks, p.chunks.data(), p.chunks.size() * sizeof(Chunk));
+  put(L.chunk_item, p.chunk_item.data(), p.chunk_item.size() * 4);
+  put(L.slice_item, p.slice_item.data(), p.slice_item.size() * 4);
+  put(L.amp_off, p.amp_off.data(), p.amp_off.size() * 8);
+  put(L.group_first, p.group_first.data(), p.group_first.size() * 4);
+  put(L.group_items, p.group_items.data(), p.group_items.size() * 4);
+  put(L.group_global, p.group_global.data(), p.group_global.size() * 4);
+  for (auto& l : lists) put(l.first, l.second->data(), l.second->size() * 4);
+  HIPCHK(hipMemcpyAsync(c->ws, c->pinned, L.meta_end, hipMemcpyHostToDevice, s), "plan upload");
+  HIPCHK(hipEventRecord(c->upload_done, s), "event");
+  c->upload_pending = true;
+
+  char* w = c->ws;
+  auto at = [&](size_t off) { return (void*)(w + off); };
+  auto ip = [&](size_t off) { return (const int32_t*)(w + off); };
+  auto M = [&](int k) { return at(o_mats + (size_t)k * Ns * mb); };     // per-slice matrix array k
+  auto CM = [&](int k) { return at(o_cmats + (size_t)k * Lc * mb); };   // per-chunk matrix array k
+  void *A = M(0), *A2 = M(1), *R0 = M(2), *S = M(3), *Qi = M(4), *T1 = M(5), *T2 = M(6);
+  void *Pl = grad ? M(7) : nullptr, *Em = grad ? M(8) : nullptr, *T3 = grad ? M(9) : nullptr,
+       *T4 = grad ? M(10) : nullptr;
+  const Item* items = (const Item*)at(L.items);
+
+  auto gemm = [&](int batch, const void* Ap, const int32_t* Ai, const void* Bp, const int32_t* Bi,
+                  const void* Cp, const int32_t* Ci, double alpha, const void* Dp = nullptr,
+                  const int32_t* Di = nullptr, double beta = 0.0, double gamma = 0.0, int tA = 0,
+                  int tB = 0, const int8_t* pred = nullptr, int thresh = 0) {
+    BigGemmArgs g{};
+    g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
+    g.D = Dp; g.Di = Di; g.alpha = alpha; g.beta = beta; g.gamma = gamma; g.transA = tA; g.transB = tB;
+    g.pred = pred; g.pred_stride = 2; g.pred_thresh = thresh;
+    return launch_bgemm(32, g, s);
+  };
+  auto axpby = [&](int batch, const void* X, const int32_t* Xi, void* Y, const int32_t* Yi, double a,
+                   const void* Z = nullptr, const int32_t* Zi = nullptr, double cc = 0.0, double d = 0.0,
+                   const int8_t* ms = nullptr) {
+    BigAxpbyArgs g{};
+    g.n = n; g.batch = batch; g.X = X; g.Xi = Xi; g.Z = Z; g.Zi = Zi; g.Y = Y; g.Yi = Yi;
+    g.a = a; g.c = cc; g.d = d; g.ms = ms;
+    return launch_baxpby(32, g, s);
+  };
+  const double* b3 = c->pade.b3;
+
+  // ---- coefficients and exponents
+  AlphaArgs aa{};
+  aa.prec = 32; aa.amps = b->amps; aa.item_amp_offset = (const int64_t*)at(L.amp_off);
+  aa.items = items; aa.n_items = (int)p.items.size(); aa.static_coef = b->static_coef;
+  aa.ctrl_scale = b->ctrl_scale; aa.n_ctrl = c->nc; aa.n_static = c->ns; aa.order = c->order;
+  aa.hold_foh = c->hold == LMAG_FOH; aa.nb = c->nb; aa.dt = b->dt;
+  aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(L.alpha);
+  aa.n_slices_total = Ns;
+  { StageTimer t(c, 0, s); HIPCHK(launch_alpha(aa, s), "alpha"); }
+  BigOmegaArgs om{};
+  om.n = n; om.n_slices = Ns; om.nb = c->nb; om.basis = c->basis32; om.alpha = (const double*)at(L.alpha);
+  om.omega = A; om.part = (double*)at(o_part); om.ms = (int8_t*)at(L.ms); om.nlev = (int8_t*)at(L.nlev);
+  for (int i = 0; i < 4; ++i) om.b3[i] = b3[i];
+  { StageTimer t(c, 1, s); HIPCHK(launch_bomega(32, om, s), "omega"); }
+  c->last_ms = (int8_t*)at(L.ms);
+  c->last_total_slices = Ns;
+  // the host needs the largest scaling exponent and Neumann level count
+  std::vector<int8_t> msh((size_t)Ns * 2), nlh(Ns);
+  HIPCHK(hipMemcpyAsync(msh.data(), at(L.ms), msh.size(), hipMemcpyDeviceToHost, s), "ms");
+  HIPCHK(hipMemcpyAsync(nlh.data(), at(L.nlev), nlh.size(), hipMemcpyDeviceToHost, s), "nlev");
+  HIPCHK(hipStreamSynchronize(s), "sync");
+  int smax = 0, kmax = 1;
+  for (int i = 0; i < Ns; ++i) {
+    smax = std::max<int>(smax, msh[2 * i + 1]);
+    kmax = std::max<int>(kmax, nlh[i] > 0 ? nlh[i] : 4);
+  }
+  // per-k lists of the slices that take a k-th squaring
+  std::vector<int32_t> sq_list, sq_off(1, 0);
+  for (int k = 0; k < smax; ++k) {
+    for (int i = 0; i < Ns; ++i)
+      if (msh[2 * i + 1] > k) sq_list.push_back(i);
+    sq_off.push_back((int32_t)sq_list.size());
+  }
+  if (!sq_list.empty())
+    HIPCHK(hipMemcpy(at(o_sq), sq_list.data(), sq_list.size() * 4, hipMemcpyHostToDevice), "squaring lists");
+  const int8_t* ms_dev = (const int8_t*)at(L.ms);
+
+  // ---- forward: Pade 3 with the Neumann inverse, squarings
+  {
+    StageTimer t(c, 2, s);
+    HIPCHK(gemm(Ns, A, nullptr, A, nullptr, A2, nullptr, 1.0), "A2");
+    HIPCHK(axpby(Ns, A2, nullptr, T1, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");
+    HIPCHK(gemm(Ns, A, nullptr, T1, nullptr, T2, nullptr, 1.0), "U");            // T2 = U
+    HIPCHK(axpby(Ns, A2, nullptr, Qi, nullptr, b3[2], nullptr, nullptr, 0.0, b3[0]), "V");   // Qi = V
+    HIPCHK(axpby(Ns, Qi, nullptr, T1, nullptr, 1.0, T2, nullptr, 1.0), "P");      // T1 = P = V + U
+    HIPCHK(axpby(Ns, Qi, nullptr, S, nullptr, -1.0, T2, nullptr, 1.0, 1.0), "E");  // S = E = I - V + U
+    HIPCHK(axpby(Ns, S, nullptr, T2, nullptr, 1.0, nullptr, nullptr, 0.0, 1.0), "X");  // T2 = X = I + E
+    void *F = S, *X = T2, *F2 = R0, *Xn = Qi;
+    for (int k = 1; k < kmax; ++k) {
+      HIPCHK(gemm(Ns, F, nullptr, F, nullptr, F2, nullptr, 1.0), "F2");
+      HIPCHK(gemm(Ns, F2, nullptr, X, nullptr, Xn, nullptr, 1.0, X, nullptr, 1.0), "X+F2X");
+      std::swap(F, F2);
+      std::swap(X, Xn);
+    }
+    if (X != Qi) HIPCHK(axpby(Ns, X, nullptr, Qi, nullptr, 1.0), "Qinv");
+    HIPCHK(gemm(Ns, Qi, nullptr, T1, nullptr, R0, nullptr, 1.0), "R0");   // R0 = Q^{-1} P
+    HIPCHK(axpby(Ns, R0, nullptr, S, nullptr, 1.0), "S");
+    for (int k = 0; k < smax; ++k) {
+      const int cnt = sq_off[k + 1] - sq_off[k];
+      const int32_t* li = ip(o_sq) + sq_off[k];
+      if (!cnt) continue;
+      HIPCHK(gemm(cnt, S, li, S, li, T1, li, 1.0), "square");
+      HIPCHK(axpby(cnt, T1, li, S, li, 1.0), "square copy");
+    }
+  }
+  // ---- ordered products inside chunks (forward chain), storing P_loc
+  void* Pc[2] = {CM(0), CM(1)};
+  {
+    StageTimer t(c, 2, s);
+    HIPCHK(axpby(Lc, Pc[0], nullptr, Pc[0], nullptr, 0.0, nullptr, nullptr, 0.0, 1.0), "P = I");
+    int cur = 0;
+    for (int k = 0; k < C; ++k) {
+      const int a0 = q.chain_off[k], cnt = q.chain_off[k + 1] - a0;
+      if (cnt == 0) continue;
+      const int32_t* sl = ip(o_cs) + a0;
+      const int32_t* chn = ip(o_cc) + a0;
+      if (grad) HIPCHK(axpby(cnt, Pc[cur], chn, Pl, sl, 1.0), "store P_loc");
+      HIPCHK(gemm(cnt, S, sl, Pc[cur], chn, Pc[cur ^ 1], chn, 1.0), "chain");
+      // chunks not advanced at this step keep their product in the other buffer too
+      HIPCHK(axpby(cnt, Pc[cur ^ 1], chn, Pc[cur], chn, 1.0), "chain sync");
+    }
+  }
+  // ---- scan over chunk totals
+  void* pre[2] = {CM(2), CM(3)};
+  void* suf[2] = {CM(4), CM(5)};
+  const void* pre_cur = Pc[0];
+  const void* suf_cur = Pc[0];
+  {
+    StageTimer t(c, 3, s);
+    int bsel = 0;
+    for (int lv = 0; lv < q.levels; ++lv) {
+      for (int dir = 0; dir < 2; ++dir) {
+        if (dir == 1 && !grad) continue;
+        const int li = 2 * lv + dir;
+        const int a0 = q.scan_off[li], cnt = q.scan_off[li + 1] - a0;
+        const int c0 = q.copy_off[li], ccnt = q.copy_off[li + 1] - c0;
+        const void* in = dir == 0 ? pre_cur : suf_cur;
+        void* out = dir == 0 ? pre[bsel] : suf[bsel];
+        if (cnt) HIPCHK(gemm(cnt, in, ip(o_sa) + a0, in, ip(o_sb) + a0, out, ip(o_sc) + a0, 1.0), "scan");
+        if (ccnt) HIPCHK(axpby(ccnt, in, ip(o_cp) + c0, out, ip(o_cp) + c0, 1.0), "scan copy");
+      }
+      pre_cur = pre[bsel];
+      if (grad) suf_cur = suf[bsel];
+      bsel ^= 1;
+    }
+  }
+  if (S_out) {
+    // U of every item = inclusive prefix at its last chunk
+    BigAxpbyArgs g{};
+    for (size_t i = 0; i < p.items.size(); ++i) {
+      const int lastc = q.item_last_chunk[i];
+      HIPCHK(hipMemcpyAsync((char*)S_out + (size_t)p.items[i].src * mb, (const char*)pre_cur + (size_t)lastc * mb,
+                            mb, hipMemcpyDeviceToDevice, s), "extract");
+    }
+    (void)g;
+  }
+  if (!fidelity) return LMAG_OK;
+  // ---- targets, fidelity, environments
+  HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, (double*)at(L.st64), (float*)at(L.st), s),
+         "targets");
+  const bool grouped = p.n_groups > 0;
+  double* F_items = grouped ? (double*)at(L.F_items) : F_out;
+  {
+    StageTimer t(c, 4, s);
+    BigFidArgs fa{};
+    fa.n = n; fa.n_items = (int)p.items.size(); fa.d = c->d; fa.U = pre_cur; fa.U_index = ip(o_il);
+    fa.st64 = (const double*)at(L.st64); fa.target = ip(o_it); fa.F = F_items;
+    fa.F_index = grouped ? nullptr : ip(o_is);
+    HIPCHK(launch_bfidelity(32, fa, s), "fidelity");
+  }
+  if (grad) {
+    void* X = CM(6);
+    void* env = CM(7);
+    {
+      StageTimer t(c, 4, s);
+      const void* st = at(L.st);
+      if (!q.env_suf_c.empty())
+        HIPCHK(gemm((int)q.env_suf_c.size(), st, ip(o_est), suf_cur, ip(o_en), X, ip(o_es), 1.0), "env X");
+      if (!q.env_nosuf_c.empty())
+        HIPCHK(axpby((int)q.env_nosuf_c.size(), st, ip(o_ent), X, ip(o_ens), 1.0), "env X copy");
+      if (!q.env_pre_c.empty())
+        HIPCHK(gemm((int)q.env_pre_c.size(), pre_cur, ip(o_epp), X, ip(o_ep), env, ip(o_ep), 1.0), "env W");
+      if (!q.env_nopre_c.empty())
+        HIPCHK(axpby((int)q.env_nopre_c.size(), X, ip(o_enp), env, ip(o_enp), 1.0), "env W copy");
+    }
+    // ---- backward chain: M_n = P_loc,n Z, Z <- Z S_n (normal orientation)
+    {
+      StageTimer t(c, 5, s);
+      void* Z[2] = {env, X};
+      int cur = 0;
+      for (int k = C - 1; k >= 0; --k) {
+        const int a0 = q.chain_off[k], cnt = q.chain_off[k + 1] - a0;
+        if (cnt == 0) continue;
+        const int32_t* sl = ip(o_cs) + a0;
+        const int32_t* chn = ip(o_cc) + a0;
+        HIPCHK(gemm(cnt, Pl, sl, Z[cur], chn, Em, sl, 1.0), "M");
+        HIPCHK(gemm(cnt, Z[cur], chn, S, sl, Z[cur ^ 1], chn, 1.0), "Z");
+        HIPCHK(axpby(cnt, Z[cur ^ 1], chn, Z[cur], chn, 1.0), "Z sync");
+      }
+      // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
+      HIPCHK(axpby(Ns, Em, nullptr, Em, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, ms_dev), "E scale");
+      HIPCHK(gemm(Ns, A, nullptr, Em, nullptr, T1, nullptr, 1.0), "AE");
+      HIPCHK(gemm(Ns, Em, nullptr, A, nullptr, T1, nullptr, 1.0, T1, nullptr, 1.0), "L2");       // T1 = L2
+      HIPCHK(axpby(Ns, A2, nullptr, T2, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");      // T2 = W
+      HIPCHK(axpby(Ns, T1, nullptr, T3, nullptr, b3[3]), "LW");                                    // T3 = L_W
+      HIPCHK(gemm(Ns, A, nullptr, T3, nullptr, T4, nullptr, 1.0), "A LW");
+      HIPCHK(gemm(Ns, Em, nullptr, T2, nullptr, T4, nullptr, 1.0, T4, nullptr, 1.0), "LU");       // T4 = L_U
+      HIPCHK(axpby(Ns, T1, nullptr, T3, nullptr, b3[2], T4, nullptr, -1.0), "LQ");                 // T3 = L_Q
+      HIPCHK(axpby(Ns, T1, nullptr, T2, nullptr, b3[2], T4, nullptr, 1.0), "LP");                  // T2 = L_P
+      HIPCHK(gemm(Ns, T3, nullptr, R0, nullptr, T1, nullptr, -1.0, T2, nullptr, 1.0), "X");        // T1 = L_P - L_Q R0
+      HIPCHK(gemm(Ns, Qi, nullptr, T1, nullptr, T3, nullptr, 1.0), "K");                           // T3 = K
+      // squaring recurrence K <- R K + K R, R <- R^2 for the slices with s > k
+      for (int k = 0; k < smax; ++k) {
+        const int cnt = sq_off[k + 1] - sq_off[k];
+        const int32_t* li = ip(o_sq) + sq_off[k];
+        if (!cnt) continue;
+        HIPCHK(gemm(cnt, R0, li, T3, li, T4, li, 1.0), "RK");
+        HIPCHK(gemm(cnt, T3, li, R0, li, T2, li, 1.0, T4, li, 1.0), "RK + KR");
+        HIPCHK(gemm(cnt, R0, li, R0, li, T1, li, 1.0), "R^2");
+        HIPCHK(axpby(cnt, T2, li, T3, li, 1.0), "K");
+        HIPCHK(axpby(cnt, T1, li, R0, li, 1.0), "R");
+      }
+    }
+    {
+      StageTimer t(c, 6, s);
+      BigTraceArgs ta{};
+      ta.n = n; ta.n_slices = Ns; ta.nb = c->nb; ta.first_slice = 0; ta.trans_basis = 1;
+      ta.K = T3; ta.basis = c->basis32; ta.part = (double*)at(o_part); ta.gtrace = (double*)at(L.gtrace);
+      HIPCHK(launch_btraces(32, ta, s), "traces");
+    }
+  }
+  if (grad || grouped) {
+    GradArgs ga{};
+    ga.prec = 32; ga.gtrace = grad ? (const double*)at(L.gtrace) : nullptr;
+    ga.amps = b->amps; ga.item_amp_offset = (const int64_t*)at(L.amp_off); ga.items = items;
+    ga.n_items = (int)p.items.size(); ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
+    ga.n_ctrl = c->nc; ga.n_static = c->ns; ga.order = c->order; ga.hold_foh = c->hold == LMAG_FOH;
+    ga.nb = c->nb; ga.dt = b->dt; ga.inv_d2 = 1.0 / ((double)c->d * c->d);
+    ga.grad = grad ? grad_out : nullptr;
+    ga.group_first_item = grouped ? (const int32_t*)at(L.group_first) : nullptr;
+    ga.group_items = grouped ? (const int32_t*)at(L.group_items) : nullptr;
+    ga.n_groups = p.n_groups; ga.F_items = F_items; ga.F_out = grouped ? F_out : nullptr;
+    ga.group_global = grouped ? (const int32_t*)at(L.group_global) : nullptr;
+    StageTimer t(c, 7, s);
+    HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad");
+  }
+  c->plan_info[0] = Ns; c->plan_info[1] = Lc; c->plan_info[2] = C; c->plan_info[3] = 0;
+  c->plan_info[4] = (int64_t)L.total;
+  c->plan_recompute = false;
+  c->plan_waves = 1;
+  return LMAG_OK;
+}
+
+
 // Splits the batch into waves that fit the workspace budget (groups stay
 // whole). A wave whose stored per-slice tiles do not fit runs in recompute
 // mode; a unit that does not fit even then is LMAG_E_NOMEM.
@@ -498,6 +880,8 @@ lmag_status run_waves(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of
                       double* F_out, void* grad_out, void* S_out, hipStream_t s) {
   lmag_status st = validate_batch(c, b, target_of_item, fidelity ? n_targets : 1);
   if (st != LMAG_OK) return st;
+  if (c->n > 64)
+    return run_big(c, b, target_of_item, n_targets, grad, fidelity, U_target, F_out, grad_out, S_out, s);
   // units: whole groups (grouped calls) or single items, in order
   std::vector<std::vector<int>> units;
   if (b->n_groups > 0) {
@@ -653,8 +1037,12 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
   try {
     if (!s) return c->fail(LMAG_E_INVALID, "system descriptor is NULL");
     const int d = s->d;
-    if (d < 1 || d * d > 64) return c->fail(d * d > 64 && d <= 64 ? LMAG_E_UNSUPPORTED : LMAG_E_INVALID,
-                                            "d must satisfy 1 <= d and d*d <= 64");
+    if (d < 1 || d > 64) return c->fail(LMAG_E_INVALID, "d must satisfy 1 <= d <= 64");
+    const bool big = d * d > 64;
+    if (big && (d * d) % 64 != 0)
+      return c->fail(LMAG_E_UNSUPPORTED, "d*d must be <= 64 or a multiple of 64");
+    if (big && s->precision != LMAG_F32)
+      return c->fail(LMAG_E_UNSUPPORTED, "superoperators larger than 64 x 64 run in FP32 only");
     if (s->n_static < 0 || s->n_ctrl < 0 || s->n_jump < 0)
       return c->fail(LMAG_E_INVALID, "negative operator count");
     if (s->n_ctrl > 8 || s->n_static > 8) return c->fail(LMAG_E_UNSUPPORTED, "at most 8 controls and 8 static terms");
@@ -674,7 +1062,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     const int nc = s->n_ctrl, ns = s->n_static;
     int nb = nc + ns + 1;
     if (s->magnus_order == 2) nb += nc + nc * ns + nc * (nc - 1) / 2;
-    if (nb > 32) return c->fail(LMAG_E_UNSUPPORTED, "basis larger than 32 tiles");
+    if (nb > (d * d > 64 ? MAX_BIG_NB : 32)) return c->fail(LMAG_E_UNSUPPORTED, "basis too large");
 
     DeviceGuard g(c->device);
     hipError_t e = hipDeviceSynchronize();
@@ -684,14 +1072,21 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     c->basis64 = nullptr;
     c->basis32 = nullptr;
     c->has_sys = false;
-    const size_t tb = (size_t)TILE * 16;
+    const size_t nn = big ? (size_t)d * d * d * d : (size_t)TILE;   // elements per basis matrix
+    const size_t tb = nn * 16;
     double* ops = nullptr;
+    double* ldl = nullptr;
+    double* tmp = nullptr;
     const size_t nops = (size_t)(ns + nc + s->n_jump) * dd2;
     if (hipMalloc((void**)&c->basis64, nb * tb) != hipSuccess ||
-        hipMalloc(&c->basis32, nb * (size_t)TILE * 8) != hipSuccess ||
-        hipMalloc((void**)&ops, std::max<size_t>(8, nops * 8)) != hipSuccess) {
+        hipMalloc(&c->basis32, nb * nn * 8) != hipSuccess ||
+        hipMalloc((void**)&ops, std::max<size_t>(8, nops * 8)) != hipSuccess ||
+        hipMalloc((void**)&ldl, std::max<size_t>(8, (size_t)s->n_jump * dd2 * 8)) != hipSuccess ||
+        (big && hipMalloc((void**)&tmp, tb) != hipSuccess)) {
       (void)hipGetLastError();
       if (ops) (void)hipFree(ops);
+      if (ldl) (void)hipFree(ldl);
+      if (tmp) (void)hipFree(tmp);
       return c->fail(LMAG_E_NOMEM, "basis allocation failed");
     }
     std::vector<double> hops(std::max<size_t>(1, nops));
@@ -704,22 +1099,38 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     const double* Hs = ops;
     const double* Hc = ops + ns * dd2;
     const double* Lj = ops + (ns + nc) * dd2;
-    auto tile = [&](int j) { return c->basis64 + (size_t)j * TILE * 2; };
+    auto tile = [&](int j) { return c->basis64 + (size_t)j * nn * 2; };
+    auto lift = [&](const double* H, double* out) {
+      return big ? launch_blift(H, d, out, st) : launch_lift(H, d, out, st);
+    };
+    // [X, Y] = X Y - Y X: tile kernel for 64 x 64, two batched products otherwise
+    auto comm = [&](const double* X, const double* Y, double* out) -> hipError_t {
+      if (!big) return launch_commutator(X, Y, out, st);
+      BigGemmArgs g{};
+      g.n = d * d; g.batch = 1; g.A = X; g.B = Y; g.C = tmp; g.alpha = 1.0;
+      hipError_t e = launch_bgemm(64, g, st);
+      if (e != hipSuccess) return e;
+      g.A = Y; g.B = X; g.C = out; g.D = tmp; g.alpha = -1.0; g.beta = 1.0;
+      return launch_bgemm(64, g, st);
+    };
     // L_c | Z_i | D | [L_c, D] | [L_c, Z_i] | [L_p, L_q]
-    for (int cc = 0; cc < nc; ++cc) HIPCHK(launch_lift(Hc + cc * dd2, d, tile(cc), st), "lift");
-    for (int i = 0; i < ns; ++i) HIPCHK(launch_lift(Hs + i * dd2, d, tile(nc + i), st), "lift");
-    HIPCHK(launch_dissipator(Lj, s->n_jump, d, tile(nc + ns), st), "dissipator");
+    for (int cc = 0; cc < nc; ++cc) HIPCHK(lift(Hc + cc * dd2, tile(cc)), "lift");
+    for (int i = 0; i < ns; ++i) HIPCHK(lift(Hs + i * dd2, tile(nc + i)), "lift");
+    if (big) HIPCHK(launch_bdissipator(Lj, s->n_jump, d, ldl, tile(nc + ns), st), "dissipator");
+    else HIPCHK(launch_dissipator(Lj, s->n_jump, d, tile(nc + ns), st), "dissipator");
     if (s->magnus_order == 2) {
       int j = nc + ns + 1;
-      for (int cc = 0; cc < nc; ++cc) HIPCHK(launch_commutator(tile(cc), tile(nc + ns), tile(j++), st), "comm");
+      for (int cc = 0; cc < nc; ++cc) HIPCHK(comm(tile(cc), tile(nc + ns), tile(j++)), "comm");
       for (int cc = 0; cc < nc; ++cc)
-        for (int i = 0; i < ns; ++i) HIPCHK(launch_commutator(tile(cc), tile(nc + i), tile(j++), st), "comm");
+        for (int i = 0; i < ns; ++i) HIPCHK(comm(tile(cc), tile(nc + i), tile(j++)), "comm");
       for (int p = 0; p < nc; ++p)
-        for (int q = p + 1; q < nc; ++q) HIPCHK(launch_commutator(tile(p), tile(q), tile(j++), st), "comm");
+        for (int q = p + 1; q < nc; ++q) HIPCHK(comm(tile(p), tile(q), tile(j++)), "comm");
     }
-    HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * TILE * 2, st), "cast");
+    HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
     HIPCHK(hipDeviceSynchronize(), "set_system sync");
     (void)hipFree(ops);
+    (void)hipFree(ldl);
+    if (tmp) (void)hipFree(tmp);
     c->d = d; c->n = d * d; c->ns = ns; c->nc = nc; c->nj = s->n_jump;
     c->prec = s->precision; c->order = s->magnus_order; c->hold = s->hold; c->nb = nb;
     c->chunk = s->chunk_slices; c->ws_max = s->workspace_bytes_max;

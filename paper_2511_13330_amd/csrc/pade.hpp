@@ -1,0 +1,70 @@
+// Pade degree / scaling selection and Neumann level count (shared by the
+// 64 x 64 and block-tiled paths).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lmag {
+
+// theta_m (Higham 2005): largest ||A||_1 with backward error of r_m below the
+// unit roundoff. Single precision uses m = 3 only; double uses m in {3, 5, 7}.
+// For these (m, theta) the denominator q_m(A) is column diagonally dominant
+// (sum_j>=1 b_j theta^j < 1), so Gauss-Jordan needs no pivoting.
+constexpr double c_theta32_3 = 4.258730016922831e-1;
+constexpr double c_theta64_3 = 1.495585217958292e-2, c_theta64_5 = 2.539398330063230e-1,
+                 c_theta64_7 = 9.504178996162932e-1;
+
+template <typename T>
+__device__ __forceinline__ void choose_ms(double nrm, int& m, int& s) {
+  s = 0;
+  if constexpr (sizeof(T) == 4) {
+    m = 3;
+    const double th = c_theta32_3;
+    if (nrm > th) {
+      s = (int)ceil(log2(nrm / th));
+      while (s < 62 && ldexp(nrm, -s) > th) ++s;
+    }
+  } else {
+    if (nrm <= c_theta64_3) m = 3;
+    else if (nrm <= c_theta64_5) m = 5;
+    else {
+      m = 7;
+      const double th = c_theta64_7;
+      if (nrm > th) {
+        s = (int)ceil(log2(nrm / th));
+        while (s < 62 && ldexp(nrm, -s) > th) ++s;
+      }
+    }
+  }
+  if (!(nrm == nrm)) { m = 3; s = 0; }  // NaN input: propagate NaN, no scaling loop
+  if (s < 0) s = 0;
+  if (s > 62) s = 62;
+}
+
+// Levels K of the binary Neumann product Q^{-1} = (I+E)(I+E^2)...(I+E^{2^{K-1}}),
+// E = I - q_m(A), from the bound ||E||_1 <= e = sum_{j>=1} b_j ||A||_1^j: the
+// smallest K with e^{2^K} <= u (1 - e). 0 selects the Gauss-Jordan inverse.
+template <typename T>
+__device__ __forceinline__ int neumann_levels(double nA, const double* b, int m) {
+  double e = 0.0, p = 1.0;
+  for (int j = 1; j <= m; ++j) { p *= nA; e += b[j] * p; }
+  const double u = sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
+  const int kmax = sizeof(T) == 4 ? 4 : 5;
+  if (!(e < 0.5)) return 0;
+  double pe = e;   // e^(2^K)
+  for (int K = 1; K <= kmax; ++K) {
+    pe *= pe;
+    if (pe <= u * (1.0 - e)) return K;
+  }
+  return 0;
+}
+
+// Block-tiled path: single precision only (m = 3).
+template <typename T>
+__device__ __forceinline__ void big_choose_ms(double nrm, int& m, int& s) { choose_ms<T>(nrm, m, s); }
+
+template <typename T>
+__device__ __forceinline__ int big_neumann_levels(double nA, const double* b3) {
+  return neumann_levels<T>(nA, b3, 3);
+}
+
+}  // namespace lmag
