@@ -149,6 +149,53 @@ def robust_sweep(args):
             "F_mean_first_candidates": [float(x) for x in F[:4].cpu().numpy()]}
 
 
+def large_system(args):
+    """4 spins (superoperator 256 x 256, 8192 slices of 0.25 ns) or 6 spins
+    (4096 x 4096, 128 slices of 1 ns): one fwd+grad evaluation per step through
+    the block-tiled path."""
+    import torch
+    import synth
+    from paper_2511_13330_amd import spin_chain_system
+    cfg = synth.config3_four() if args.workload == "four_spin" else synth.config3_six()
+    t0 = time.perf_counter()
+    sysm = spin_chain_system(cfg["n_spins"], cfg["T1"], cfg["T2"], precision="f32",
+                             magnus_order=2, hold="foh", chunk_slices=args.chunk)
+    t_setup = time.perf_counter() - t0
+    N = cfg["n_slices"]
+    a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
+    b = np.asarray(cfg["B"])[None, :]
+    F, g = sysm.fidelity_and_grad(a, [N], cfg["dt"], cfg["U_target"], static_coef=b)  # warm-up
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    sysm.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        F, g = sysm.fidelity_and_grad(a, [N], cfg["dt"], cfg["U_target"], static_coef=b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    sysm.set_profiling(False)
+    prof = sysm.read_profile()
+    hist = sysm.selection_histogram()
+    n = 4 ** cfg["n_spins"]
+    Mf = 8.0 * n ** 3
+    flops = 0.0
+    for mi, m in enumerate((3, 5, 7)):
+        for s in range(hist.shape[1]):
+            if hist[mi, s]:
+                flops += hist[mi, s] * (3 * PI_M[m] + 3 * s + 19.0 / 3.0) * Mf
+    return {"metric": f"fwd+grad evaluations/s ({cfg['n_spins']} spins, {N} slices)",
+            "value": 1.0 / dt, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded config-3 draws)",
+            "config": {"workload": f"{cfg['n_spins']} spins, superoperator {n}x{n}, {N} slices of "
+                                   f"{cfg['dt'] * 1e3:g} ns, FOH 2nd order, FP32 fwd+grad",
+                       "plan": sysm.last_plan()},
+            "seconds_per_eval": dt, "seconds_set_system": t_setup,
+            "tflops_algorithmic": flops / dt / 1e12,
+            "frac_fp32_mfma": flops / dt / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+            "stage_ms": {k: v[0] / steps for k, v in prof.items()},
+            "F": float(F.item())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,7 +209,8 @@ def main():
                     help="tune chunk length and inverse variant before the timed steps")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES (counter calibration)")
-    ap.add_argument("--workload", default="pulse", choices=["pulse", "proposal", "robust"],
+    ap.add_argument("--workload", default="pulse",
+                    choices=["pulse", "proposal", "robust", "four_spin", "six_spin"],
                     help="pulse: the headline metric (default); proposal: learned proposal + "
                          "refine vs cold start; robust: candidates x noise samples, uneven N")
     args = ap.parse_args()
@@ -194,6 +242,9 @@ def main():
         return
     if args.workload == "robust":
         print(json.dumps(robust_sweep(args)), flush=True)
+        return
+    if args.workload in ("four_spin", "six_spin"):
+        print(json.dumps(large_system(args)), flush=True)
         return
     dev = torch.device("cuda", 0)
     if args.copy_calibration > 0:

@@ -70,3 +70,15 @@ def test_four_spin_full_size_invariants():
     # covered by the small cases; here the sampled gradient must be finite and
     # the propagator a contraction in the trace norm sense
     assert np.linalg.norm(U, 2) < 1.5
+
+
+def test_five_spin_propagator_and_fidelity():
+    # superoperator 1024 x 1024 (16 x 16 tiles per side), two slices
+    cfg = synth.small_case(73, n_spins=5, n_slices=2, dt=2.5e-4)
+    amps = rounded(cfg["amps"], "f32")
+    sysm, U, F, _ = run(cfg, amps, want_grad=False)
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    assert rel(U, U_ref) < 2e-5
+    F_ref, _ = oracle.fidelity(U_ref, cfg["U_target"])
+    assert abs(F - F_ref) < 1e-6
