@@ -317,7 +317,7 @@ def main():
                                f"batch of {B} pulses per step",
                    "batch_pulses": B, "n_slices": 4096, "superop_dim": 64,
                    "chunk_slices": plan["chunk_slices"], "grid": plan["grid"],
-                   "inverse": "autotuned" if tuned else "auto (MFMA Neumann where bounded)",
+                   "inverse": "autotuned" if tuned else "auto (power series, MFMA Neumann or Gauss-Jordan per slice bound)",
                    "autotune": list(tuned) if tuned else None},
         "roofline": roofline,
         "whole_step_tflops": total_flops / (elapsed / args.steps) / 1e12,

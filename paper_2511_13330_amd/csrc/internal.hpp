@@ -47,7 +47,8 @@ struct SliceArgs {
   const void* env;          // [n_chunks][64][64] chunk environments W_c (backward input)
   double* gtrace;           // [n_slices_total][nb] Re Tr(K_n B_j) (backward output)
   int8_t* ms;               // [n_slices_total][2] Pade degree and scaling exponent
-  int8_t* nlev;             // [n_slices_total] Neumann levels of the inverse (0 = Gauss-Jordan)
+  int8_t* nlev;             // [n_slices_total] inverse variant code (see inverse_code)
+  int inv_mode;             // 0 automatic; 2 no power series (Neumann or Gauss-Jordan)
   void* gscratch;           // per-workgroup global scratch slots (double precision)
   void* omega;              // [n_slices_total][64][64]: Omega_n / 2^s, then K_n^T (backward)
   long long* clk;           // [32] per-phase cycle counters of workgroup 0, or null

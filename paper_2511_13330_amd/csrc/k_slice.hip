@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
         ms_sh[0] = m; ms_sh[1] = sc;
         a.ms[2 * (size_t)n] = (int8_t)m;
         a.ms[2 * (size_t)n + 1] = (int8_t)sc;
-        if (a.nlev) a.nlev[n] = (int8_t)neumann_levels<T>(ldexp(v, -sc), pade_b<T>(a.pade, m), m);
+        if (a.nlev)
+          a.nlev[n] = (int8_t)inverse_code<T>(ldexp(v, -sc), pade_b<T>(a.pade, m), m, a.inv_mode != 2);
       }
     }
     __syncthreads();
@@ -241,7 +242,24 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   }
   ck.mark(2);
   const int K = a.nlev ? a.nlev[n] : 0;
-  if (K > 0) {
+  if (sizeof(T) == 4 && K >= 16) {
+    // Q^{-1} = sum_{k<=5} c_k A^k = even(A^2) + A odd(A^2), the power series of
+    // 1/q_3 (its tail is below the unit roundoff by the selection rule)
+    double c[8];
+    inv_series(b, 3, c, 8);
+    __syncthreads();
+    put<T, false>(A2, slot<T, 1>(sh, gs));
+    __syncthreads();
+    RT<T> A4;
+    rt_zero(A4);
+    mm(A4, slot<T, 1>(sh, gs), A2);
+    RT<T> odd;
+    rt_poly1(odd, A2, (T)c[3], (T)c[1]);
+    rt_axpy(odd, (T)c[5], A4);
+    rt_poly1(V, A2, (T)c[2], (T)c[0]);
+    rt_axpy(V, (T)c[4], A4);
+    mm(V, slot<T, 0>(sh, gs), odd);   // V = even + A odd
+  } else if (K > 0 && K < 16) {
     // binary Neumann product on MFMA: X = (I + E)(I + E^2)...; E = I - Q
     RT<T> F;
 #pragma unroll

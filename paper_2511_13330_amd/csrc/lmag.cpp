@@ -403,6 +403,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     if (inv == 0 && c->chunk <= 0)
       if (const auto* t = tuned_for(c, p.total_slices)) inv = t->second;
     if (inv == 1) sa.nlev = nullptr;   // Gauss-Jordan for every slice
+    sa.inv_mode = inv;
   }
   sa.gscratch = c->prec == 64 ? at(L.gscratch) : nullptr; sa.pade = c->pade;
   sa.omega = at(L.omega); sa.clk = c->clk_on ? c->clk_dev : nullptr;
@@ -1244,7 +1245,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     (void)hipEventCreate(&e1);
     double best = 1e300;
     int bestC = chunks[0], bestInv = 0;
-    for (int inv : {0, 1}) {
+    for (int inv : {0, 1, 2}) {
       for (int C : chunks) {
         c->chunk = C;
         c->inv_variant = inv;
@@ -1308,7 +1309,7 @@ lmag_status lmag_load_tuning(lmag_ctx* c, const char* path) {
     char key[128];
     int C = 0, inv = 0;
     if (std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"inverse\": %d", key, &C, &inv) == 3 &&
-        C > 0 && (inv == 0 || inv == 1)) {
+        C > 0 && inv >= 0 && inv <= 2) {
       bool found = false;
       for (auto& t : c->tuned)
         if (t.first == key) { t.second = {C, inv}; found = true; }

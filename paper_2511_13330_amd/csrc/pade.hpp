@@ -58,6 +58,40 @@ __device__ __forceinline__ int neumann_levels(double nA, const double* b, int m)
   return 0;
 }
 
+// Power series of 1 / q_m(x), q_m(x) = sum_j (-1)^j b_j x^j (b_0 = 1):
+// c_0 = 1, c_k = sum_{j=1}^{min(k,m)} (-1)^{j+1} b_j c_{k-j}.
+__device__ __forceinline__ void inv_series(const double* b, int m, double* c, int K) {
+  c[0] = 1.0;
+  for (int k = 1; k < K; ++k) {
+    double v = 0.0;
+    for (int j = 1; j <= m && j <= k; ++j) v += ((j & 1) ? b[j] : -b[j]) * c[k - j];
+    c[k] = v;
+  }
+}
+
+// Inverse of the Pade denominator, per slice (code stored with the slice):
+//   21      power series of 1/q_3 truncated at degree 5 (single precision,
+//           m = 3), when sum_{k > 5} |c_k| ||A||_1^k <= u / 2;
+//   1..5    binary Neumann product with that many levels;
+//   0       Gauss-Jordan.
+template <typename T>
+__device__ __forceinline__ int inverse_code(double nA, const double* b, int m, int allow_series) {
+  if (sizeof(T) == 4 && m == 3 && allow_series && nA == nA) {
+    double c[48];
+    inv_series(b, 3, c, 48);
+    const double u = 5.9604644775390625e-8;
+    for (int D = 5; D <= 5; D += 2) {
+      double tail = 0.0, p = 1.0;
+      for (int k = 1; k < 48; ++k) {
+        p *= nA;
+        if (k > D) tail += fabs(c[k]) * p;
+      }
+      if (tail <= 0.5 * u) return 16 + D;
+    }
+  }
+  return neumann_levels<T>(nA, b, m);
+}
+
 // Block-tiled path: single precision only (m = 3).
 template <typename T>
 __device__ __forceinline__ void big_choose_ms(double nrm, int& m, int& s) { choose_ms<T>(nrm, m, s); }

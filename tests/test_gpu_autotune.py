@@ -34,3 +34,23 @@ def test_autotune_choice_is_used_and_keeps_parity(tmp_path, monkeypatch):
     fresh.load_tuning(cache)
     fresh.fidelity_and_grad(a, [256], cfg["dt"], cfg["U_target"], static_coef=b)
     assert fresh.last_plan()["chunk_slices"] == C
+
+
+@pytest.mark.parametrize("inverse", [0, 1, 2])
+def test_each_inverse_variant_keeps_parity(tmp_path, inverse):
+    # 0: power series / Neumann / Gauss-Jordan chosen per slice; 1: Gauss-Jordan;
+    # 2: Neumann or Gauss-Jordan. Forced through a tuning line for this size.
+    cfg = synth.small_case(62, n_slices=48)
+    amps = rounded(cfg["amps"], "f32")
+    total = 48
+    key = f"p32_o2_d8_s{int(np.floor(np.log2(total)))}"
+    f = tmp_path / "t.jsonl"
+    f.write_text(json.dumps({"key": key, "chunk": 7, "inverse": inverse, "ms": 1.0}) + "\n")
+    sysm = lib_system(cfg)
+    sysm.load_tuning(f)
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    F, g = sysm.fidelity_and_grad(a, [total], cfg["dt"], cfg["U_target"],
+                                  static_coef=np.asarray(cfg["B"])[None, :])
+    assert sysm.last_plan()["chunk_slices"] == 7
+    Fr, gr = oracle.grad_adjoint(oracle_system(cfg), amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    assert abs(F.item() - Fr) < 1e-7 and rel(g.cpu().numpy(), gr) < 1e-4
