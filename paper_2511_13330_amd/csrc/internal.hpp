@@ -192,7 +192,8 @@ struct BigGemmArgs {
   const void* B; const int32_t* Bi;
   const void* C; const int32_t* Ci;      // output
   const void* D; const int32_t* Di;      // epilogue addend (may alias C)
-  double alpha, beta, gamma;
+  const void* D2; const int32_t* D2i;    // second addend (may be null)
+  double alpha, beta, gamma, beta2;
   int transA, transB;
   const int8_t* pred; int pred_stride; int pred_thresh;   // active if pred[i*stride] > thresh
 };

@@ -215,16 +215,21 @@ __device__ __forceinline__ void tile_copy(cpx<T>* dst, const cpx<T>* src) {
   for (int i = threadIdx.x; i < TILE; i += WG) dst[i] = src[i];
 }
 
-// out = X Y for global tiles; X staged through LDS, Y as a register tile.
+// Chunk totals, prefixes and suffixes are stored as M - I (with short chunks
+// they are near the identity, and an FP32 product of two such matrices would
+// accumulate small terms onto O(1) diagonal entries). For global tiles X, Y
+// in that form, out = (I + X)(I + Y) - I = X + Y + X Y; X is staged through
+// LDS, Y is a register tile.
 template <typename T>
-__device__ void tile_mul(ScanShared<T>& sh, const cpx<T>* X, const cpx<T>* Y, cpx<T>* out) {
+__device__ void tile_mul_delta(ScanShared<T>& sh, const cpx<T>* X, const cpx<T>* Y, cpx<T>* out) {
   RT<T> Xr, Yr, acc;
   rt_load<T, false>(Xr, X, 64);
   rt_load<T, false>(Yr, Y, 64);
   __syncthreads();
   rt_store<T, false>(Xr, sh.slot, PITCH);
   __syncthreads();
-  rt_zero(acc);
+  rt_copy(acc, Yr);
+  rt_axpy(acc, T(1), Xr);
   gemm_acc<T, false, PITCH>(acc, sh.slot, Yr);
   rt_store<T, false>(acc, out, 64);
 }
@@ -244,10 +249,10 @@ template <typename T> __global__ void __launch_bounds__(WG) k_scan_level(ScanArg
   const cpx<T>* self = in + (size_t)cidx * TILE;
   cpx<T>* dst = out + (size_t)cidx * TILE;
   if (!suffix) {
-    if (lc >= st) tile_mul<T>(sh, self, in + (size_t)(cidx - st) * TILE, dst);
+    if (lc >= st) tile_mul_delta<T>(sh, self, in + (size_t)(cidx - st) * TILE, dst);
     else tile_copy<T>(dst, self);
   } else {
-    if (lc + st < Lc) tile_mul<T>(sh, in + (size_t)(cidx + st) * TILE, self, dst);
+    if (lc + st < Lc) tile_mul_delta<T>(sh, in + (size_t)(cidx + st) * TILE, self, dst);
     else tile_copy<T>(dst, self);
   }
 }
@@ -255,6 +260,8 @@ template <typename T> __global__ void __launch_bounds__(WG) k_scan_level(ScanArg
 
 // W_c = Pre_excl(c) S_T^dag Suf_excl(c); F = Re Tr(S_T^dag U) / d^2 with U the
 // item's total, accumulated in FP64 (computed by the item's first chunk).
+// Prefixes and suffixes arrive as M - I; the identity is added exactly (in the
+// FP64 trace, and as the initial value of the products).
 template <typename T> __global__ void __launch_bounds__(WG) k_env(EnvArgs a) {
   __shared__ ScanShared<T> sh;
   const int cidx = blockIdx.x;
@@ -274,6 +281,7 @@ template <typename T> __global__ void __launch_bounds__(WG) k_env(EnvArgs a) {
       const cpx<T> y = U[c * 64 + r];
       re += x.re * (double)y.re - x.im * (double)y.im;
       im += x.re * (double)y.im + x.im * (double)y.re;
+      if (r == c) { re += x.re; im += x.im; }
     }
     re = wg_sum(re, sh.red);
     im = wg_sum(im, sh.red);
@@ -296,7 +304,7 @@ template <typename T> __global__ void __launch_bounds__(WG) k_env(EnvArgs a) {
     __syncthreads();
     rt_store<T, false>(Sr, sh.slot, PITCH);
     __syncthreads();
-    rt_zero(X);
+    rt_copy(X, Sr);   // S_T^dag (I + Y)
     gemm_acc<T, false, PITCH>(X, sh.slot, Y);
   } else {
     rt_load<T, false>(X, st, 64);
@@ -308,7 +316,7 @@ template <typename T> __global__ void __launch_bounds__(WG) k_env(EnvArgs a) {
     rt_store<T, false>(Pr, sh.slot, PITCH);
     __syncthreads();
     RT<T> W;
-    rt_zero(W);
+    rt_copy(W, X);    // (I + Pr) X
     gemm_acc<T, false, PITCH>(W, sh.slot, X);
     rt_store<T, false>(W, out, 64);
   } else {
@@ -323,7 +331,7 @@ hipError_t launch_env(const EnvArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// S_out[item] = top-left n x n block of the item's total product
+// S_out[item] = top-left n x n block of the item's total product (stored as U - I)
 template <typename T> __global__ void k_extract(ExtractArgs a) {
   const int itn = blockIdx.y;
   const Item it = a.items[itn];
@@ -331,7 +339,9 @@ template <typename T> __global__ void k_extract(ExtractArgs a) {
   cpx<T>* out = (cpx<T>*)a.out + (size_t)it.src * a.n * a.n;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n * a.n; i += gridDim.x * blockDim.x) {
     const int r = i / a.n, c = i % a.n;
-    out[i] = U[r * 64 + c];
+    cpx<T> v = U[r * 64 + c];
+    if (r == c) v.re += T(1);
+    out[i] = v;
   }
 }
 

@@ -25,7 +25,7 @@ __device__ __forceinline__ const cpx<T>* mat(const void* base, const int32_t* id
   return reinterpret_cast<const cpx<T>*>(base) + (size_t)(idx ? idx[b] : b) * nn;
 }
 
-// C_b = alpha * op(A_b) op(B_b) + beta * D_b + gamma * I, for every batch entry
+// C_b = alpha * op(A_b) op(B_b) + beta * D_b + beta2 * D2_b + gamma * I, for every batch entry
 // b with (pred == null or pred[b] != 0); other entries copy D_b (or A_b when
 // D is null) into C_b. op = transpose when the flag is set.
 template <typename T, bool TA, bool TB>
@@ -67,6 +67,11 @@ __global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
     RT<T> Dt;
     rt_load<T, false>(Dt, D + (size_t)ti * 64 * g.n + tj * 64, g.n);
     rt_axpy(acc, (T)g.beta, Dt);
+  }
+  if (g.D2 && g.beta2 != 0.0) {
+    RT<T> Dt;
+    rt_load<T, false>(Dt, mat<T>(g.D2, g.D2i, b, nn) + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    rt_axpy(acc, (T)g.beta2, Dt);
   }
   if (g.gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.gamma);
   rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
@@ -282,6 +287,7 @@ __global__ void k_bfidelity(BigFidArgs g) {
     const cpx<T> y = U[c * g.n + a];
     re += x.re * (double)y.re - x.im * (double)y.im;
     im += x.re * (double)y.im + x.im * (double)y.re;
+    if (a == c) { re += x.re; im += x.im; }   // U is stored as U - I
   }
   red[0][threadIdx.x] = re;
   red[1][threadIdx.x] = im;

@@ -192,14 +192,19 @@ __global__ void __launch_bounds__(WG) k_traces(SliceArgs a, int n_total) {
   }
 }
 
-// One slice forward; returns S_n in R. Stores go to the workspace when requested.
+// One slice forward; returns D_n = S_n - I in R. Every matrix near the identity
+// is carried as I + X with only X inside the MFMA accumulators: accumulating
+// small products onto O(1) diagonal entries in FP32 biases them by a fraction of
+// an ulp, and over a chain of thousands of slices that bias adds up linearly.
+// Stores go to the workspace when requested: A^2, Q^{-1} - I and r_m(A) - I
+// (before the squarings).
 template <typename T>
 __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
                           cpx<T>* ws, Clock& ck) {
   RT<T> A;
   rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)n), 64);
   const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
-  const double* b = pade_b<T>(a.pade, m);
+  const double* b = pade_b<T>(a.pade, m);   // b[0] = 1
   ck.mark(0);
   const bool st = ws != nullptr;
 
@@ -211,9 +216,9 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   mm(A2, slot<T, 0>(sh, gs), A);
   ck.mark(1);
   if (st) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
-  RT<T> W, V;
+  RT<T> W, V;   // V holds the even part minus I
   rt_poly1(W, A2, (T)b[3], (T)b[1]);
-  rt_poly1(V, A2, (T)b[2], (T)b[0]);
+  rt_poly1(V, A2, (T)b[2], T(0));
   if (sizeof(T) == 8 && m >= 5) {   // single precision uses m = 3 only
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
@@ -233,7 +238,7 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   RT<T> U;
   rt_zero(U);
   mm(U, slot<T, 0>(sh, gs), W);
-  // P = V + U (in U), Q = V - U (in V)
+  // P = I + X_P with X_P = (V - I) + U (in U); Q = I + E_Q with E_Q = (V - I) - U (in V)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const auto vr = V.re[q], vi = V.im[q];
@@ -241,10 +246,11 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     U.re[q] = vr + U.re[q]; U.im[q] = vi + U.im[q];
   }
   ck.mark(2);
+  // X_Q = Q^{-1} - I into V
   const int K = a.nlev ? a.nlev[n] : 0;
   if (sizeof(T) == 4 && K >= 16) {
     // Q^{-1} = sum_{k<=5} c_k A^k = even(A^2) + A odd(A^2), the power series of
-    // 1/q_3 (its tail is below the unit roundoff by the selection rule)
+    // 1/q_3 (its tail is below the unit roundoff by the selection rule); c_0 = 1
     double c[8];
     inv_series(b, 3, c, 8);
     __syncthreads();
@@ -256,17 +262,16 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     RT<T> odd;
     rt_poly1(odd, A2, (T)c[3], (T)c[1]);
     rt_axpy(odd, (T)c[5], A4);
-    rt_poly1(V, A2, (T)c[2], (T)c[0]);
+    rt_poly1(V, A2, (T)c[2], T(0));
     rt_axpy(V, (T)c[4], A4);
-    mm(V, slot<T, 0>(sh, gs), odd);   // V = even + A odd
+    mm(V, slot<T, 0>(sh, gs), odd);   // X_Q = even - I + A odd
   } else if (K > 0 && K < 16) {
-    // binary Neumann product on MFMA: X = (I + E)(I + E^2)...; E = I - Q
+    // binary Neumann product on MFMA: Q^{-1} = (I + F)(I + F^2)(I + F^4)...,
+    // F = I - Q = -E_Q; with X = Q^{-1} - I each level is X += F2 + F2 X
     RT<T> F;
 #pragma unroll
     for (int q = 0; q < 4; ++q) { F.re[q] = -V.re[q]; F.im[q] = -V.im[q]; }
-    rt_add_diag(F, T(1));
     rt_copy(V, F);
-    rt_add_diag(V, T(1));
     for (int k = 1; k < K; ++k) {
       __syncthreads();
       put<T, false>(F, slot<T, 2>(sh, gs));
@@ -278,32 +283,102 @@ __device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
       put<T, false>(F2, slot<T, 2>(sh, gs));
       __syncthreads();
       RT<T> T1;
-      rt_zero(T1);
+      rt_copy(T1, F2);
       mm(T1, slot<T, 2>(sh, gs), V);
       rt_axpy(V, T(1), T1);
       rt_copy(F, F2);
     }
   } else {
+    rt_add_diag(V, T(1));
     rt_gj_inverse(V, sh.colbuf);
+    rt_add_diag(V, T(-1));
   }
   ck.mark(3);
   if (st) rt_store<T, false>(V, ws + WS_QINV * TILE, 64);
+  // D = r_m(A) - I = X_Q + X_P + X_Q X_P
   put<T, false>(V, slot<T, 1>(sh, gs));
   __syncthreads();
-  rt_zero(R);
+  rt_copy(R, U);
+  rt_axpy(R, T(1), V);
   mm(R, slot<T, 1>(sh, gs), U);
   if (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
   ck.mark(4);
+  // squarings: (I + D)^2 = I + 2 D + D^2
   for (int k = 0; k < s; ++k) {
     __syncthreads();
     put<T, false>(R, slot<T, 2>(sh, gs));
     __syncthreads();
     RT<T> R2;
-    rt_zero(R2);
+    rt_copy(R2, R);
+    rt_scale(R2, T(2));
     mm(R2, slot<T, 2>(sh, gs), R);
     rt_copy(R, R2);
   }
   ck.mark(5);
+}
+
+// The chunk's running product P_loc is accumulated in FP64 registers (same
+// layout as a register tile); the MFMA sees its FP32 rounding. With the slice in
+// the form I + D the step is P <- P + D P, so the O(1) part of P is never
+// rounded to FP32 along the chain.
+struct RTW {
+  double re[4][4], im[4][4];
+};
+
+// identity in the register-tile layout of T
+template <typename T>
+__device__ __forceinline__ void rtw_identity(RTW& P) {
+  const Lane L;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      P.re[q][r] = (L.template row<T>(q, r) == L.col) ? 1.0 : 0.0;
+      P.im[q][r] = 0.0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void rtw_narrow(RT<T>& X, const RTW& P) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { X.re[q][r] = (T)P.re[q][r]; X.im[q][r] = (T)P.im[q][r]; }
+}
+
+// P <- P + D P with D in LDS (or global scratch) at slot Dm
+template <typename T>
+__device__ __forceinline__ void chain_step(RTW& P, const cpx<T>* Dm) {
+  RT<T> Pf, Pn;
+  rtw_narrow(Pf, P);
+  rt_zero(Pn);
+  mm(Pn, Dm, Pf);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { P.re[q][r] += (double)Pn.re[q][r]; P.im[q][r] += (double)Pn.im[q][r]; }
+}
+
+template <typename T>
+__device__ __forceinline__ void rtw_store(const RTW& P, cpx<T>* M) {
+  RT<T> X;
+  rtw_narrow(X, P);
+  rt_store<T, false>(X, M, 64);
+}
+
+// stores P - I (the form of chunk totals); the identity is removed in FP64
+template <typename T>
+__device__ __forceinline__ void rtw_store_delta(const RTW& P, cpx<T>* M) {
+  const Lane L;
+  RT<T> X;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      X.re[q][r] = (T)(P.re[q][r] - ((L.template row<T>(q, r) == L.col) ? 1.0 : 0.0));
+      X.im[q][r] = (T)P.im[q][r];
+    }
+  rt_store<T, false>(X, M, 64);
 }
 
 template <typename T>
@@ -324,24 +399,21 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
     const Chunk ch = a.chunks[idx];
-    RT<T> P;
-    rt_identity(P);
+    RTW P;
+    rtw_identity<T>(P);
     for (int k = 0; k < ch.count; ++k) {
       const int n = ch.first + k;
       cpx<T>* ws = (a.store && a.ws_tiles) ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
-      if (ws) rt_store<T, false>(P, ws + WS_PLOC * TILE, 64);
-      RT<T> S;
-      fwd_slice<T>(S, sh, gs, a, n, ws, ck);
+      if (ws) rtw_store<T>(P, ws + WS_PLOC * TILE);
+      RT<T> D;
+      fwd_slice<T>(D, sh, gs, a, n, ws, ck);
       __syncthreads();
-      put<T, false>(S, slot<T, 3>(sh, gs));
+      put<T, false>(D, slot<T, 3>(sh, gs));
       __syncthreads();
-      RT<T> Pn;
-      rt_zero(Pn);
-      mm(Pn, slot<T, 3>(sh, gs), P);
-      rt_copy(P, Pn);
+      chain_step<T>(P, slot<T, 3>(sh, gs));
       ck.mark(6);
     }
-    rt_store<T, false>(P, tile_at<T>(a.totals, (size_t)ch.chunk), 64);
+    rtw_store_delta<T>(P, tile_at<T>(a.totals, (size_t)ch.chunk));
   }
   ck.flush(a.clk);
 }
@@ -428,17 +500,19 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     LU.re[q] = vr + LU.re[q]; LU.im[q] = vi + LU.im[q];
   }
   RT<T> R;
-  rt_load<T, true>(R, ws + WS_S * TILE, 64);   // r_m(A)^T
+  rt_load<T, true>(R, ws + WS_S * TILE, 64);   // D^T = (r_m(A) - I)^T
+  // X = L_P - L_Q r_m(A) = (L_P - L_Q) - L_Q D
+#pragma unroll
+  for (int q = 0; q < 4; ++q) { LU.re[q] -= LW.re[q]; LU.im[q] -= LW.im[q]; }
   __syncthreads();
   put<T, false>(LW, slot<T, 1>(sh, gs));
   {
-    RT<T> Qi;
+    RT<T> Qi;   // (Q^{-1} - I)^T
     rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
     put<T, false>(Qi, slot<T, 2>(sh, gs));
   }
   __syncthreads();
   ck.mark(6);
-  // X = L_P - L_Q R ; L = Q^{-1} X
   {
     RT<T> Tm;
     rt_zero(Tm);
@@ -446,19 +520,23 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
 #pragma unroll
     for (int q = 0; q < 4; ++q) { LU.re[q] -= Tm.re[q]; LU.im[q] -= Tm.im[q]; }
   }
+  // L = Q^{-1} X = X + (Q^{-1} - I) X
   RT<T> K;
-  rt_zero(K);
+  rt_copy(K, LU);
   mm(K, slot<T, 2>(sh, gs), LU);
   for (int k = 0; k < s; ++k) {
     __syncthreads();
     put<T, false>(R, slot<T, 0>(sh, gs));
     put<T, false>(K, slot<T, 1>(sh, gs));
     __syncthreads();
+    // with R = I + D: K <- R K + K R = 2 K + D K + K D ; D <- 2 D + D D
     RT<T> Kn, Rn;
-    rt_zero(Kn);
+    rt_copy(Kn, K);
+    rt_scale(Kn, T(2));
     mm(Kn, slot<T, 0>(sh, gs), K);
     mm(Kn, slot<T, 1>(sh, gs), R);
-    rt_zero(Rn);
+    rt_copy(Rn, R);
+    rt_scale(Rn, T(2));
     mm(Rn, slot<T, 0>(sh, gs), R);
     rt_copy(K, Kn);
     rt_copy(R, Rn);
@@ -467,18 +545,21 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   // K_n^T replaces A_n; the traces Re Tr(K_n B_j) are taken by k_traces
   rt_store<T, false>(K, tile_at<T>(a.omega, (size_t)n), 64);
   ck.mark(8);
-  // Z_{n-1}^T = S_n^T Z_n^T
+  // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T
   __syncthreads();
   put<T, false>(R, slot<T, 0>(sh, gs));
   __syncthreads();
   RT<T> Zn;
-  rt_zero(Zn);
+  rt_copy(Zn, Z);
   mm(Zn, slot<T, 0>(sh, gs), Z);
   rt_copy(Z, Zn);
   ck.mark(9);
 }
 
-template <typename T>
+// RC: recompute mode (the chunk's forward is re-run into per-workgroup scratch);
+// a separate instantiation so that the stored-workspace kernel carries none of
+// its register pressure.
+template <typename T, bool RC>
 __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
   __shared__ Shared<T> sh;
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
@@ -488,25 +569,22 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
     const Chunk ch = a.chunks[idx];
-    cpx<T>* rs = a.recompute ? tile_at<T>(a.rscratch, (size_t)blockIdx.x * a.max_chunk * WS_TILES)
-                             : nullptr;
-    if (rs) {
+    cpx<T>* rs = RC ? tile_at<T>(a.rscratch, (size_t)blockIdx.x * a.max_chunk * WS_TILES)
+                    : nullptr;
+    if (RC) {
       // recompute the chunk's forward into this workgroup's scratch tiles
-      RT<T> P;
-      rt_identity(P);
+      RTW P;
+      rtw_identity<T>(P);
       for (int k = 0; k < ch.count; ++k) {
         cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
-        rt_store<T, false>(P, ws + WS_PLOC * TILE, 64);
-        RT<T> S;
-        fwd_slice<T>(S, sh, gs, a, ch.first + k, ws, ck);
+        rtw_store<T>(P, ws + WS_PLOC * TILE);
+        RT<T> D;
+        fwd_slice<T>(D, sh, gs, a, ch.first + k, ws, ck);
         if (k + 1 < ch.count) {
           __syncthreads();
-          put<T, false>(S, slot<T, 3>(sh, gs));
+          put<T, false>(D, slot<T, 3>(sh, gs));
           __syncthreads();
-          RT<T> Pn;
-          rt_zero(Pn);
-          mm(Pn, slot<T, 3>(sh, gs), P);
-          rt_copy(P, Pn);
+          chain_step<T>(P, slot<T, 3>(sh, gs));
         }
       }
     }
@@ -546,8 +624,13 @@ hipError_t launch_traces(int prec, const SliceArgs& a, int n_total, hipStream_t 
 }
 
 hipError_t launch_slice_backward(int prec, const SliceArgs& a, int grid, hipStream_t s) {
-  if (prec == 32) hipLaunchKernelGGL(k_backward<float>, dim3(grid), dim3(WG), 0, s, a);
-  else hipLaunchKernelGGL(k_backward<double>, dim3(grid), dim3(WG), 0, s, a);
+  if (prec == 32) {
+    if (a.recompute) hipLaunchKernelGGL((k_backward<float, true>), dim3(grid), dim3(WG), 0, s, a);
+    else hipLaunchKernelGGL((k_backward<float, false>), dim3(grid), dim3(WG), 0, s, a);
+  } else {
+    if (a.recompute) hipLaunchKernelGGL((k_backward<double, true>), dim3(grid), dim3(WG), 0, s, a);
+    else hipLaunchKernelGGL((k_backward<double, false>), dim3(grid), dim3(WG), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -585,6 +668,7 @@ __global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, Sl
   Clock ck(nullptr, sh.clk);
   RT<T> R;
   fwd_slice<T>(R, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
+  rt_add_diag(R, T(1));
   rt_store<T, false>(R, C, 64);
 }
 

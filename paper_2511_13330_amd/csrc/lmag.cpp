@@ -649,6 +649,20 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     g.pred = pred; g.pred_stride = 2; g.pred_thresh = thresh;
     return launch_bgemm(32, g, s);
   };
+  // C = alpha A B + beta D + beta2 D2 with index maps (null: the batch index)
+  auto gemmx = [&](int batch, const void* Ap, const int32_t* Ai, const void* Bp, const int32_t* Bi,
+                   const void* Cp, const int32_t* Ci, double alpha, const void* Dp, const int32_t* Di,
+                   double beta, const void* D2p, const int32_t* D2i, double beta2) {
+    BigGemmArgs g{};
+    g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
+    g.D = Dp; g.Di = Di; g.D2 = D2p; g.D2i = D2i;
+    g.alpha = alpha; g.beta = beta; g.beta2 = beta2; g.pred_stride = 2;
+    return launch_bgemm(32, g, s);
+  };
+  auto gemm2 = [&](int batch, const void* Ap, const void* Bp, const void* Cp, double alpha,
+                   const void* Dp, double beta, const void* D2p, double beta2) {
+    return gemmx(batch, Ap, nullptr, Bp, nullptr, Cp, nullptr, alpha, Dp, nullptr, beta, D2p, nullptr, beta2);
+  };
   auto axpby = [&](int batch, const void* X, const int32_t* Xi, void* Y, const int32_t* Yi, double a,
                    const void* Z = nullptr, const int32_t* Zi = nullptr, double cc = 0.0, double d = 0.0,
                    const int8_t* ms = nullptr) {
@@ -696,47 +710,51 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     HIPCHK(hipMemcpy(at(o_sq), sq_list.data(), sq_list.size() * 4, hipMemcpyHostToDevice), "squaring lists");
   const int8_t* ms_dev = (const int8_t*)at(L.ms);
 
-  // ---- forward: Pade 3 with the Neumann inverse, squarings
+  // ---- forward: Pade 3 with the Neumann inverse, squarings. Matrices near the
+  // identity are carried as I + X with only X inside the products (see the
+  // 64 x 64 slice kernel): P = I + X_P, Q = I - E, Q^{-1} = I + X_Q, r = I + D.
   {
     StageTimer t(c, 2, s);
     HIPCHK(gemm(Ns, A, nullptr, A, nullptr, A2, nullptr, 1.0), "A2");
     HIPCHK(axpby(Ns, A2, nullptr, T1, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");
-    HIPCHK(gemm(Ns, A, nullptr, T1, nullptr, T2, nullptr, 1.0), "U");            // T2 = U
-    HIPCHK(axpby(Ns, A2, nullptr, Qi, nullptr, b3[2], nullptr, nullptr, 0.0, b3[0]), "V");   // Qi = V
-    HIPCHK(axpby(Ns, Qi, nullptr, T1, nullptr, 1.0, T2, nullptr, 1.0), "P");      // T1 = P = V + U
-    HIPCHK(axpby(Ns, Qi, nullptr, S, nullptr, -1.0, T2, nullptr, 1.0, 1.0), "E");  // S = E = I - V + U
-    HIPCHK(axpby(Ns, S, nullptr, T2, nullptr, 1.0, nullptr, nullptr, 0.0, 1.0), "X");  // T2 = X = I + E
+    HIPCHK(gemm(Ns, A, nullptr, T1, nullptr, T2, nullptr, 1.0), "U");                  // T2 = U
+    HIPCHK(axpby(Ns, A2, nullptr, T1, nullptr, b3[2], T2, nullptr, 1.0), "X_P");        // T1 = b2 A2 + U
+    HIPCHK(axpby(Ns, A2, nullptr, S, nullptr, -b3[2], T2, nullptr, 1.0), "E");         // S = E = U - b2 A2
+    HIPCHK(axpby(Ns, S, nullptr, T2, nullptr, 1.0), "X = E");                           // T2 = X
+    // (I + X)(I + F2) - I = X + F2 + F2 X
     void *F = S, *X = T2, *F2 = R0, *Xn = Qi;
     for (int k = 1; k < kmax; ++k) {
       HIPCHK(gemm(Ns, F, nullptr, F, nullptr, F2, nullptr, 1.0), "F2");
-      HIPCHK(gemm(Ns, F2, nullptr, X, nullptr, Xn, nullptr, 1.0, X, nullptr, 1.0), "X+F2X");
+      HIPCHK(gemm2(Ns, F2, X, Xn, 1.0, X, 1.0, F2, 1.0), "X + F2 + F2 X");
       std::swap(F, F2);
       std::swap(X, Xn);
     }
-    if (X != Qi) HIPCHK(axpby(Ns, X, nullptr, Qi, nullptr, 1.0), "Qinv");
-    HIPCHK(gemm(Ns, Qi, nullptr, T1, nullptr, R0, nullptr, 1.0), "R0");   // R0 = Q^{-1} P
+    if (X != Qi) HIPCHK(axpby(Ns, X, nullptr, Qi, nullptr, 1.0), "X_Q");
+    HIPCHK(gemm2(Ns, Qi, T1, R0, 1.0, Qi, 1.0, T1, 1.0), "D");   // R0 = X_Q + X_P + X_Q X_P
     HIPCHK(axpby(Ns, R0, nullptr, S, nullptr, 1.0), "S");
+    // (I + D)^2 = I + 2 D + D^2
     for (int k = 0; k < smax; ++k) {
       const int cnt = sq_off[k + 1] - sq_off[k];
       const int32_t* li = ip(o_sq) + sq_off[k];
       if (!cnt) continue;
-      HIPCHK(gemm(cnt, S, li, S, li, T1, li, 1.0), "square");
+      HIPCHK(gemm(cnt, S, li, S, li, T1, li, 1.0, S, li, 2.0), "square");
       HIPCHK(axpby(cnt, T1, li, S, li, 1.0), "square copy");
     }
   }
-  // ---- ordered products inside chunks (forward chain), storing P_loc
+  // ---- ordered products inside chunks (forward chain), storing P_loc. Chunk
+  // products, prefixes and suffixes are kept as M - I: (I + D)(I + Q) - I = Q + D + D Q.
   void* Pc[2] = {CM(0), CM(1)};
   {
     StageTimer t(c, 2, s);
-    HIPCHK(axpby(Lc, Pc[0], nullptr, Pc[0], nullptr, 0.0, nullptr, nullptr, 0.0, 1.0), "P = I");
+    HIPCHK(axpby(Lc, Pc[0], nullptr, Pc[0], nullptr, 0.0), "P - I = 0");
     int cur = 0;
     for (int k = 0; k < C; ++k) {
       const int a0 = q.chain_off[k], cnt = q.chain_off[k + 1] - a0;
       if (cnt == 0) continue;
       const int32_t* sl = ip(o_cs) + a0;
       const int32_t* chn = ip(o_cc) + a0;
-      if (grad) HIPCHK(axpby(cnt, Pc[cur], chn, Pl, sl, 1.0), "store P_loc");
-      HIPCHK(gemm(cnt, S, sl, Pc[cur], chn, Pc[cur ^ 1], chn, 1.0), "chain");
+      if (grad) HIPCHK(axpby(cnt, Pc[cur], chn, Pl, sl, 1.0, nullptr, nullptr, 0.0, 1.0), "store P_loc");
+      HIPCHK(gemmx(cnt, S, sl, Pc[cur], chn, Pc[cur ^ 1], chn, 1.0, Pc[cur], chn, 1.0, S, sl, 1.0), "chain");
       // chunks not advanced at this step keep their product in the other buffer too
       HIPCHK(axpby(cnt, Pc[cur ^ 1], chn, Pc[cur], chn, 1.0), "chain sync");
     }
@@ -757,7 +775,9 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         const int c0 = q.copy_off[li], ccnt = q.copy_off[li + 1] - c0;
         const void* in = dir == 0 ? pre_cur : suf_cur;
         void* out = dir == 0 ? pre[bsel] : suf[bsel];
-        if (cnt) HIPCHK(gemm(cnt, in, ip(o_sa) + a0, in, ip(o_sb) + a0, out, ip(o_sc) + a0, 1.0), "scan");
+        if (cnt)
+          HIPCHK(gemmx(cnt, in, ip(o_sa) + a0, in, ip(o_sb) + a0, out, ip(o_sc) + a0, 1.0, in,
+                       ip(o_sa) + a0, 1.0, in, ip(o_sb) + a0, 1.0), "scan");
         if (ccnt) HIPCHK(axpby(ccnt, in, ip(o_cp) + c0, out, ip(o_cp) + c0, 1.0), "scan copy");
       }
       pre_cur = pre[bsel];
@@ -765,16 +785,9 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       bsel ^= 1;
     }
   }
-  if (S_out) {
-    // U of every item = inclusive prefix at its last chunk
-    BigAxpbyArgs g{};
-    for (size_t i = 0; i < p.items.size(); ++i) {
-      const int lastc = q.item_last_chunk[i];
-      HIPCHK(hipMemcpyAsync((char*)S_out + (size_t)p.items[i].src * mb, (const char*)pre_cur + (size_t)lastc * mb,
-                            mb, hipMemcpyDeviceToDevice, s), "extract");
-    }
-    (void)g;
-  }
+  if (S_out)   // U of every item = I + inclusive prefix at its last chunk
+    HIPCHK(axpby((int)p.items.size(), pre_cur, ip(o_il), S_out, ip(o_is), 1.0, nullptr, nullptr, 0.0, 1.0),
+           "extract");
   if (!fidelity) return LMAG_OK;
   // ---- targets, fidelity, environments
   HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, (double*)at(L.st64), (float*)at(L.st), s),
@@ -796,15 +809,17 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       StageTimer t(c, 4, s);
       const void* st = at(L.st);
       if (!q.env_suf_c.empty())
-        HIPCHK(gemm((int)q.env_suf_c.size(), st, ip(o_est), suf_cur, ip(o_en), X, ip(o_es), 1.0), "env X");
+        HIPCHK(gemm((int)q.env_suf_c.size(), st, ip(o_est), suf_cur, ip(o_en), X, ip(o_es), 1.0, st,
+                    ip(o_est), 1.0), "env X");   // S_T^dag (I + Suf)
       if (!q.env_nosuf_c.empty())
         HIPCHK(axpby((int)q.env_nosuf_c.size(), st, ip(o_ent), X, ip(o_ens), 1.0), "env X copy");
       if (!q.env_pre_c.empty())
-        HIPCHK(gemm((int)q.env_pre_c.size(), pre_cur, ip(o_epp), X, ip(o_ep), env, ip(o_ep), 1.0), "env W");
+        HIPCHK(gemm((int)q.env_pre_c.size(), pre_cur, ip(o_epp), X, ip(o_ep), env, ip(o_ep), 1.0, X,
+                    ip(o_ep), 1.0), "env W");   // (I + Pre) X
       if (!q.env_nopre_c.empty())
         HIPCHK(axpby((int)q.env_nopre_c.size(), X, ip(o_enp), env, ip(o_enp), 1.0), "env W copy");
     }
-    // ---- backward chain: M_n = P_loc,n Z, Z <- Z S_n (normal orientation)
+    // ---- backward chain: M_n = P_loc,n Z, Z <- Z S_n = Z + Z D_n (normal orientation)
     {
       StageTimer t(c, 5, s);
       void* Z[2] = {env, X};
@@ -815,7 +830,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         const int32_t* sl = ip(o_cs) + a0;
         const int32_t* chn = ip(o_cc) + a0;
         HIPCHK(gemm(cnt, Pl, sl, Z[cur], chn, Em, sl, 1.0), "M");
-        HIPCHK(gemm(cnt, Z[cur], chn, S, sl, Z[cur ^ 1], chn, 1.0), "Z");
+        HIPCHK(gemm(cnt, Z[cur], chn, S, sl, Z[cur ^ 1], chn, 1.0, Z[cur], chn, 1.0), "Z");
         HIPCHK(axpby(cnt, Z[cur ^ 1], chn, Z[cur], chn, 1.0), "Z sync");
       }
       // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
@@ -828,16 +843,18 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       HIPCHK(gemm(Ns, Em, nullptr, T2, nullptr, T4, nullptr, 1.0, T4, nullptr, 1.0), "LU");       // T4 = L_U
       HIPCHK(axpby(Ns, T1, nullptr, T3, nullptr, b3[2], T4, nullptr, -1.0), "LQ");                 // T3 = L_Q
       HIPCHK(axpby(Ns, T1, nullptr, T2, nullptr, b3[2], T4, nullptr, 1.0), "LP");                  // T2 = L_P
-      HIPCHK(gemm(Ns, T3, nullptr, R0, nullptr, T1, nullptr, -1.0, T2, nullptr, 1.0), "X");        // T1 = L_P - L_Q R0
-      HIPCHK(gemm(Ns, Qi, nullptr, T1, nullptr, T3, nullptr, 1.0), "K");                           // T3 = K
-      // squaring recurrence K <- R K + K R, R <- R^2 for the slices with s > k
+      // r = I + D (R0 = D), Q^{-1} = I + X_Q (Qi = X_Q)
+      HIPCHK(gemm2(Ns, T3, R0, T1, -1.0, T2, 1.0, T3, -1.0), "X");   // T1 = L_P - L_Q - L_Q D
+      HIPCHK(gemm(Ns, Qi, nullptr, T1, nullptr, T3, nullptr, 1.0, T1, nullptr, 1.0), "K");   // T3 = K
+      // squaring recurrence K <- R K + K R = 2 K + D K + K D, D <- 2 D + D D for the
+      // slices with s > k
       for (int k = 0; k < smax; ++k) {
         const int cnt = sq_off[k + 1] - sq_off[k];
         const int32_t* li = ip(o_sq) + sq_off[k];
         if (!cnt) continue;
-        HIPCHK(gemm(cnt, R0, li, T3, li, T4, li, 1.0), "RK");
-        HIPCHK(gemm(cnt, T3, li, R0, li, T2, li, 1.0, T4, li, 1.0), "RK + KR");
-        HIPCHK(gemm(cnt, R0, li, R0, li, T1, li, 1.0), "R^2");
+        HIPCHK(gemm(cnt, R0, li, T3, li, T4, li, 1.0, T3, li, 2.0), "2K + DK");
+        HIPCHK(gemm(cnt, T3, li, R0, li, T2, li, 1.0, T4, li, 1.0), "+ KD");
+        HIPCHK(gemm(cnt, R0, li, R0, li, T1, li, 1.0, R0, li, 2.0), "2D + D^2");
         HIPCHK(axpby(cnt, T2, li, T3, li, 1.0), "K");
         HIPCHK(axpby(cnt, T1, li, R0, li, 1.0), "R");
       }

@@ -82,3 +82,20 @@ def test_five_spin_propagator_and_fidelity():
     assert rel(U, U_ref) < 2e-5
     F_ref, _ = oracle.fidelity(U_ref, cfg["U_target"])
     assert abs(F - F_ref) < 1e-6
+
+
+def test_four_spin_high_fidelity_closed_system():
+    """F near 1 on the block-tiled path: 1024 slices of 0.25 ns, target = the
+    oracle's own closed-system propagator (|up up up up> spans a one-dimensional
+    S_z sector, so the top-left d x d block is the unitary up to a phase)."""
+    cfg = synth.small_case(72, n_spins=4, n_slices=1024, dt=2.5e-4)
+    amps = rounded(cfg["amps"], "f32")
+    osys = oracle_system(cfg, dissipative=False)
+    S_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    d = cfg["d"]
+    tgt = S_ref[:d, :d] / np.abs(np.linalg.det(S_ref[:d, :d])) ** (1.0 / d)
+    F_ref, _ = oracle.fidelity(S_ref, tgt)
+    assert F_ref > 1 - 1e-12
+    sysm, U, F, _ = run({**cfg, "U_target": tgt}, amps, want_grad=False, dissipative=False)
+    assert rel(U, S_ref) < 1e-4
+    assert abs(F - F_ref) <= 1e-6

@@ -139,3 +139,37 @@ def test_config1_gradient_sampled(config1_run):
     assert rel(ours, adj) <= 1e-3
     fd = oracle.grad_fd_cached(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"], coords, h=1e-4)
     assert rel(ours, fd) <= 1e-3
+
+
+def test_config1_high_fidelity_closed_system():
+    """F near 1 is where rounding along the 4096-slice chain shows most (the
+    error of F is first order in any non-unitary drift of the product). The
+    target is the oracle's own closed-system propagator of the same pulse: the
+    |up up up> state spans a one-dimensional S_z sector, so the top-left d x d
+    block of the superoperator is the unitary up to a global phase."""
+    cfg = synth.config1()
+    amps = rounded(cfg["amps"], "f32")
+    osys = oracle_system(cfg, dissipative=False)
+    S_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    d = 8
+    tgt = S_ref[:d, :d] / np.abs(np.linalg.det(S_ref[:d, :d])) ** (1.0 / d)
+    F_ref, _ = oracle.fidelity(S_ref, tgt)
+    assert F_ref > 1 - 1e-12
+    sysm = lib_system(cfg, dissipative=False)
+    S = sysm.propagate(to_dev(amps, sysm), [4096], cfg["dt"],
+                       static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    assert rel(S, S_ref) <= 1e-4
+    F, _ = lib_fid(sysm, {**cfg, "U_target": tgt}, amps, want_grad=False)
+    assert abs(F[0] - F_ref) <= 1e-6
+    # gradient near (not at) the optimum, F about 0.995
+    rng = np.random.default_rng(11)
+    a2 = rounded(amps + rng.normal(0.0, 0.05 * synth.A_MAX, amps.shape), "f32")
+    F2, g2 = lib_fid(sysm, {**cfg, "U_target": tgt}, a2)
+    coords = np.asarray(cfg["fd_coords"])
+    rows = sorted(set(int(c) // 2 for c in coords))
+    F2_ref, g_at = oracle.grad_adjoint_at(osys, a2, cfg["dt"], 2, "foh", tgt, rows)
+    assert 0.9 < F2_ref < 1 - 1e-4
+    assert abs(F2[0] - F2_ref) <= 1e-6
+    ours = np.array([g2[int(c) // 2, int(c) % 2] for c in coords])
+    adj = np.array([g_at[int(c) // 2][int(c) % 2] for c in coords])
+    assert rel(ours, adj) <= 1e-3
