@@ -105,6 +105,67 @@ def read_traffic(kernel, slices):
         return None
 
 
+TRAFFIC_SOURCES = ["paper_2511_13330_amd/csrc/k_slice.hip", "paper_2511_13330_amd/csrc/tile.hpp",
+                   "paper_2511_13330_amd/csrc/internal.hpp"]
+
+
+def record_traffic(fetch_csv, write_csv, slices, copy_bytes):
+    """Writes profiles/traffic_<kernel>.json for k_forward and k_backward from
+    two rocprofv3 counter runs of this script (FETCH_SIZE, then WRITE_SIZE, in
+    KiB per dispatch), each scaled by what the same counter reads for the plain
+    device copy of `copy_bytes` bytes that --copy-calibration dispatches first.
+    Runs on the host from the CSV files; prints a markdown table."""
+    import csv
+    import hashlib
+
+    def read(path, counter):
+        rows = {}
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                rows.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return rows
+
+    kib = copy_bytes / 1024.0
+    out = {}
+    scales = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = read(path, counter)
+        copies = [v for k, vals in rows.items() if "copyBuffer" in k for v in vals]
+        if not copies:
+            raise SystemExit(f"{path}: no calibration copy dispatch found")
+        scales[counter] = kib / max(copies)
+        for name, vals in rows.items():
+            for kern in ("k_forward", "k_backward", "k_omega", "k_traces"):
+                if f"lmag::{kern}<" in name:
+                    out.setdefault(kern, {})[counter] = float(np.mean(vals))
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read / slice | write / slice |")
+    print("|---|---|---|---|---|")
+    for kern, c in sorted(out.items()):
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        fb = c["FETCH_SIZE"] * scales["FETCH_SIZE"] * 1024.0 / slices
+        wb = c["WRITE_SIZE"] * scales["WRITE_SIZE"] * 1024.0 / slices
+        print(f"| {kern} | {c['FETCH_SIZE']:,.0f} | {c['WRITE_SIZE']:,.0f} | {fb / 1024:.1f} KiB | "
+              f"{wb / 1024:.1f} KiB |")
+        if kern not in ("k_forward", "k_backward"):
+            continue
+        rec = {"kernel": kern, "sources": TRAFFIC_SOURCES, "source_sha256": h.hexdigest(),
+               "fetch_kib_raw": c["FETCH_SIZE"], "write_kib_raw": c["WRITE_SIZE"],
+               "fetch_scale": scales["FETCH_SIZE"], "write_scale": scales["WRITE_SIZE"],
+               "slices_per_dispatch_measured": slices, "bytes_per_slice": fb + wb,
+               "fetch_bytes_per_slice": fb, "write_bytes_per_slice": wb}
+        with open(os.path.join(ROOT, "profiles", f"traffic_{kern}.json"), "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+    print(f"\ncalibration: FETCH_SIZE x {scales['FETCH_SIZE']:.4f}, WRITE_SIZE x {scales['WRITE_SIZE']:.4f}")
+
+
 def robust_sweep(args):
     """Candidates x quasi-static noise samples with uneven slice counts in one
     call per sweep: per-candidate mean fidelity and mean gradient."""
@@ -213,7 +274,16 @@ def main():
                     choices=["pulse", "proposal", "robust", "four_spin", "six_spin"],
                     help="pulse: the headline metric (default); proposal: learned proposal + "
                          "refine vs cold start; robust: candidates x noise samples, uneven N")
+    ap.add_argument("--record-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="host only: write profiles/traffic_<kernel>.json from two counter runs "
+                         "(rocprofv3 counter_collection.csv of a --copy-calibration run with this "
+                         "--batch)")
     args = ap.parse_args()
+    if args.record_traffic:
+        if args.copy_calibration <= 0:
+            ap.error("--record-traffic needs the --copy-calibration size the counter runs used")
+        record_traffic(*args.record_traffic, slices=args.batch * 4096, copy_bytes=args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU design is described in DESIGN.md).", file=sys.stderr)
