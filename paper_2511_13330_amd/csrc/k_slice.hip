@@ -198,11 +198,11 @@ __global__ void __launch_bounds__(WG) k_traces(SliceArgs a, int n_total) {
 // an ulp, and over a chain of thousands of slices that bias adds up linearly.
 // Stores go to the workspace when requested: A^2, Q^{-1} - I and r_m(A) - I
 // (before the squarings).
+// A holds Omega_n / 2^s (loaded by the caller, which prefetches it during the
+// previous slice's chain product).
 template <typename T>
-__device__ void fwd_slice(RT<T>& R, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
-                          cpx<T>* ws, Clock& ck) {
-  RT<T> A;
-  rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)n), 64);
+__device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a,
+                          int n, cpx<T>* ws, Clock& ck) {
   const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
   const double* b = pade_b<T>(a.pade, m);   // b[0] = 1
   ck.mark(0);
@@ -401,15 +401,18 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     const Chunk ch = a.chunks[idx];
     RTW P;
     rtw_identity<T>(P);
+    RT<T> A;
+    rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
     for (int k = 0; k < ch.count; ++k) {
       const int n = ch.first + k;
       cpx<T>* ws = (a.store && a.ws_tiles) ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
       if (ws) rtw_store<T>(P, ws + WS_PLOC * TILE);
       RT<T> D;
-      fwd_slice<T>(D, sh, gs, a, n, ws, ck);
+      fwd_slice<T>(D, A, sh, gs, a, n, ws, ck);
       __syncthreads();
       put<T, false>(D, slot<T, 3>(sh, gs));
       __syncthreads();
+      if (k + 1 < ch.count) rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)n + 1), 64);
       chain_step<T>(P, slot<T, 3>(sh, gs));
       ck.mark(6);
     }
@@ -575,12 +578,15 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       // recompute the chunk's forward into this workgroup's scratch tiles
       RTW P;
       rtw_identity<T>(P);
+      RT<T> A;
+      rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
       for (int k = 0; k < ch.count; ++k) {
         cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
         rtw_store<T>(P, ws + WS_PLOC * TILE);
         RT<T> D;
-        fwd_slice<T>(D, sh, gs, a, ch.first + k, ws, ck);
+        fwd_slice<T>(D, A, sh, gs, a, ch.first + k, ws, ck);
         if (k + 1 < ch.count) {
+          rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
           __syncthreads();
           put<T, false>(D, slot<T, 3>(sh, gs));
           __syncthreads();
@@ -666,8 +672,9 @@ template <typename T>
 __global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, SliceArgs a) {
   __shared__ Shared<T> sh;
   Clock ck(nullptr, sh.clk);
-  RT<T> R;
-  fwd_slice<T>(R, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
+  RT<T> R, A;
+  rt_load<T, false>(A, tile_at<T>(a.omega, 0), 64);
+  fwd_slice<T>(R, A, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
   rt_add_diag(R, T(1));
   rt_store<T, false>(R, C, 64);
 }
