@@ -233,8 +233,11 @@ lmag_status lmag_read_profile(lmag_ctx *ctx, double *ms_out /*[LMAG_STAGES]*/,
  * slices per chunk, workgroups of the persistent slice kernels, workspace bytes
  * in use, recompute mode (1 = the backward re-ran each chunk's forward instead of
  * reading stored per-slice tiles), number of waves the call was split into to
- * fit workspace_bytes_max (or 85 % of free device memory). */
-lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[7]*/);
+ * fit workspace_bytes_max (or 85 % of free device memory), and the number of
+ * support positions of the system's sparse basis tables (0: the basis is too
+ * dense and the dense Omega and trace kernels are used; also 0 for systems
+ * larger than one tile). */
+lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[8]*/);
 
 /* Instrumentation: per-phase shader-clock cycles of workgroup 0 of the slice
  * kernels, summed over the calls made while enabled. enable = 1 clears and

@@ -10,6 +10,28 @@ namespace lmag {
 // scaling thresholds theta_m, for the degrees this library evaluates.
 struct PadeTable {
   double b3[4], b5[6], b7[8];
+  double ser_max32;         // largest ||A||_1 for the degree-5 series of 1/q_3 (FP32)
+};
+
+// Sparse form of a 64 x 64 basis (built by set_system from its nonzero entries
+// B_j[x], x = row * 64 + col). Support positions p (the union of the basis
+// supports) are numbered column by column, by ascending row. n_sup = 0 means
+// the dense kernels are used (a column with more than SP_COLCAP support rows).
+constexpr int SP_COLCAP = 16;
+struct SparseBasis {
+  int n_sup, nnz;
+  const int32_t* col_ptr;   // [65] support positions of column c
+  const uint8_t* sup_row;   // [n_sup] row of each support position
+  const int32_t* sup_eptr;  // [n_sup + 1] entries of position p: [sup_eptr[p], sup_eptr[p + 1])
+  const uint8_t* pe_j;      // [nnz] position-ordered entries (ascending j within a position)
+  const void* pe_val;       // [nnz] complex value, compute type
+  // Compact K_n^T: the support positions in register-tile order (thread by
+  // thread, each thread's registers in order), so a thread's entries are
+  // consecutive. kpack[t] = (first slot << 16) | (mask of its 16 registers).
+  const uint32_t* kpack;    // [256]
+  const int32_t* ptr_j;     // [nb + 1] j-ordered entries of B_j: [ptr_j[j], ptr_j[j + 1])
+  const uint16_t* ent_slot; // [nnz] compact slot of each j-ordered entry's position
+  const void* ent_val;      // [nnz] complex value, compute type
 };
 
 // One chunk of consecutive slices of one item; the unit of work of the slice
@@ -50,12 +72,14 @@ struct SliceArgs {
   int8_t* nlev;             // [n_slices_total] inverse variant code (see inverse_code)
   int inv_mode;             // 0 automatic; 2 no power series (Neumann or Gauss-Jordan)
   void* gscratch;           // per-workgroup global scratch slots (double precision)
-  void* omega;              // [n_slices_total][64][64]: Omega_n / 2^s, then K_n^T (backward)
+  void* omega;              // [n_slices_total][64][64]: Omega_n / 2^s, then K_n^T (backward;
+                            // with a sparse basis only its support positions, compacted)
   long long* clk;           // [32] per-phase cycle counters of workgroup 0, or null
   int recompute;            // backward recomputes each chunk's forward tiles
   void* rscratch;           // [grid][max_chunk][WS_TILES] tiles (recompute mode)
   int max_chunk;            // slices per chunk (scratch stride)
   PadeTable pade;
+  SparseBasis sp;           // sparse basis (Omega build, compact K_n^T, traces), or n_sup = 0
 };
 
 // launchers (kernel files)

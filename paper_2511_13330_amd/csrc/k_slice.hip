@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
         a.ms[2 * (size_t)n] = (int8_t)m;
         a.ms[2 * (size_t)n + 1] = (int8_t)sc;
         if (a.nlev)
-          a.nlev[n] = (int8_t)inverse_code<T>(ldexp(v, -sc), pade_b<T>(a.pade, m), m, a.inv_mode != 2);
+          a.nlev[n] = (int8_t)inverse_code<T>(ldexp(v, -sc), pade_b<T>(a.pade, m), m, a.inv_mode != 2,
+                                              a.pade.ser_max32);
       }
     }
     __syncthreads();
@@ -143,6 +144,95 @@ __global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
       cpx<T> v; v.re = acc[s][e].re * f; v.im = acc[s][e].im * f;
       out[(rb + e) * 64 + col] = v;
     }
+  }
+}
+
+// Omega_n / 2^s from the sparse basis: one wave per slice, lane c owns column c.
+// Each support entry is summed over its basis terms in ascending j (the order of
+// the dense kernel, whose other terms are exact zeros) into registers; the FP64
+// column 1-norm selects (m, s); the lane then writes its column: zeros with
+// row-coalesced stores, followed (same lane, same addresses, program order) by
+// its support values.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_omega_sparse(SliceArgs a, int n_total) {
+  __shared__ T al_sh[4][MAXNB];
+  const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
+  const int n = blockIdx.x * 4 + w;
+  const bool valid = n < n_total;
+  if (valid && c < a.nb) al_sh[w][c] = (T)a.alpha[(size_t)n * a.nb + c];
+  __syncthreads();
+  if (!valid) return;   // wave-uniform; no barrier follows
+  const SparseBasis& sp = a.sp;
+  const cpx<T>* val = (const cpx<T>*)sp.pe_val;
+  const T* al = al_sh[w];
+  const int p0 = sp.col_ptr[c], cnt = sp.col_ptr[c + 1] - p0;
+  cpx<T> v[SP_COLCAP];
+  int row[SP_COLCAP];
+  double cs = 0.0;
+#pragma unroll
+  for (int q = 0; q < SP_COLCAP; ++q) {
+    v[q].re = T(0);
+    v[q].im = T(0);
+    row[q] = 0;
+    if (q < cnt) {
+      row[q] = sp.sup_row[p0 + q];
+      for (int i = sp.sup_eptr[p0 + q]; i < sp.sup_eptr[p0 + q + 1]; ++i) {
+        const T aj = al[sp.pe_j[i]];
+        const cpx<T> b = val[i];
+        v[q].re += aj * b.re;
+        v[q].im += aj * b.im;
+      }
+      const double x = (double)v[q].re, y = (double)v[q].im;
+      cs += sqrt(x * x + y * y);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) cs = fmax(cs, __shfl_xor(cs, off));
+  int m = 3, sc = 0;
+  choose_ms<T>(cs, m, sc);
+  if (c == 0) {
+    a.ms[2 * (size_t)n] = (int8_t)m;
+    a.ms[2 * (size_t)n + 1] = (int8_t)sc;
+    if (a.nlev)
+      a.nlev[n] = (int8_t)inverse_code<T>(ldexp(cs, -sc), pade_b<T>(a.pade, m), m, a.inv_mode != 2,
+                                          a.pade.ser_max32);
+  }
+  const T f = (T)ldexp(1.0, -sc);
+  cpx<T>* out = tile_at<T>(a.omega, (size_t)n);
+  const cpx<T> zero{T(0), T(0)};
+  for (int r = 0; r < 64; ++r) out[r * 64 + c] = zero;
+#pragma unroll
+  for (int q = 0; q < SP_COLCAP; ++q)
+    if (q < cnt) {
+      cpx<T> x;
+      x.re = v[q].re * f;
+      x.im = v[q].im * f;
+      out[row[q] * 64 + c] = x;
+    }
+}
+
+// Traces from the compact K_n^T (its support positions, stored at the start of
+// the slice's exponent tile by the backward): one wave per slice; for each basis
+// element the lanes take its entries in a fixed order and the wave sums them
+// in FP64.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_traces_sparse(SliceArgs a, int n_total) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int n = blockIdx.x * 4 + w;
+  if (n >= n_total) return;
+  const SparseBasis& sp = a.sp;
+  const cpx<T>* kc = tile_at<T>(a.omega, (size_t)n);
+  const cpx<T>* val = (const cpx<T>*)sp.ent_val;
+  for (int j = 0; j < a.nb; ++j) {
+    double t = 0.0;
+    for (int i = sp.ptr_j[j] + l; i < sp.ptr_j[j + 1]; i += 64) {
+      const cpx<T> k = kc[sp.ent_slot[i]];
+      const cpx<T> b = val[i];
+      t += (double)(k.re * b.re - k.im * b.im);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+    if (l == 0) a.gtrace[(size_t)n * a.nb + j] = t;
   }
 }
 
@@ -423,9 +513,10 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
 
 // One slice backward in the transposed frame. Z holds Z_n^T on entry and
 // Z_{n-1}^T on exit.
+// kpack: this thread's compact-K_n^T word (sparse basis), see SparseBasis.
 template <typename T>
 __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
-                          const cpx<T>* ws, Clock& ck) {
+                          const cpx<T>* ws, Clock& ck, uint32_t kpack) {
   const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
@@ -545,8 +636,24 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     rt_copy(R, Rn);
   }
   ck.mark(7);
-  // K_n^T replaces A_n; the traces Re Tr(K_n B_j) are taken by k_traces
-  rt_store<T, false>(K, tile_at<T>(a.omega, (size_t)n), 64);
+  // K_n^T replaces A_n (whole tile, or only its support positions, compacted,
+  // with a sparse basis); the traces Re Tr(K_n B_j) are taken afterwards
+  if (a.sp.n_sup > 0) {
+    cpx<T>* kc = tile_at<T>(a.omega, (size_t)n) + (kpack >> 16);
+    int slot = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if ((kpack >> (4 * q + r)) & 1u) {
+          cpx<T> x;
+          x.re = K.re[q][r];
+          x.im = K.im[q][r];
+          kc[slot++] = x;
+        }
+  } else {
+    rt_store<T, false>(K, tile_at<T>(a.omega, (size_t)n), 64);
+  }
   ck.mark(8);
   // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T
   __syncthreads();
@@ -568,6 +675,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
                           : nullptr;
   Clock ck(a.clk ? a.clk + 16 : nullptr, sh.clk);
+  const uint32_t kpack = a.sp.n_sup > 0 ? a.sp.kpack[threadIdx.x] : 0u;
   for (;;) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
@@ -601,7 +709,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       const int n = ch.first + k;
       const cpx<T>* ws = rs ? rs + (size_t)k * WS_TILES * TILE
                             : tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES);
-      bwd_slice<T>(Z, sh, gs, a, n, ws, ck);
+      bwd_slice<T>(Z, sh, gs, a, n, ws, ck, kpack);
     }
   }
   ck.flush(a.clk ? a.clk + 16 : nullptr);
@@ -615,6 +723,12 @@ hipError_t launch_slice_forward(int prec, const SliceArgs& a, int grid, hipStrea
 
 hipError_t launch_omega(int prec, const SliceArgs& a, int n_total, hipStream_t s) {
   if (n_total <= 0) return hipSuccess;
+  if (a.sp.n_sup > 0) {
+    const dim3 g((n_total + 3) / 4);
+    if (prec == 32) hipLaunchKernelGGL(k_omega_sparse<float>, g, dim3(WG), 0, s, a, n_total);
+    else hipLaunchKernelGGL(k_omega_sparse<double>, g, dim3(WG), 0, s, a, n_total);
+    return hipGetLastError();
+  }
   const dim3 g((n_total + OMEGA_SLICES - 1) / OMEGA_SLICES);
   if (prec == 32) hipLaunchKernelGGL(k_omega<float>, g, dim3(WG), 0, s, a, n_total);
   else hipLaunchKernelGGL(k_omega<double>, g, dim3(WG), 0, s, a, n_total);
@@ -623,6 +737,12 @@ hipError_t launch_omega(int prec, const SliceArgs& a, int n_total, hipStream_t s
 
 hipError_t launch_traces(int prec, const SliceArgs& a, int n_total, hipStream_t s) {
   if (n_total <= 0) return hipSuccess;
+  if (a.sp.n_sup > 0) {
+    const dim3 g((n_total + 3) / 4);
+    if (prec == 32) hipLaunchKernelGGL(k_traces_sparse<float>, g, dim3(WG), 0, s, a, n_total);
+    else hipLaunchKernelGGL(k_traces_sparse<double>, g, dim3(WG), 0, s, a, n_total);
+    return hipGetLastError();
+  }
   const dim3 g((n_total + TRACE_SLICES - 1) / TRACE_SLICES);
   if (prec == 32) hipLaunchKernelGGL(k_traces<float>, g, dim3(WG), 0, s, a, n_total);
   else hipLaunchKernelGGL(k_traces<double>, g, dim3(WG), 0, s, a, n_total);

@@ -3,6 +3,7 @@
 #include "../../include/lmag.h"
 #include "internal.hpp"
 #include "tile.hpp"
+#include "pade.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -64,6 +65,8 @@ struct lmag_ctx {
   size_t ws_max = 0;
   double* basis64 = nullptr;
   void* basis32 = nullptr;
+  void* sp_dev = nullptr;     // sparse basis tables (64 x 64 path), see build_sparse
+  SparseBasis sp{};
   // workspace
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -409,6 +412,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   sa.omega = at(L.omega); sa.clk = c->clk_on ? c->clk_dev : nullptr;
   sa.recompute = grad && p.recompute; sa.rscratch = sa.recompute ? at(L.rscratch) : nullptr;
   sa.max_chunk = p.chunk_size;
+  sa.sp = c->sp;
   if (sa.recompute) { sa.store = 0; sa.ws_tiles = nullptr; }
   { StageTimer t(c, 1, s); HIPCHK(launch_omega(c->prec, sa, p.total_slices, s), "omega"); }
   { StageTimer t(c, 2, s); HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward"); }
@@ -505,6 +509,112 @@ struct BigPlan {
   std::vector<int32_t> ident;                                    // 0, 1, 2, ...
   int C = 0, levels = 0;
 };
+
+// Sparse tables of the 64 x 64 basis (host copy of the FP64 tiles): the union
+// of the supports, numbered column by column (ascending rows), each position
+// with its entries by ascending j; and the entries of each B_j with their
+// position. Returns false (dense kernels) if a column has more than SP_COLCAP
+// support rows.
+bool build_sparse(lmag_ctx* c, const std::vector<double>& hb, int nb, int prec) {
+  auto at = [&](int j, int x, int part) { return hb[((size_t)j * TILE + x) * 2 + part]; };
+  auto nz = [&](int j, int x) { return at(j, x, 0) != 0.0 || at(j, x, 1) != 0.0; };
+  std::vector<int16_t> cslot(TILE, -1);
+  std::vector<int32_t> col_ptr(65, 0), sup_eptr(1, 0), ptr_j(nb + 1, 0);
+  std::vector<uint8_t> sup_row, pe_j;
+  std::vector<double> pe_v;
+  int n_sup = 0;
+  for (int col = 0; col < 64; ++col) {
+    for (int row = 0; row < 64; ++row) {
+      const int x = row * 64 + col;
+      bool any = false;
+      for (int j = 0; j < nb; ++j)
+        if (nz(j, x)) {
+          any = true;
+          pe_j.push_back((uint8_t)j);
+          pe_v.push_back(at(j, x, 0));
+          pe_v.push_back(at(j, x, 1));
+        }
+      if (!any) continue;
+      cslot[x] = (int16_t)n_sup++;
+      sup_row.push_back((uint8_t)row);
+      sup_eptr.push_back((int32_t)pe_j.size());
+    }
+    col_ptr[col + 1] = n_sup;
+    if (col_ptr[col + 1] - col_ptr[col] > SP_COLCAP) return false;
+  }
+  const int nnz = (int)pe_j.size();
+  if (nnz == 0) return false;
+  // compact slots in register-tile order: thread t = 64 w + 16 g + cc holds
+  // column 16 w + cc and rows 16 q + sub(g, r) in register 4 q + r
+  std::vector<uint32_t> kpack(256);
+  std::vector<int32_t> slot_of(TILE, -1);
+  int next = 0;
+  for (int t = 0; t < 256; ++t) {
+    const int w = t >> 6, g = (t & 63) >> 4, cc = t & 15;
+    uint32_t mask = 0;
+    const int first = next;
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * q + (prec == 32 ? 4 * g + r : g + 4 * r), col = 16 * w + cc;
+        const int x = row * 64 + col;
+        if (cslot[x] < 0) continue;
+        mask |= 1u << (4 * q + r);
+        slot_of[x] = next++;
+      }
+    kpack[t] = ((uint32_t)first << 16) | mask;
+  }
+  std::vector<uint16_t> ent_slot;
+  std::vector<double> ent_v;
+  for (int j = 0; j < nb; ++j) {
+    for (int col = 0; col < 64; ++col)
+      for (int row = 0; row < 64; ++row) {
+        const int x = row * 64 + col;
+        if (!nz(j, x)) continue;
+        ent_slot.push_back((uint16_t)slot_of[x]);
+        ent_v.push_back(at(j, x, 0));
+        ent_v.push_back(at(j, x, 1));
+      }
+    ptr_j[j + 1] = (int32_t)ent_slot.size();
+  }
+  std::vector<char> blob;
+  auto add = [&](const void* src, size_t bytes) {
+    const size_t off = (blob.size() + 255) / 256 * 256;
+    blob.resize(off + bytes);
+    if (bytes) std::memcpy(blob.data() + off, src, bytes);
+    return off;
+  };
+  auto addv = [&](const std::vector<double>& v) {
+    if (prec == 64) return add(v.data(), v.size() * 8);
+    std::vector<float> f(v.begin(), v.end());
+    return add(f.data(), f.size() * 4);
+  };
+  const size_t o_cp = add(col_ptr.data(), col_ptr.size() * 4), o_sr = add(sup_row.data(), sup_row.size()),
+               o_se = add(sup_eptr.data(), sup_eptr.size() * 4), o_pj = add(pe_j.data(), pe_j.size()),
+               o_pv = addv(pe_v), o_ptr = add(ptr_j.data(), ptr_j.size() * 4),
+               o_es = add(ent_slot.data(), ent_slot.size() * 2), o_ev = addv(ent_v),
+               o_kp = add(kpack.data(), kpack.size() * 4);
+  void* dev = nullptr;
+  if (hipMalloc(&dev, blob.size()) != hipSuccess) { (void)hipGetLastError(); return false; }
+  if (hipMemcpy(dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(dev);
+    return false;
+  }
+  char* d = (char*)dev;
+  c->sp_dev = dev;
+  c->sp.n_sup = n_sup;
+  c->sp.nnz = nnz;
+  c->sp.col_ptr = (const int32_t*)(d + o_cp);
+  c->sp.sup_row = (const uint8_t*)(d + o_sr);
+  c->sp.sup_eptr = (const int32_t*)(d + o_se);
+  c->sp.pe_j = (const uint8_t*)(d + o_pj);
+  c->sp.pe_val = d + o_pv;
+  c->sp.ptr_j = (const int32_t*)(d + o_ptr);
+  c->sp.ent_slot = (const uint16_t*)(d + o_es);
+  c->sp.ent_val = d + o_ev;
+  c->sp.kpack = (const uint32_t*)(d + o_kp);
+  return true;
+}
 
 lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
                     int n_targets, bool grad, bool fidelity, const void* U_target, double* F_out,
@@ -1015,6 +1125,7 @@ lmag_status lmag_create(lmag_ctx** out, int hip_device) {
     pade_coeffs(3, c->pade.b3);
     pade_coeffs(5, c->pade.b5);
     pade_coeffs(7, c->pade.b7);
+    c->pade.ser_max32 = series_limit32(c->pade.b3);
     *out = c;
     return LMAG_OK;
   } catch (...) {
@@ -1029,6 +1140,7 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   if (c->basis64) (void)hipFree(c->basis64);
   if (c->basis32) (void)hipFree(c->basis32);
+  if (c->sp_dev) (void)hipFree(c->sp_dev);
   if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
   if (c->clk_dev) (void)hipFree(c->clk_dev);
   if (c->mse_part) (void)hipFree(c->mse_part);
@@ -1087,8 +1199,11 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     if (e != hipSuccess) return c->hip_fail(e, "hipDeviceSynchronize");
     if (c->basis64) (void)hipFree(c->basis64);
     if (c->basis32) (void)hipFree(c->basis32);
+    if (c->sp_dev) (void)hipFree(c->sp_dev);
     c->basis64 = nullptr;
     c->basis32 = nullptr;
+    c->sp_dev = nullptr;
+    c->sp = SparseBasis{};
     c->has_sys = false;
     const size_t nn = big ? (size_t)d * d * d * d : (size_t)TILE;   // elements per basis matrix
     const size_t tb = nn * 16;
@@ -1146,6 +1261,11 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     }
     HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
     HIPCHK(hipDeviceSynchronize(), "set_system sync");
+    if (!big) {
+      std::vector<double> hb((size_t)nb * TILE * 2);
+      HIPCHK(hipMemcpy(hb.data(), c->basis64, hb.size() * 8, hipMemcpyDeviceToHost), "basis copy");
+      build_sparse(c, hb, nb, s->precision);
+    }
     (void)hipFree(ops);
     (void)hipFree(ldl);
     if (tmp) (void)hipFree(tmp);
@@ -1523,6 +1643,7 @@ lmag_status lmag_last_plan(lmag_ctx* c, int64_t* out) {
   for (int i = 0; i < 5; ++i) out[i] = c->plan_info[i];
   out[5] = c->plan_recompute ? 1 : 0;
   out[6] = c->plan_waves;
+  out[7] = c->sp.n_sup;
   return LMAG_OK;
 }
 

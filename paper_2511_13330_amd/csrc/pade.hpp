@@ -60,7 +60,7 @@ __device__ __forceinline__ int neumann_levels(double nA, const double* b, int m)
 
 // Power series of 1 / q_m(x), q_m(x) = sum_j (-1)^j b_j x^j (b_0 = 1):
 // c_0 = 1, c_k = sum_{j=1}^{min(k,m)} (-1)^{j+1} b_j c_{k-j}.
-__device__ __forceinline__ void inv_series(const double* b, int m, double* c, int K) {
+__host__ __device__ inline void inv_series(const double* b, int m, double* c, int K) {
   c[0] = 1.0;
   for (int k = 1; k < K; ++k) {
     double v = 0.0;
@@ -69,26 +69,42 @@ __device__ __forceinline__ void inv_series(const double* b, int m, double* c, in
   }
 }
 
+// Tail sum_{k > D} |c_k| x^k of the series of 1/q_m (48 terms; at the x where
+// it is used the terms fall by more than a factor 4 per degree).
+__host__ __device__ inline double inv_series_tail(const double* b, int m, int D, double x) {
+  double c[48];
+  inv_series(b, m, c, 48);
+  double tail = 0.0, p = 1.0;
+  for (int k = 1; k < 48; ++k) {
+    p *= x;
+    if (k > D) tail += fabs(c[k]) * p;
+  }
+  return tail;
+}
+
+// Largest ||A||_1 for which the degree-5 series of 1/q_3 has tail <= u / 2 in
+// single precision. The tail increases with ||A||_1, so a slice may use the
+// series exactly when its norm is at most this limit (bisection, host side).
+inline double series_limit32(const double* b3) {
+  const double u = 5.9604644775390625e-8;
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (inv_series_tail(b3, 3, 5, mid) <= 0.5 * u) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Inverse of the Pade denominator, per slice (code stored with the slice):
 //   21      power series of 1/q_3 truncated at degree 5 (single precision,
-//           m = 3), when sum_{k > 5} |c_k| ||A||_1^k <= u / 2;
+//           m = 3), when sum_{k > 5} |c_k| ||A||_1^k <= u / 2, i.e. when
+//           ||A||_1 <= ser_max (series_limit32);
 //   1..5    binary Neumann product with that many levels;
 //   0       Gauss-Jordan.
 template <typename T>
-__device__ __forceinline__ int inverse_code(double nA, const double* b, int m, int allow_series) {
-  if (sizeof(T) == 4 && m == 3 && allow_series && nA == nA) {
-    double c[48];
-    inv_series(b, 3, c, 48);
-    const double u = 5.9604644775390625e-8;
-    for (int D = 5; D <= 5; D += 2) {
-      double tail = 0.0, p = 1.0;
-      for (int k = 1; k < 48; ++k) {
-        p *= nA;
-        if (k > D) tail += fabs(c[k]) * p;
-      }
-      if (tail <= 0.5 * u) return 16 + D;
-    }
-  }
+__device__ __forceinline__ int inverse_code(double nA, const double* b, int m, int allow_series,
+                                            double ser_max) {
+  if (sizeof(T) == 4 && m == 3 && allow_series && nA <= ser_max) return 21;
   return neumann_levels<T>(nA, b, m);
 }
 

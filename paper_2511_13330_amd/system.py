@@ -206,10 +206,11 @@ class System:
         return out
 
     def last_plan(self):
-        out = np.zeros(7, dtype=np.int64)
+        out = np.zeros(8, dtype=np.int64)
         check(lib().lmag_last_plan(self._ctx, out.ctypes.data_as(_lib.c_int64_p)), self._ctx)
         return dict(zip(("total_slices", "total_chunks", "chunk_slices", "grid",
-                         "workspace_bytes", "recompute", "waves"), (int(x) for x in out)))
+                         "workspace_bytes", "recompute", "waves", "sparse_support"),
+                        (int(x) for x in out)))
 
     # --------------------------------------------------------- tile unit ops
     def debug_tile_gemm(self, A, B, transA=False, precision=None):

@@ -38,6 +38,7 @@ def test_recompute_matches_stored(prec):
     F1, g1, p1 = run(cfg, amps, [600], budget, 2, prec)
     assert p0["recompute"] == 0 and p1["recompute"] == 1
     assert p1["grid"] < p0["grid"]
+    assert p0["sparse_support"] > 0   # compact K_n^T shares the tiles the recompute reads
     assert np.array_equal(F0, F1) and np.array_equal(g0, g1)
 
 
