@@ -44,9 +44,9 @@ __device__ __forceinline__ cpx<T>* slot(Shared<T>& sh, cpx<T>* gs) {
 template <typename T, bool TRANS>
 __device__ __forceinline__ void put(const RT<T>& X, cpx<T>* S) { rt_store<T, TRANS>(X, S, PITCH); }
 
-template <typename T>
+template <typename T, bool PIPE = true>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) {
-  gemm_acc<T, false, PITCH>(acc, A, B);
+  gemm_acc<T, false, PITCH, PIPE>(acc, A, B);
 }
 
 template <typename T>
@@ -442,7 +442,7 @@ __device__ __forceinline__ void chain_step(RTW& P, const cpx<T>* Dm) {
   RT<T> Pf, Pn;
   rtw_narrow(Pf, P);
   rt_zero(Pn);
-  mm(Pn, Dm, Pf);
+  mm<T, false>(Pn, Dm, Pf);   // the FP64 running product leaves no room for the pipelined form
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll

@@ -22,7 +22,7 @@
 namespace lmag {
 
 constexpr int TN = 64;        // tile edge (superoperator dimension of the fast path)
-constexpr int PITCH = 66;     // LDS row pitch in complex elements (16-byte row skew)
+constexpr int PITCH = 65;     // LDS row pitch in complex elements (one 8-byte bank pair of skew)
 constexpr int WG = 256;       // threads per workgroup
 
 template <typename T> struct cpx { T re, im; };
@@ -147,34 +147,72 @@ __device__ __forceinline__ void rt_store(const RT<T>& X, cpx<T>* __restrict__ M,
 // acc += alpha-free X * Y where X is read from memory (LDS or global) row-major
 // with pitch PA, in orientation TA (false: X = A, true: X = A^T), and Y is an RT.
 // acc and B must be different register tiles.
-template <typename T, bool TA, int PA>
+// PIPE (single precision): issue the next k-step's A loads ahead of this
+// step's MFMAs and pin that order; off where registers are too tight for it.
+template <typename T, bool TA, int PA, bool PIPE = true>
 __device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ A, const RT<T>& B) {
   const Lane L;
   const int g = L.g, c = L.c;
   if constexpr (sizeof(T) == 4) {
-    // 3M: K1 = (Ar + Ai) Br, Cr += K1 - Ai (Br + Bi), Ci += K1 + Ar (Bi - Br)
+    // 3M: K1 = (Ar + Ai) Br, Cr += K1 - Ai (Br + Bi), Ci += K1 + Ar (Bi - Br).
+    // Software-pipelined over the 16 k-steps (kb, t): the next step's four A
+    // values are requested before this step's 12 MFMAs, which cover the LDS
+    // latency.
     typename vec4<T>::type k1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) k1[q] = typename vec4<T>::type{0.f, 0.f, 0.f, 0.f};
+    auto ld = [&](int st, int q) {
+      const int kb = st >> 2, t = st & 3;
+      return TA ? A[(16 * kb + Sub<T>::row(g, t)) * PA + 16 * q + c]
+                : A[(16 * q + c) * PA + 16 * kb + Sub<T>::row(g, t)];
+    };
+    if constexpr (!PIPE) {
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      cpx<T> a[4][4];
+      for (int kb = 0; kb < 4; ++kb) {
+        cpx<T> a[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          a[q][t] = TA ? A[(16 * kb + Sub<T>::row(g, t)) * PA + 16 * q + c]
-                       : A[(16 * q + c) * PA + 16 * kb + Sub<T>::row(g, t)];
+          for (int t = 0; t < 4; ++t) a[q][t] = ld(4 * kb + t, q);
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const T br = B.re[kb][t], bi = B.im[kb][t];
-        const T nsum = -(br + bi), diff = bi - br;
+        for (int t = 0; t < 4; ++t) {
+          const T br = B.re[kb][t], bi = B.im[kb][t];
+          const T nsum = -(br + bi), diff = bi - br;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          k1[q] = mfma4<T>(a[q][t].re + a[q][t].im, br, k1[q]);
-          acc.re[q] = mfma4<T>(a[q][t].im, nsum, acc.re[q]);
-          acc.im[q] = mfma4<T>(a[q][t].re, diff, acc.im[q]);
+          for (int q = 0; q < 4; ++q) {
+            k1[q] = mfma4<T>(a[q][t].re + a[q][t].im, br, k1[q]);
+            acc.re[q] = mfma4<T>(a[q][t].im, nsum, acc.re[q]);
+            acc.im[q] = mfma4<T>(a[q][t].re, diff, acc.im[q]);
+          }
         }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) { acc.re[q] += k1[q]; acc.im[q] += k1[q]; }
+      return;
+    }
+    cpx<T> cur[4], nxt[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cur[q] = ld(0, q);
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      if (st + 1 < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nxt[q] = ld(st + 1, q);
+      }
+      // keep the scheduler from sinking these loads next to their use
+      __builtin_amdgcn_sched_barrier(0);
+      const T br = B.re[st >> 2][st & 3], bi = B.im[st >> 2][st & 3];
+      const T nsum = -(br + bi), diff = bi - br;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        k1[q] = mfma4<T>(cur[q].re + cur[q].im, br, k1[q]);
+        acc.re[q] = mfma4<T>(cur[q].im, nsum, acc.re[q]);
+        acc.im[q] = mfma4<T>(cur[q].re, diff, acc.im[q]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + 1 < 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
       }
     }
 #pragma unroll
