@@ -15,6 +15,7 @@ in plain numpy float64 / complex128, in the order the paper states it:
 * process fidelity Re Tr(S_T^dagger U) / d^2 against S_T = conj(U_T) (x) U_T;
 * exact adjoint gradient from the block-triangular Frechet derivative, central
   finite differences, and an RK4 integrator of Eq. 9;
+* logical-subspace scores (Eq. 16-17) and the adjoint for any score of U;
 * MLP and Adam references for the learned proposal and the optimiser.
 """
 from .model import (pauli, spin_op, exchange_terms, zeeman_terms, jump_ops,
@@ -24,8 +25,9 @@ from .magnus import gl2_nodes, slice_omegas, slice_omega
 from .expm import expm_taylor, frechet_block
 from .optim import adam_project
 from . import mlp
+from . import logical
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
-                         grad_adjoint, grad_adjoint_at, grad_fd, grad_fd_cached, rk4_propagator,
+                         grad_adjoint, grad_adjoint_at, grad_adjoint_seed, grad_fd, grad_fd_cached, rk4_propagator,
                          slice_products)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

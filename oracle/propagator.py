@@ -133,6 +133,29 @@ def grad_adjoint(system, amps, dt, order, hold, U_target):
     return F, grad
 
 
+def grad_adjoint_seed(system, amps, dt, order, hold, seed_fn):
+    """(s, ds/du) for a score s(U) of the total propagator: seed_fn(U) returns
+    (s, M) with ds = Re Tr(M dU); the adjoint runs as in grad_adjoint with the
+    suffix started from M instead of S_T^dag / d^2."""
+    amps = np.asarray(amps, dtype=float)
+    N = amps.shape[0]
+    oms = system.omegas(amps, dt, order, hold)
+    S = slice_products(oms)
+    n = oms[0].shape[0]
+    X = [np.eye(n, dtype=complex)]
+    for k in range(N):
+        X.append(S[k] @ X[-1])
+    value, Y = seed_fn(X[N])
+    grad = np.zeros_like(amps)
+    for k in range(N - 1, -1, -1):
+        M = X[k] @ Y
+        K = frechet_block(oms[k], M)
+        for (m, c), dom in system.domega(amps, k, dt, order, hold).items():
+            grad[m, c] += float(np.real(np.trace(K @ dom)))
+        Y = Y @ S[k]
+    return value, grad
+
+
 def grad_fd(system, amps, dt, order, hold, U_target, coords, h=1e-4):
     """Central differences of F at flat indices coords of amps (float64)."""
     amps = np.asarray(amps, dtype=float)
