@@ -134,6 +134,30 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx *ctx, const lmag_batch *batch,
                                    const int32_t *target_of_item, double *F_out,
                                    void *grad_out, void *hip_stream);
 
+/* Logical-subspace score of the propagator and (optionally) its gradient
+ * (Sec. III-C, Eq. 16-17). With P the n x L matrix whose columns are the
+ * vectorised (column-stacked) logical operators, every item's U is projected to
+ * Pi = P^dag U P (Eq. 16) and scored:
+ *   LMAG_SCORE_PROJECTED: s = ||Pi - T||_F^2 = Tr((Pi - T)^dag (Pi - T)), the
+ *     Frobenius loss of Eq. 17 (read with the conjugate transpose);
+ *   LMAG_SCORE_LINEAR:    s = Re Tr(T^dag Pi) / L (for the operator basis
+ *     |a><b| of a logical qubit and T = conj(V) (x) V: the gate's process
+ *     fidelity restricted to the logical subspace).
+ * The gradient is that of s (with the fidelity's conventions for groups).
+ * kind:            LMAG_SCORE_PROJECTED or LMAG_SCORE_LINEAR
+ * L:               1..4 logical operators
+ * P:               HOST double [L][n][2] (column k = vec of operator k, complex)
+ * T:               DEVICE [n_targets][L][L] complex128, row-major
+ * target_of_item:  HOST [n_items] in [0, n_targets) or NULL (= target 0)
+ * score_out:       DEVICE double [n_items] (or [n_groups] when grouped)
+ * grad_out:        DEVICE like amps, or NULL for the score only.
+ * Systems with n = d * d <= 64 only (LMAG_E_UNSUPPORTED otherwise). */
+enum { LMAG_SCORE_PROJECTED = 1, LMAG_SCORE_LINEAR = 2 };
+lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, int kind, int L,
+                                        const double *P, const void *T, int n_targets,
+                                        const int32_t *target_of_item, double *score_out,
+                                        void *grad_out, void *hip_stream);
+
 /* Autotuner of the persistent slice kernels: times lmag_fidelity_and_grad on
  * this batch (reps timed calls after one warm-up, HIP events on the stream) for
  * every candidate chunk length (slices per work unit) and the inverse variants

@@ -27,7 +27,7 @@ from .optim import adam_project
 from . import mlp
 from . import logical
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
-                         grad_adjoint, grad_adjoint_at, grad_adjoint_seed, grad_fd, grad_fd_cached, rk4_propagator,
+                         grad_adjoint, grad_adjoint_at, grad_adjoint_seed, grad_adjoint_seed_at, grad_fd, grad_fd_cached, rk4_propagator,
                          slice_products)
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -234,6 +234,34 @@ def grad_adjoint_at(system, amps, dt, order, hold, U_target, slices):
     return F, out
 
 
+def grad_adjoint_seed_at(system, amps, dt, order, hold, seed_fn, slices):
+    """grad_adjoint_seed restricted to the rows in `slices` (as grad_adjoint_at)."""
+    amps = np.asarray(amps, dtype=float)
+    N = amps.shape[0]
+    want = set(int(s) for s in slices)
+    need = set()
+    for s in want:
+        need.add(s)
+        if hold == "foh" and s > 0:
+            need.add(s - 1)
+    oms = system.omegas(amps, dt, order, hold)
+    S = slice_products(oms)
+    n = oms[0].shape[0]
+    X = [np.eye(n, dtype=complex)]
+    for k in range(N):
+        X.append(S[k] @ X[-1])
+    value, Y = seed_fn(X[N])
+    out = {s: np.zeros(amps.shape[1]) for s in want}
+    for k in range(N - 1, -1, -1):
+        if k in need:
+            K = frechet_block(oms[k], X[k] @ Y)
+            for (m, c), dom in system.domega(amps, k, dt, order, hold).items():
+                if m in want:
+                    out[m][c] += float(np.real(np.trace(K @ dom)))
+        Y = Y @ S[k]
+    return value, out
+
+
 def grad_fd_cached(system, amps, dt, order, hold, U_target, coords, h=1e-4):
     """Central differences of F, like grad_fd, for long pulses: a change of row
     m only changes the slices m-1 and m (FOH) or m (ZOH), so F(u +- h e) is the

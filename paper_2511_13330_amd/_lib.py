@@ -19,6 +19,8 @@ LMAG_F32 = 32
 LMAG_F64 = 64
 LMAG_ZOH = 0
 LMAG_FOH = 1
+LMAG_SCORE_PROJECTED = 1
+LMAG_SCORE_LINEAR = 2
 
 STATUS_NAMES = {0: "LMAG_OK", -1: "LMAG_E_INVALID", -2: "LMAG_E_NOSYSTEM",
                 -3: "LMAG_E_NOMEM", -4: "LMAG_E_DEVICE", -5: "LMAG_E_UNSUPPORTED"}
@@ -56,6 +58,8 @@ SIGNATURES = {
     "lmag_propagate": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_void_p]),
     "lmag_fidelity_and_grad": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_int,
                                        c_int32_p, c_void_p, c_void_p, c_void_p]),
+    "lmag_logical_score_and_grad": (c_int, [c_void_p, ctypes.POINTER(Batch), c_int, c_int, c_double_p,
+                                            c_void_p, c_int, c_int32_p, c_void_p, c_void_p, c_void_p]),
     "lmag_sync": (c_int, [c_void_p, c_void_p]),
     "lmag_mlp_forward": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
                                  c_int, ctypes.c_float, c_void_p, c_void_p, c_void_p]),

@@ -119,6 +119,26 @@ struct TargetArgs {
 };
 hipError_t launch_targets(const TargetArgs& a, hipStream_t s);
 
+// Logical-subspace scores: Pi = P^dag U P (L x L) per item, from the item's
+// total U = I + X (stored as X); score s and the seed M (ds = Re Tr(M dU))
+// written where the target tiles go, one per item.
+constexpr int MAX_LOGICAL = 4;
+struct LogicalArgs {
+  int prec;
+  const Item* items;
+  int n_items;
+  const void* pre;          // inclusive prefixes (X = U - I at each item's last chunk)
+  int kind;                 // 1: ||Pi - T||_F^2, 2: Re Tr(T^dag Pi) / L
+  int L;
+  const double* P;          // [64][L] complex, row i = superoperator index
+  const double* T;          // [n_targets][L][L] complex, row-major
+  double* score;            // out, indexed like EnvArgs::F (f_by_src)
+  int f_by_src;
+  double* st64;             // out [n_items][64][64] complex seed M
+  float* st32;              // out, same in float (may be null)
+};
+hipError_t launch_logical(const LogicalArgs& a, hipStream_t s);
+
 struct ScanArgs {
   int prec;
   const Item* items;
@@ -144,6 +164,7 @@ struct EnvArgs {
   double* F;                // out (Re), may be null
   double* Fim;              // out (Im), may be null
   int f_by_src;             // index F / Fim by the caller's item index
+  int seed_by_item;         // st tiles are per item (logical scores), not per target
   int d;
 };
 hipError_t launch_env(const EnvArgs& a, hipStream_t s);

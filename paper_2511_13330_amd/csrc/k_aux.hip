@@ -270,10 +270,11 @@ template <typename T> __global__ void __launch_bounds__(WG) k_env(EnvArgs a) {
   const int lc = cidx - it.first_chunk, Lc = it.n_chunks;
   const cpx<T>* pre = (const cpx<T>*)a.pre;
   const cpx<T>* suf = (const cpx<T>*)a.suf;
-  const cpx<T>* st = (const cpx<T>*)a.st + (size_t)it.target * TILE;
+  const int tix = a.seed_by_item ? itn : it.target;
+  const cpx<T>* st = (const cpx<T>*)a.st + (size_t)tix * TILE;
   if (lc == 0 && (a.F || a.Fim)) {
     const cpx<T>* U = pre + (size_t)(it.first_chunk + Lc - 1) * TILE;
-    const cpx<double>* S = (const cpx<double>*)a.st64 + (size_t)it.target * TILE;
+    const cpx<double>* S = (const cpx<double>*)a.st64 + (size_t)tix * TILE;
     double re = 0.0, im = 0.0;
     for (int i = threadIdx.x; i < TILE; i += WG) {
       const int r = i / 64, c = i % 64;
@@ -328,6 +329,98 @@ hipError_t launch_env(const EnvArgs& a, hipStream_t s) {
   if (a.n_chunks_total <= 0) return hipSuccess;
   if (a.prec == 32) hipLaunchKernelGGL(k_env<float>, dim3(a.n_chunks_total), dim3(WG), 0, s, a);
   else hipLaunchKernelGGL(k_env<double>, dim3(a.n_chunks_total), dim3(WG), 0, s, a);
+  return hipGetLastError();
+}
+
+// Logical-subspace score of one item per workgroup, in FP64 from the item's
+// total U = I + X: Y = U P = P + X P (64 x L), Pi = P^dag Y, then
+//   kind 1: D = Pi - T, s = Tr(D^dag D), C = 2 D^dag;
+//   kind 2: s = Re Tr(T^dag Pi) / L, C = T^dag / L;
+// and the seed M = P C P^dag (ds = Re Tr(M dU)) into the item's tile.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_logical(LogicalArgs a) {
+  __shared__ cpx<double> Y[64][MAX_LOGICAL], Q[64][MAX_LOGICAL], Pi[MAX_LOGICAL][MAX_LOGICAL],
+      C[MAX_LOGICAL][MAX_LOGICAL];
+  const int itn = blockIdx.x, tid = threadIdx.x, L = a.L;
+  const Item it = a.items[itn];
+  const cpx<T>* X = (const cpx<T>*)a.pre + (size_t)(it.first_chunk + it.n_chunks - 1) * TILE;
+  const cpx<double>* P = (const cpx<double>*)a.P;
+  const cpx<double>* Tt = (const cpx<double>*)a.T + (size_t)it.target * L * L;
+  {
+    const int i = tid & 63, k = tid >> 6;
+    if (k < L) {
+      cpx<double> y = P[i * L + k];
+      for (int j = 0; j < 64; ++j) {
+        const cpx<T> x = X[i * 64 + j];
+        const cpx<double> p = P[j * L + k];
+        y.re += (double)x.re * p.re - (double)x.im * p.im;
+        y.im += (double)x.re * p.im + (double)x.im * p.re;
+      }
+      Y[i][k] = y;
+    }
+  }
+  __syncthreads();
+  if (tid < L * L) {
+    const int r = tid / L, c = tid % L;
+    cpx<double> z{0.0, 0.0};
+    for (int i = 0; i < 64; ++i) {
+      const cpx<double> p = P[i * L + r], y = Y[i][c];
+      z.re += p.re * y.re + p.im * y.im;     // conj(p) y
+      z.im += p.re * y.im - p.im * y.re;
+    }
+    Pi[r][c] = z;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sc = 0.0;
+    for (int r = 0; r < L; ++r)
+      for (int c = 0; c < L; ++c) {
+        const cpx<double> t = Tt[r * L + c], p = Pi[r][c];
+        if (a.kind == 1) {
+          const double dr = p.re - t.re, di = p.im - t.im;
+          sc += dr * dr + di * di;
+          C[c][r] = cpx<double>{2.0 * dr, -2.0 * di};          // 2 D^dag
+        } else {
+          sc += t.re * p.re + t.im * p.im;                     // Re conj(t) p
+          C[c][r] = cpx<double>{t.re / L, -t.im / L};          // T^dag / L
+        }
+      }
+    if (a.kind == 2) sc /= L;
+    a.score[a.f_by_src ? it.src : itn] = sc;
+  }
+  __syncthreads();
+  {
+    const int i = tid & 63, k = tid >> 6;    // Q = P C
+    if (k < L) {
+      cpx<double> q{0.0, 0.0};
+      for (int b = 0; b < L; ++b) {
+        const cpx<double> p = P[i * L + b], c = C[b][k];
+        q.re += p.re * c.re - p.im * c.im;
+        q.im += p.re * c.im + p.im * c.re;
+      }
+      Q[i][k] = q;
+    }
+  }
+  __syncthreads();
+  cpx<double>* M64 = (cpx<double>*)a.st64 + (size_t)itn * TILE;
+  cpx<float>* M32 = a.st32 ? (cpx<float>*)a.st32 + (size_t)itn * TILE : nullptr;
+  for (int e = tid; e < TILE; e += WG) {
+    const int i = e / 64, j = e % 64;
+    cpx<double> m{0.0, 0.0};
+    for (int b = 0; b < L; ++b) {            // Q[i][b] conj(P[j][b])
+      const cpx<double> q = Q[i][b], p = P[j * L + b];
+      m.re += q.re * p.re + q.im * p.im;
+      m.im += q.im * p.re - q.re * p.im;
+    }
+    M64[e] = m;
+    if (M32) M32[e] = cpx<float>{(float)m.re, (float)m.im};
+  }
+}
+
+hipError_t launch_logical(const LogicalArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (a.prec == 32) hipLaunchKernelGGL(k_logical<float>, dim3(a.n_items), dim3(WG), 0, s, a);
+  else hipLaunchKernelGGL(k_logical<double>, dim3(a.n_items), dim3(WG), 0, s, a);
   return hipGetLastError();
 }
 

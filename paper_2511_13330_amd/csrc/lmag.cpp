@@ -67,6 +67,9 @@ struct lmag_ctx {
   void* basis32 = nullptr;
   void* sp_dev = nullptr;     // sparse basis tables (64 x 64 path), see build_sparse
   SparseBasis sp{};
+  // logical-subspace score of the current call (0: process fidelity)
+  int score_kind = 0, score_L = 0;
+  double* logP_dev = nullptr;   // [64][MAX_LOGICAL] complex
   // workspace
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -267,8 +270,10 @@ Layout layout(const lmag_ctx* c, const Plan& p, int n_targets, bool grad, int gr
   L.ms = take((size_t)p.total_slices * 2);
   L.nlev = take((size_t)p.total_slices);
   L.F_items = take(p.items.size() * 8);
-  L.st64 = take((size_t)std::max(1, n_targets) * TILE * 16);
-  L.st = take((size_t)std::max(1, n_targets) * tile);
+  // target tiles, or one seed tile per item for a logical-subspace score
+  const int n_st = std::max(1, c->score_kind ? std::max(n_targets, (int)p.items.size()) : n_targets);
+  L.st64 = take((size_t)n_st * TILE * 16);
+  L.st = take((size_t)n_st * tile);
   L.totals = take((size_t)p.total_chunks * tile);
   L.pre[0] = take((size_t)p.total_chunks * tile);
   L.pre[1] = take((size_t)p.total_chunks * tile);
@@ -444,22 +449,31 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   }
   if (!fidelity) return LMAG_OK;
 
-  TargetArgs ta{};
-  ta.U = (const double*)U_target; ta.n_targets = n_targets; ta.d = c->d;
-  ta.st64 = (double*)at(L.st64);
-  ta.st32 = c->prec == 32 ? (float*)at(L.st) : nullptr;
-  HIPCHK(launch_targets(ta, s), "targets");
-  const void* st_tiles = c->prec == 32 ? at(L.st) : at(L.st64);
-
   const bool grouped = p.n_groups > 0;
   double* F_items = grouped ? (double*)at(L.F_items) : F_out;
+  if (c->score_kind) {
+    // logical-subspace score: Pi, score and the per-item seed from each total
+    LogicalArgs la{};
+    la.prec = c->prec; la.items = items; la.n_items = (int)p.items.size(); la.pre = pre_cur;
+    la.kind = c->score_kind; la.L = c->score_L; la.P = c->logP_dev; la.T = (const double*)U_target;
+    la.score = F_items; la.f_by_src = grouped ? 0 : 1;
+    la.st64 = (double*)at(L.st64); la.st32 = c->prec == 32 ? (float*)at(L.st) : nullptr;
+    { StageTimer t(c, 4, s); HIPCHK(launch_logical(la, s), "logical score"); }
+  } else {
+    TargetArgs ta{};
+    ta.U = (const double*)U_target; ta.n_targets = n_targets; ta.d = c->d;
+    ta.st64 = (double*)at(L.st64);
+    ta.st32 = c->prec == 32 ? (float*)at(L.st) : nullptr;
+    HIPCHK(launch_targets(ta, s), "targets");
+  }
+  const void* st_tiles = c->prec == 32 ? at(L.st) : at(L.st64);
   EnvArgs ev{};
   ev.prec = c->prec; ev.items = items; ev.n_items = (int)p.items.size();
   ev.chunk_item = (const int32_t*)at(L.chunk_item); ev.n_chunks_total = p.total_chunks;
   ev.pre = pre_cur; ev.suf = suf_cur; ev.st = st_tiles; ev.st64 = (const double*)at(L.st64);
-  ev.env = grad ? at(L.env) : nullptr; ev.F = F_items; ev.Fim = nullptr; ev.d = c->d;
-  ev.f_by_src = grouped ? 0 : 1;
-  { StageTimer t(c, 4, s); HIPCHK(launch_env(ev, s), "env"); }
+  ev.env = grad ? at(L.env) : nullptr; ev.F = c->score_kind ? nullptr : F_items; ev.Fim = nullptr;
+  ev.d = c->d; ev.f_by_src = grouped ? 0 : 1; ev.seed_by_item = c->score_kind ? 1 : 0;
+  if (grad || !c->score_kind) { StageTimer t(c, 4, s); HIPCHK(launch_env(ev, s), "env"); }
 
   if (grad) {
     HIPCHK(launch_fill_int((int*)at(L.counters) + 16, 0, 16, s), "fill");
@@ -473,7 +487,8 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     ga.amps = b->amps; ga.item_amp_offset = (const int64_t*)at(L.amp_off); ga.items = items;
     ga.n_items = (int)p.items.size(); ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
     ga.n_ctrl = c->nc; ga.n_static = c->ns; ga.order = c->order; ga.hold_foh = c->hold == LMAG_FOH;
-    ga.nb = c->nb; ga.dt = b->dt; ga.inv_d2 = 1.0 / ((double)c->d * c->d);
+    ga.nb = c->nb; ga.dt = b->dt;
+    ga.inv_d2 = c->score_kind ? 1.0 : 1.0 / ((double)c->d * c->d);   // the seed carries its scale
     ga.grad = grad ? grad_out : nullptr;
     ga.group_first_item = grouped ? (const int32_t*)at(L.group_first) : nullptr;
     ga.group_items = grouped ? (const int32_t*)at(L.group_items) : nullptr;
@@ -1141,6 +1156,7 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->basis64) (void)hipFree(c->basis64);
   if (c->basis32) (void)hipFree(c->basis32);
   if (c->sp_dev) (void)hipFree(c->sp_dev);
+  if (c->logP_dev) (void)hipFree(c->logP_dev);
   if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
   if (c->clk_dev) (void)hipFree(c->clk_dev);
   if (c->mse_part) (void)hipFree(c->mse_part);
@@ -1529,6 +1545,52 @@ lmag_status lmag_cast_bf16(lmag_ctx* c, const float* in, uint16_t* out, int64_t 
   DeviceGuard g(c->device);
   HIPCHK(launch_cast_bf16(in, out, n, (hipStream_t)hip_stream), "cast_bf16");
   return LMAG_OK;
+}
+
+lmag_status lmag_logical_score_and_grad(lmag_ctx* c, const lmag_batch* b, int kind, int L,
+                                        const double* P, const void* T, int n_targets,
+                                        const int32_t* target_of_item, double* score_out,
+                                        void* grad_out, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  try {
+    if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
+    if (kind != LMAG_SCORE_PROJECTED && kind != LMAG_SCORE_LINEAR)
+      return c->fail(LMAG_E_INVALID, "unknown score kind");
+    if (L < 1 || L > MAX_LOGICAL) return c->fail(LMAG_E_INVALID, "L must be 1..4");
+    if (!P || !T || n_targets < 1) return c->fail(LMAG_E_INVALID, "P or T NULL, or n_targets < 1");
+    if (!score_out) return c->fail(LMAG_E_INVALID, "score_out is NULL");
+    if (c->n > 64) return c->fail(LMAG_E_UNSUPPORTED, "logical scores need d * d <= 64");
+    if (!finite_array(P, (size_t)c->n * L * 2)) return c->fail(LMAG_E_INVALID, "non-finite P");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    c->last_stream = s;
+    if (!c->logP_dev) {
+      hipError_t e = hipMalloc((void**)&c->logP_dev, (size_t)64 * MAX_LOGICAL * 16);
+      if (e != hipSuccess) { c->logP_dev = nullptr; return c->hip_fail(e, "hipMalloc(P)"); }
+    }
+    // P arrives column by column (n x L); the kernel reads [64][L] rows, zero padded
+    std::vector<double> h((size_t)64 * L * 2, 0.0);
+    for (int k = 0; k < L; ++k)
+      for (int i = 0; i < c->n; ++i) {
+        h[((size_t)i * L + k) * 2] = P[((size_t)k * c->n + i) * 2];
+        h[((size_t)i * L + k) * 2 + 1] = P[((size_t)k * c->n + i) * 2 + 1];
+      }
+    HIPCHK(hipMemcpyAsync(c->logP_dev, h.data(), h.size() * 8, hipMemcpyHostToDevice, s), "P upload");
+    HIPCHK(hipStreamSynchronize(s), "P upload");
+    c->score_kind = kind;
+    c->score_L = L;
+    const lmag_status st = run_waves(c, b, target_of_item, n_targets, grad_out != nullptr, true, T,
+                                     score_out, grad_out, nullptr, s);
+    c->score_kind = 0;
+    c->score_L = 0;
+    return st;
+  } catch (const std::bad_alloc&) {
+    c->score_kind = 0;
+    return c->fail(LMAG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    c->score_kind = 0;
+    return c->fail(LMAG_E_DEVICE, "unknown error");
+  }
 }
 
 lmag_status lmag_sync(lmag_ctx* c, void* hip_stream) {

@@ -133,6 +133,39 @@ class System:
             _stream(stream)), self._ctx)
         return F, grad
 
+    def logical_score_and_grad(self, amps, n_slices, dt, P, T, kind="projected",
+                               slice_offset=None, static_coef=None, ctrl_scale=None,
+                               target_of_item=None, groups=None, want_grad=True, stream=None):
+        """Logical-subspace score (lmag_logical_score_and_grad): P [n, L] complex
+        (columns: vectorised logical operators), T [n_targets, L, L] complex,
+        kind "projected" (||P^dag U P - T||_F^2) or "linear" (Re Tr(T^dag Pi) / L).
+        Returns (score [n_items or n_groups] float64, d score/du like amps or None)."""
+        b, keep, n_items, ng = self._batch(amps, n_slices, slice_offset, dt, static_coef,
+                                           ctrl_scale, groups)
+        Pm = np.asarray(P, dtype=np.complex128)
+        if Pm.ndim != 2 or Pm.shape[0] != self.n:
+            raise ValueError(f"P must be [{self.n}, L]")
+        L = Pm.shape[1]
+        Ph = np.ascontiguousarray(Pm.T)   # [L][n] complex = [L][n][2] doubles
+        keep.append(Ph)
+        Td = torch.as_tensor(np.asarray(T, dtype=np.complex128), device=self.device)
+        Td = Td.reshape(-1, L, L).contiguous()
+        tp = None
+        if target_of_item is not None:
+            toi = np.ascontiguousarray(target_of_item, dtype=np.int32).reshape(-1)
+            keep.append(toi)
+            tp = toi.ctypes.data_as(_lib.c_int32_p)
+        kinds = {"projected": _lib.LMAG_SCORE_PROJECTED, "linear": _lib.LMAG_SCORE_LINEAR}
+        S = torch.empty(ng if ng else n_items, dtype=torch.float64, device=self.device)
+        grad = torch.empty_like(amps) if want_grad else None
+        check(lib().lmag_logical_score_and_grad(
+            self._ctx, ctypes.byref(b), kinds[kind], L,
+            Ph.ctypes.data_as(_lib.c_double_p), ctypes.c_void_p(Td.data_ptr()), Td.shape[0], tp,
+            ctypes.c_void_p(S.data_ptr()),
+            ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
+            _stream(stream)), self._ctx)
+        return S, grad
+
     def adam_project(self, amps, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
                      grad_scale=-1.0, lo=0.0, hi=float("inf"), row_active=None, stream=None):
         """In-place Adam + projection step of the library (lmag_adam_project)."""

@@ -101,3 +101,15 @@ def test_seed_adjoint_matches_finite_differences(kind, proj):
         e[m, c] = h
         fd = (f(amps + e) - f(amps - e)) / (2 * h)
         assert abs(fd - g[m, c]) < 1e-6 * max(1.0, abs(fd)), (m, c, fd, g[m, c])
+
+
+def test_seed_adjoint_at_sampled_rows_matches_full():
+    cfg = synth.small_case(12, n_slices=9, dt=2.5e-4)
+    osys = oracle_system(cfg)
+    P, T = lg.populations_projector(), lg.populations_target(haar2(13))
+    fn = lambda U: lg.score(U, P, T, "projected")
+    v0, g0 = oracle.grad_adjoint_seed(osys, cfg["amps"], cfg["dt"], 2, "foh", fn)
+    v1, g1 = oracle.grad_adjoint_seed_at(osys, cfg["amps"], cfg["dt"], 2, "foh", fn, [0, 4, 8])
+    assert v0 == v1
+    for r in (0, 4, 8):
+        assert np.allclose(g1[r], g0[r], rtol=1e-13, atol=1e-16)
