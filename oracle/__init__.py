@@ -16,6 +16,7 @@ in plain numpy float64 / complex128, in the order the paper states it:
 * exact adjoint gradient from the block-triangular Frechet derivative, central
   finite differences, and an RK4 integrator of Eq. 9;
 * logical-subspace scores (Eq. 16-17) and the adjoint for any score of U;
+* RK4 evolution of a state and the Uhlmann fidelity (the accuracy study);
 * MLP and Adam references for the learned proposal and the optimiser.
 """
 from .model import (pauli, spin_op, exchange_terms, zeeman_terms, jump_ops,
@@ -26,6 +27,7 @@ from .expm import expm_taylor, frechet_block
 from .optim import adam_project
 from . import mlp
 from . import logical
+from . import states
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
                          grad_adjoint, grad_adjoint_at, grad_adjoint_seed, grad_adjoint_seed_at, grad_fd, grad_fd_cached, rk4_propagator,
                          slice_products)

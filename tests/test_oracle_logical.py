@@ -113,3 +113,38 @@ def test_seed_adjoint_at_sampled_rows_matches_full():
     assert v0 == v1
     for r in (0, 4, 8):
         assert np.allclose(g1[r], g0[r], rtol=1e-13, atol=1e-16)
+
+
+# ------------------------------------------------ state-level reference
+def test_uhlmann_closed_forms():
+    from oracle import states as st
+    rng = np.random.default_rng(20)
+    psi = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+    phi = rng.standard_normal(8) + 1j * rng.standard_normal(8)
+    psi /= np.linalg.norm(psi)
+    phi /= np.linalg.norm(phi)
+    F = st.uhlmann(np.outer(psi, psi.conj()) + 0 * 1e-300, np.outer(phi, phi.conj()))
+    assert abs(F - abs(np.vdot(psi, phi)) ** 2) < 1e-8          # sqrtm of a rank-1 matrix
+    p = rng.random(8); p /= p.sum()
+    q = rng.random(8); q /= q.sum()
+    assert abs(st.uhlmann(np.diag(p), np.diag(q)) - np.sum(np.sqrt(p * q)) ** 2) < 1e-13
+    rho = st.random_density(8, rng)
+    assert abs(st.uhlmann(rho, rho) - 1.0) < 1e-12
+
+
+def test_rk4_state_constant_control_is_the_exponential():
+    from oracle import states as st
+    cfg = synth.small_case(21, n_slices=4)
+    osys = oracle_system(cfg)
+    u = np.array([2 * np.pi * 7.0, 2 * np.pi * 3.0])
+    rho0 = st.random_density(8, np.random.default_rng(22))
+    T = 0.05
+    ref = oracle.unvec(sla_expm(T * osys.liouv(u)) @ oracle.vec(rho0), 8)
+    e1 = np.abs(st.rk4_state(osys, lambda t: u, T, 200, rho0) - ref).max()
+    e2 = np.abs(st.rk4_state(osys, lambda t: u, T, 400, rho0) - ref).max()
+    assert e2 < 1e-10 and 12.0 < e1 / e2 < 20.0     # fourth order: halving h divides by 16
+
+
+def sla_expm(A):
+    import scipy.linalg
+    return scipy.linalg.expm(A)
