@@ -137,7 +137,8 @@ def record_traffic(fetch_csv, write_csv, slices, copy_bytes):
             raise SystemExit(f"{path}: no calibration copy dispatch found")
         scales[counter] = kib / max(copies)
         for name, vals in rows.items():
-            for kern in ("k_forward", "k_backward", "k_omega", "k_traces"):
+            for kern in ("k_forward", "k_backward", "k_omega", "k_traces", "k_omega_sparse",
+                         "k_traces_sparse"):
                 if f"lmag::{kern}<" in name:
                     out.setdefault(kern, {})[counter] = float(np.mean(vals))
     h = hashlib.sha256()
