@@ -27,7 +27,7 @@ METRIC = ("fwd+grad pulse evals/s (3-spin, 4096 slices) & MFMA util, "
 PEAK_FP32_MFMA_TFLOPS = 157.3
 N_SUPER = 64
 M_FLOPS = 8.0 * N_SUPER ** 3          # one complex 64x64x64 product, real flops
-PI_M = {3: 2, 5: 3, 7: 4}             # products to evaluate the Pade-m numerator/denominator
+PI_M = {2: 1, 3: 2, 5: 3, 7: 4}       # products to evaluate the Pade-m numerator/denominator
 
 
 def forward_flops_per_slice(m, s):
@@ -42,7 +42,7 @@ def backward_flops_per_slice(m, s):
 
 def flops_from_hist(hist, per_slice):
     tot = 0.0
-    for mi, m in enumerate((3, 5, 7)):
+    for mi, m in enumerate((2, 3, 5, 7)):
         for s in range(hist.shape[1]):
             if hist[mi, s]:
                 tot += hist[mi, s] * per_slice(m, s)
@@ -241,7 +241,7 @@ def large_system(args):
     n = 4 ** cfg["n_spins"]
     Mf = 8.0 * n ** 3
     flops = 0.0
-    for mi, m in enumerate((3, 5, 7)):
+    for mi, m in enumerate((2, 3, 5, 7)):
         for s in range(hist.shape[1]):
             if hist[mi, s]:
                 flops += hist[mi, s] * (3 * PI_M[m] + 3 * s + 19.0 / 3.0) * Mf

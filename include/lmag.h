@@ -230,16 +230,16 @@ lmag_status lmag_cast_bf16(lmag_ctx *ctx, const float *in, uint16_t *out, int64_
                            void *hip_stream);
 
 /* Host-only queries (no device needed). */
-/* Pade coefficients b_0..b_m of r_m = p_m / p_m(-x), m in {3, 5, 7}. */
+/* Pade coefficients b_0..b_m of r_m = p_m / p_m(-x), m in {2, 3, 5, 7}. */
 lmag_status lmag_pade_coefficients(int m, double *b_out);
-/* theta_m used for scaling selection: precision LMAG_F32 (m = 3) or
- * LMAG_F64 (m in {3, 5, 7}). */
+/* theta_m used for degree and scaling selection: precision LMAG_F32 (m in
+ * {2, 3}) or LMAG_F64 (m in {3, 5, 7}). */
 lmag_status lmag_pade_theta(int precision, int m, double *theta_out);
 
 /* Histogram of the (m, s) selections of the last forward pass of this context:
- * counts[m_index * 64 + s], m_index 0/1/2 for m = 3/5/7. Blocks (syncs the
+ * counts[m_index * 64 + s], m_index 0/1/2/3 for m = 2/3/5/7. Blocks (syncs the
  * stream of the last call). */
-lmag_status lmag_last_selection_histogram(lmag_ctx *ctx, int64_t *counts_out /*[3*64]*/);
+lmag_status lmag_last_selection_histogram(lmag_ctx *ctx, int64_t *counts_out /*[4*64]*/);
 
 /* Per-stage kernel timers measured with HIP events recorded on the caller's
  * stream around every launch (the stream the kernels run on). Stages:

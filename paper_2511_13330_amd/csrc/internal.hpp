@@ -9,8 +9,8 @@ namespace lmag {
 // Pade coefficients b_j = (2m-j)! m! / ((2m)! j! (m-j)!), j = 0..m, and the
 // scaling thresholds theta_m, for the degrees this library evaluates.
 struct PadeTable {
-  double b3[4], b5[6], b7[8];
-  double ser_max32;         // largest ||A||_1 for the degree-5 series of 1/q_3 (FP32)
+  double b2[3], b3[4], b5[6], b7[8];
+  double ser_max32_2, ser_max32_3;   // largest ||A||_1 for the series inverse of q_2, q_3 (FP32)
 };
 
 // Sparse form of a 64 x 64 basis (built by set_system from its nonzero entries

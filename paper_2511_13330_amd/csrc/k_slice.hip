@@ -51,7 +51,7 @@ __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) 
 
 template <typename T>
 __device__ __forceinline__ const double* pade_b(const PadeTable& pt, int m) {
-  return m == 3 ? pt.b3 : (m == 5 ? pt.b5 : pt.b7);
+  return m == 2 ? pt.b2 : (m == 3 ? pt.b3 : (m == 5 ? pt.b5 : pt.b7));
 }
 
 template <typename T> __device__ __forceinline__ cpx<T>* tile_at(void* base, size_t idx) {
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
         a.ms[2 * (size_t)n + 1] = (int8_t)sc;
         if (a.nlev)
           a.nlev[n] = (int8_t)inverse_code<T>(ldexp(v, -sc), pade_b<T>(a.pade, m), m, a.inv_mode != 2,
-                                              a.pade.ser_max32);
+                                              a.pade.ser_max32_2, a.pade.ser_max32_3);
       }
     }
     __syncthreads();
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(WG) k_omega_sparse(SliceArgs a, int n_total) {
     a.ms[2 * (size_t)n + 1] = (int8_t)sc;
     if (a.nlev)
       a.nlev[n] = (int8_t)inverse_code<T>(ldexp(cs, -sc), pade_b<T>(a.pade, m), m, a.inv_mode != 2,
-                                          a.pade.ser_max32);
+                                          a.pade.ser_max32_2, a.pade.ser_max32_3);
   }
   const T f = (T)ldexp(1.0, -sc);
   cpx<T>* out = tile_at<T>(a.omega, (size_t)n);
@@ -305,11 +305,20 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   rt_zero(A2);
   mm(A2, slot<T, 0>(sh, gs), A);
   ck.mark(1);
-  if (st) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
-  RT<T> W, V;   // V holds the even part minus I
+  if (st && !(sizeof(T) == 4 && m == 2))   // the Pade-2 adjoint does not read A^2
+    rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
+  RT<T> V;   // the even part minus I
+  RT<T> U;   // the odd part
+  if (sizeof(T) == 4 && m == 2) {
+    // Pade-2: U = b_1 A (from the copy in LDS), V - I = b_2 A^2, no product
+    rt_poly1(V, A2, (T)b[2], T(0));
+    rt_load<T, false>(U, slot<T, 0>(sh, gs), PITCH);
+    rt_scale(U, (T)b[1]);
+  } else {
+  RT<T> W;
   rt_poly1(W, A2, (T)b[3], (T)b[1]);
   rt_poly1(V, A2, (T)b[2], T(0));
-  if (sizeof(T) == 8 && m >= 5) {   // single precision uses m = 3 only
+  if (sizeof(T) == 8 && m >= 5) {   // single precision uses m in {2, 3} only
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
     RT<T> A4;
@@ -325,9 +334,9 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
       rt_axpy(V, (T)b[6], A6);
     }
   }
-  RT<T> U;
   rt_zero(U);
   mm(U, slot<T, 0>(sh, gs), W);
+  }
   // P = I + X_P with X_P = (V - I) + U (in U); Q = I + E_Q with E_Q = (V - I) - U (in V)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -339,10 +348,11 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   // X_Q = Q^{-1} - I into V
   const int K = a.nlev ? a.nlev[n] : 0;
   if (sizeof(T) == 4 && K >= 16) {
-    // Q^{-1} = sum_{k<=5} c_k A^k = even(A^2) + A odd(A^2), the power series of
-    // 1/q_3 (its tail is below the unit roundoff by the selection rule); c_0 = 1
+    // Q^{-1} = sum_{k<=D} c_k A^k = even(A^2) + A odd(A^2), the power series of
+    // 1/q_m (D = K - 16; its tail is below the unit roundoff by the selection
+    // rule); c_0 = 1, and for m = 2 (D = 4) c_5 = 0 anyway
     double c[8];
-    inv_series(b, 3, c, 8);
+    inv_series(b, m, c, 8);
     __syncthreads();
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
@@ -351,7 +361,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
     mm(A4, slot<T, 1>(sh, gs), A2);
     RT<T> odd;
     rt_poly1(odd, A2, (T)c[3], (T)c[1]);
-    rt_axpy(odd, (T)c[5], A4);
+    if (K - 16 >= 5) rt_axpy(odd, (T)c[5], A4);
     rt_poly1(V, A2, (T)c[2], T(0));
     rt_axpy(V, (T)c[4], A4);
     mm(V, slot<T, 0>(sh, gs), odd);   // X_Q = even - I + A odd
@@ -547,7 +557,10 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
   mm(L2, slot<T, 1>(sh, gs), A);
   ck.mark(3);
   RT<T> W, LW, LV;
-  {
+  const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
+  if (pade2) {
+    rt_poly1(LV, L2, (T)b[2], T(0));
+  } else {
     RT<T> A2;
     rt_load<T, true>(A2, ws + WS_A2 * TILE, 64);
     rt_poly1(W, A2, (T)b[3], (T)b[1]);
@@ -579,12 +592,17 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
       }
     }
   }
-  // L_U = A L_W + E W
+  // L_U = A L_W + E W (Pade-2: b_1 E, E from its copy in LDS)
   ck.mark(4);
   RT<T> LU;
-  rt_zero(LU);
-  mm(LU, slot<T, 0>(sh, gs), LW);
-  mm(LU, slot<T, 1>(sh, gs), W);
+  if (pade2) {
+    rt_load<T, false>(LU, slot<T, 1>(sh, gs), PITCH);
+    rt_scale(LU, (T)b[1]);
+  } else {
+    rt_zero(LU);
+    mm(LU, slot<T, 0>(sh, gs), LW);
+    mm(LU, slot<T, 1>(sh, gs), W);
+  }
   ck.mark(5);
   // L_Q = L_V - L_U (into LW), L_P = L_V + L_U (into LU)
 #pragma unroll

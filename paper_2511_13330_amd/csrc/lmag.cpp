@@ -36,7 +36,7 @@ void pade_coeffs(int m, double* b) {
     b[j] = fact(2 * m - j) * fact(m) / (fact(2 * m) * fact(j) * fact(m - j));
 }
 
-const double kTheta32_3 = 4.258730016922831e-1;
+const double kTheta32_2 = 8.093024022188482e-2, kTheta32_3 = 4.258730016922831e-1;
 const double kTheta64[3] = {1.495585217958292e-2, 2.539398330063230e-1, 9.504178996162932e-1};
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -1140,7 +1140,9 @@ lmag_status lmag_create(lmag_ctx** out, int hip_device) {
     pade_coeffs(3, c->pade.b3);
     pade_coeffs(5, c->pade.b5);
     pade_coeffs(7, c->pade.b7);
-    c->pade.ser_max32 = series_limit32(c->pade.b3);
+    pade_coeffs(2, c->pade.b2);
+    c->pade.ser_max32_2 = series_limit32(c->pade.b2, 2, series_degree(2));
+    c->pade.ser_max32_3 = series_limit32(c->pade.b3, 3, series_degree(3));
     *out = c;
     return LMAG_OK;
   } catch (...) {
@@ -1604,7 +1606,7 @@ lmag_status lmag_sync(lmag_ctx* c, void* hip_stream) {
 }
 
 lmag_status lmag_pade_coefficients(int m, double* b_out) {
-  if (!b_out || (m != 3 && m != 5 && m != 7)) return LMAG_E_INVALID;
+  if (!b_out || (m != 2 && m != 3 && m != 5 && m != 7)) return LMAG_E_INVALID;
   pade_coeffs(m, b_out);
   return LMAG_OK;
 }
@@ -1612,8 +1614,8 @@ lmag_status lmag_pade_coefficients(int m, double* b_out) {
 lmag_status lmag_pade_theta(int precision, int m, double* theta_out) {
   if (!theta_out) return LMAG_E_INVALID;
   if (precision == LMAG_F32) {
-    if (m != 3) return LMAG_E_INVALID;
-    *theta_out = kTheta32_3;
+    if (m != 2 && m != 3) return LMAG_E_INVALID;
+    *theta_out = m == 2 ? kTheta32_2 : kTheta32_3;
     return LMAG_OK;
   }
   if (precision == LMAG_F64) {
@@ -1630,7 +1632,7 @@ lmag_status lmag_last_selection_histogram(lmag_ctx* c, int64_t* counts) {
   if (!c) return LMAG_E_INVALID;
   if (!counts) return c->fail(LMAG_E_INVALID, "counts is NULL");
   DeviceGuard g(c->device);
-  std::memset(counts, 0, sizeof(int64_t) * 3 * 64);
+  std::memset(counts, 0, sizeof(int64_t) * 4 * 64);
   if (!c->last_ms || c->last_total_slices <= 0) return LMAG_OK;
   std::vector<int8_t> h((size_t)c->last_total_slices * 2);
   hipError_t e = hipStreamSynchronize(c->last_stream);
@@ -1639,7 +1641,7 @@ lmag_status lmag_last_selection_histogram(lmag_ctx* c, int64_t* counts) {
   if (e != hipSuccess) return c->hip_fail(e, "hipMemcpy(ms)");
   for (int i = 0; i < c->last_total_slices; ++i) {
     const int m = h[2 * i], s = h[2 * i + 1];
-    const int mi = m == 3 ? 0 : (m == 5 ? 1 : (m == 7 ? 2 : -1));
+    const int mi = m == 2 ? 0 : (m == 3 ? 1 : (m == 5 ? 2 : (m == 7 ? 3 : -1)));
     if (mi >= 0 && s >= 0 && s < 64) counts[mi * 64 + s]++;
   }
   return LMAG_OK;

@@ -6,9 +6,12 @@
 namespace lmag {
 
 // theta_m (Higham 2005): largest ||A||_1 with backward error of r_m below the
-// unit roundoff. Single precision uses m = 3 only; double uses m in {3, 5, 7}.
-// For these (m, theta) the denominator q_m(A) is column diagonally dominant
-// (sum_j>=1 b_j theta^j < 1), so Gauss-Jordan needs no pivoting.
+// unit roundoff. Single precision uses m in {2, 3} (Pade-2 needs one product
+// fewer than Pade-3 and covers the short slices of the spin workloads);
+// double uses m in {3, 5, 7}. For these (m, theta) the denominator q_m(A) is
+// column diagonally dominant (sum_j>=1 b_j theta^j < 1), so Gauss-Jordan needs
+// no pivoting.
+constexpr double c_theta32_2 = 8.093024022188482e-2;
 constexpr double c_theta32_3 = 4.258730016922831e-1;
 constexpr double c_theta64_3 = 1.495585217958292e-2, c_theta64_5 = 2.539398330063230e-1,
                  c_theta64_7 = 9.504178996162932e-1;
@@ -17,7 +20,7 @@ template <typename T>
 __device__ __forceinline__ void choose_ms(double nrm, int& m, int& s) {
   s = 0;
   if constexpr (sizeof(T) == 4) {
-    m = 3;
+    m = nrm <= c_theta32_2 ? 2 : 3;
     const double th = c_theta32_3;
     if (nrm > th) {
       s = (int)ceil(log2(nrm / th));
@@ -82,35 +85,43 @@ __host__ __device__ inline double inv_series_tail(const double* b, int m, int D,
   return tail;
 }
 
-// Largest ||A||_1 for which the degree-5 series of 1/q_3 has tail <= u / 2 in
+// Largest ||A||_1 for which the degree-D series of 1/q_m has tail <= u / 2 in
 // single precision. The tail increases with ||A||_1, so a slice may use the
 // series exactly when its norm is at most this limit (bisection, host side).
-inline double series_limit32(const double* b3) {
+inline double series_limit32(const double* b, int m, int D) {
   const double u = 5.9604644775390625e-8;
   double lo = 0.0, hi = 1.0;
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (lo + hi);
-    if (inv_series_tail(b3, 3, 5, mid) <= 0.5 * u) lo = mid; else hi = mid;
+    if (inv_series_tail(b, m, D, mid) <= 0.5 * u) lo = mid; else hi = mid;
   }
   return lo;
 }
 
+// Series degree used for each single-precision Pade degree: 1/q_2 needs degree
+// 4 (its c_5 is zero), 1/q_3 degree 5; both take A^4 and one product with A.
+constexpr int series_degree(int m) { return m == 2 ? 4 : 5; }
+
 // Inverse of the Pade denominator, per slice (code stored with the slice):
-//   21      power series of 1/q_3 truncated at degree 5 (single precision,
-//           m = 3), when sum_{k > 5} |c_k| ||A||_1^k <= u / 2, i.e. when
-//           ||A||_1 <= ser_max (series_limit32);
+//   16 + D  power series of 1/q_m truncated at degree D = series_degree(m)
+//           (single precision, m in {2, 3}), when sum_{k > D} |c_k| ||A||_1^k
+//           <= u / 2, i.e. when ||A||_1 <= the limit for that m;
 //   1..5    binary Neumann product with that many levels;
 //   0       Gauss-Jordan.
 template <typename T>
 __device__ __forceinline__ int inverse_code(double nA, const double* b, int m, int allow_series,
-                                            double ser_max) {
-  if (sizeof(T) == 4 && m == 3 && allow_series && nA <= ser_max) return 21;
+                                            double ser_max2, double ser_max3) {
+  if (sizeof(T) == 4 && allow_series && ((m == 2 && nA <= ser_max2) || (m == 3 && nA <= ser_max3)))
+    return 16 + series_degree(m);
   return neumann_levels<T>(nA, b, m);
 }
 
-// Block-tiled path: single precision only (m = 3).
+// Block-tiled path: single precision, Pade-3 only.
 template <typename T>
-__device__ __forceinline__ void big_choose_ms(double nrm, int& m, int& s) { choose_ms<T>(nrm, m, s); }
+__device__ __forceinline__ void big_choose_ms(double nrm, int& m, int& s) {
+  choose_ms<T>(nrm, m, s);
+  m = 3;
+}
 
 template <typename T>
 __device__ __forceinline__ int big_neumann_levels(double nA, const double* b3) {

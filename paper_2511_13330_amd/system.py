@@ -213,10 +213,11 @@ class System:
         check(lib().lmag_sync(self._ctx, _stream(stream)), self._ctx)
 
     def selection_histogram(self):
-        h = np.zeros(3 * 64, dtype=np.int64)
+        """[4, 64] counts of (m, s) selections, rows m = 2, 3, 5, 7."""
+        h = np.zeros(4 * 64, dtype=np.int64)
         check(lib().lmag_last_selection_histogram(self._ctx, h.ctypes.data_as(_lib.c_int64_p)),
               self._ctx)
-        return h.reshape(3, 64)
+        return h.reshape(4, 64)
 
     STAGES = ("alpha", "omega", "forward", "scan", "env", "backward", "traces", "grad")
 

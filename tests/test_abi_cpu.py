@@ -43,7 +43,7 @@ def exact_pade(m):
             for j in range(m + 1)]
 
 
-@pytest.mark.parametrize("m", [3, 5, 7])
+@pytest.mark.parametrize("m", [2, 3, 5, 7])
 def test_pade_coefficients(L, m):
     b = (ctypes.c_double * (m + 1))()
     assert L.lmag_pade_coefficients(m, b) == 0
@@ -89,7 +89,7 @@ def backward_error_bound(m, theta, K=None):
     return sum(abs(float(ci)) * theta ** k for k, ci in enumerate(c)) / theta
 
 
-@pytest.mark.parametrize("prec,m,u", [(32, 3, 2.0 ** -24), (64, 3, 2.0 ** -53),
+@pytest.mark.parametrize("prec,m,u", [(32, 2, 2.0 ** -24), (32, 3, 2.0 ** -24), (64, 3, 2.0 ** -53),
                                       (64, 5, 2.0 ** -53), (64, 7, 2.0 ** -53)])
 def test_theta_is_the_unit_roundoff_threshold(L, prec, m, u):
     t = ctypes.c_double()
