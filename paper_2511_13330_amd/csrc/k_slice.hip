@@ -348,23 +348,35 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   // X_Q = Q^{-1} - I into V
   const int K = a.nlev ? a.nlev[n] : 0;
   if (sizeof(T) == 4 && K >= 16) {
-    // Q^{-1} = sum_{k<=D} c_k A^k = even(A^2) + A odd(A^2), the power series of
-    // 1/q_m (D = K - 16; its tail is below the unit roundoff by the selection
-    // rule); c_0 = 1, and for m = 2 (D = 4) c_5 = 0 anyway
+    // Q^{-1} = sum_{k<=D} c_k A^k, the power series of 1/q_m (D = K - 16; its
+    // tail is below the unit roundoff by the selection rule); c_0 = 1
     double c[8];
     inv_series(b, m, c, 8);
     __syncthreads();
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
+    if (K - 16 == 4) {
+      // degree 4 with A and A^2 at hand: X_Q = c_1 A + A^2 (c_2 I + c_3 A + c_4 A^2),
+      // one product
+      RT<T> Bk;
+      rt_load<T, false>(Bk, slot<T, 0>(sh, gs), PITCH);
+      rt_copy(V, Bk);
+      rt_scale(V, (T)c[1]);
+      rt_scale(Bk, (T)c[3]);
+      rt_axpy(Bk, (T)c[4], A2);
+      rt_add_diag(Bk, (T)c[2]);
+      mm(V, slot<T, 1>(sh, gs), Bk);
+    } else {
     RT<T> A4;
     rt_zero(A4);
     mm(A4, slot<T, 1>(sh, gs), A2);
     RT<T> odd;
     rt_poly1(odd, A2, (T)c[3], (T)c[1]);
-    if (K - 16 >= 5) rt_axpy(odd, (T)c[5], A4);
+    rt_axpy(odd, (T)c[5], A4);
     rt_poly1(V, A2, (T)c[2], T(0));
     rt_axpy(V, (T)c[4], A4);
     mm(V, slot<T, 0>(sh, gs), odd);   // X_Q = even - I + A odd
+    }
   } else if (K > 0 && K < 16) {
     // binary Neumann product on MFMA: Q^{-1} = (I + F)(I + F^2)(I + F^4)...,
     // F = I - Q = -E_Q; with X = Q^{-1} - I each level is X += F2 + F2 X
@@ -417,66 +429,84 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   ck.mark(5);
 }
 
-// The chunk's running product P_loc is accumulated in FP64 registers (same
-// layout as a register tile); the MFMA sees its FP32 rounding. With the slice in
-// the form I + D the step is P <- P + D P, so the O(1) part of P is never
-// rounded to FP32 along the chain.
-struct RTW {
-  double re[4][4], im[4][4];
+// The chunk's running product P_loc, kept beyond the compute precision: in FP32
+// as an unevaluated sum hi + lo of two register tiles (double-float, about 48
+// bits), where hi is also the FP32 operand the MFMA needs; in FP64 as one tile.
+// With the slice in the form I + D the step is P <- P + D hi, so the O(1) part
+// of P is never rounded to the compute precision along the chain.
+template <typename T> struct RunProd {
+  RT<T> hi, lo;
 };
 
-// identity in the register-tile layout of T
 template <typename T>
-__device__ __forceinline__ void rtw_identity(RTW& P) {
-  const Lane L;
+__device__ __forceinline__ void rp_identity(RunProd<T>& P) {
+  rt_identity(P.hi);
+  rt_zero(P.lo);
+}
+
+// (h, l) <- renormalised (h + l + x): Knuth's two-sum of h and x, its error
+// folded into l, then a fast two-sum so that h is the rounding of the total
+__device__ __forceinline__ void df_add(float& h, float& l, float x) {
+  const float s = h + x;
+  const float bb = s - h;
+  const float e = (h - (s - bb)) + (x - bb);
+  const float lo = l + e;
+  const float hn = s + lo;
+  l = lo - (hn - s);
+  h = hn;
+}
+
+// hi + lo += X (float: double-float addition; double: hi += X)
+template <typename T>
+__device__ __forceinline__ void rp_add(RunProd<T>& P, const RT<T>& X) {
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      P.re[q][r] = (L.template row<T>(q, r) == L.col) ? 1.0 : 0.0;
-      P.im[q][r] = 0.0;
+      if constexpr (sizeof(T) == 4) {
+        float h = P.hi.re[q][r], l = P.lo.re[q][r];
+        df_add(h, l, X.re[q][r]);
+        P.hi.re[q][r] = h;
+        P.lo.re[q][r] = l;
+        h = P.hi.im[q][r];
+        l = P.lo.im[q][r];
+        df_add(h, l, X.im[q][r]);
+        P.hi.im[q][r] = h;
+        P.lo.im[q][r] = l;
+      } else {
+        P.hi.re[q][r] += X.re[q][r];
+        P.hi.im[q][r] += X.im[q][r];
+      }
     }
 }
 
+// P <- P + D P (D in LDS or global scratch at Dm; the product uses hi)
 template <typename T>
-__device__ __forceinline__ void rtw_narrow(RT<T>& X, const RTW& P) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) { X.re[q][r] = (T)P.re[q][r]; X.im[q][r] = (T)P.im[q][r]; }
-}
-
-// P <- P + D P with D in LDS (or global scratch) at slot Dm
-template <typename T>
-__device__ __forceinline__ void chain_step(RTW& P, const cpx<T>* Dm) {
-  RT<T> Pf, Pn;
-  rtw_narrow(Pf, P);
+__device__ __forceinline__ void chain_step(RunProd<T>& P, const cpx<T>* Dm) {
+  RT<T> Pn;
   rt_zero(Pn);
-  mm<T, false>(Pn, Dm, Pf);   // the FP64 running product leaves no room for the pipelined form
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) { P.re[q][r] += (double)Pn.re[q][r]; P.im[q][r] += (double)Pn.im[q][r]; }
+  mm<T, false>(Pn, Dm, P.hi);
+  rp_add(P, Pn);
 }
 
 template <typename T>
-__device__ __forceinline__ void rtw_store(const RTW& P, cpx<T>* M) {
-  RT<T> X;
-  rtw_narrow(X, P);
-  rt_store<T, false>(X, M, 64);
+__device__ __forceinline__ void rp_store(const RunProd<T>& P, cpx<T>* M) {
+  rt_store<T, false>(P.hi, M, 64);
 }
 
-// stores P - I (the form of chunk totals); the identity is removed in FP64
+// stores P - I (the form of chunk totals): (hi - I) is exact near the identity
+// (Sterbenz), then lo is added
 template <typename T>
-__device__ __forceinline__ void rtw_store_delta(const RTW& P, cpx<T>* M) {
+__device__ __forceinline__ void rp_store_delta(const RunProd<T>& P, cpx<T>* M) {
   const Lane L;
   RT<T> X;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      X.re[q][r] = (T)(P.re[q][r] - ((L.template row<T>(q, r) == L.col) ? 1.0 : 0.0));
-      X.im[q][r] = (T)P.im[q][r];
+      const T d = (L.template row<T>(q, r) == L.col) ? T(1) : T(0);
+      X.re[q][r] = (P.hi.re[q][r] - d) + P.lo.re[q][r];
+      X.im[q][r] = P.hi.im[q][r] + P.lo.im[q][r];
     }
   rt_store<T, false>(X, M, 64);
 }
@@ -499,14 +529,14 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     const int idx = grab(sh, a.counter);
     if (idx >= a.n_chunks) break;
     const Chunk ch = a.chunks[idx];
-    RTW P;
-    rtw_identity<T>(P);
+    RunProd<T> P;
+    rp_identity(P);
     RT<T> A;
     rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
     for (int k = 0; k < ch.count; ++k) {
       const int n = ch.first + k;
       cpx<T>* ws = (a.store && a.ws_tiles) ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
-      if (ws) rtw_store<T>(P, ws + WS_PLOC * TILE);
+      if (ws) rp_store<T>(P, ws + WS_PLOC * TILE);
       RT<T> D;
       fwd_slice<T>(D, A, sh, gs, a, n, ws, ck);
       __syncthreads();
@@ -516,7 +546,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
       chain_step<T>(P, slot<T, 3>(sh, gs));
       ck.mark(6);
     }
-    rtw_store_delta<T>(P, tile_at<T>(a.totals, (size_t)ch.chunk));
+    rp_store_delta<T>(P, tile_at<T>(a.totals, (size_t)ch.chunk));
   }
   ck.flush(a.clk);
 }
@@ -702,13 +732,13 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
                     : nullptr;
     if (RC) {
       // recompute the chunk's forward into this workgroup's scratch tiles
-      RTW P;
-      rtw_identity<T>(P);
+      RunProd<T> P;
+      rp_identity(P);
       RT<T> A;
       rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
       for (int k = 0; k < ch.count; ++k) {
         cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
-        rtw_store<T>(P, ws + WS_PLOC * TILE);
+        rp_store<T>(P, ws + WS_PLOC * TILE);
         RT<T> D;
         fwd_slice<T>(D, A, sh, gs, a, ch.first + k, ws, ck);
         if (k + 1 < ch.count) {
