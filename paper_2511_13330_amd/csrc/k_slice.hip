@@ -282,21 +282,43 @@ __global__ void __launch_bounds__(WG) k_traces(SliceArgs a, int n_total) {
   }
 }
 
+// Per-slice codes read inside the slice loops (Pade degree, scaling exponent,
+// inverse variant) go through the scalar unit: a load from the constant address
+// space. Vector memory operations complete in order, so a vector load here would
+// also wait for every tile prefetch and workspace store still in flight. The
+// codes are written by an earlier kernel and only read here. The aligned word
+// holding the byte never leaves the allocation's page.
+__device__ __forceinline__ uint32_t code_word(const int8_t* p) {
+  const uintptr_t at = (uintptr_t)p;
+  return *(const __attribute__((address_space(4))) uint32_t*)(at & ~(uintptr_t)3) >> ((at & 3) * 8);
+}
+
+struct SliceMS { int m, s; };
+__device__ __forceinline__ SliceMS slice_ms(const SliceArgs& a, int n) {
+  const uint32_t w = code_word(a.ms + 2 * (size_t)n);   // even offset: both bytes in one word
+  return {(int)(int8_t)(w & 0xff), (int)(int8_t)((w >> 8) & 0xff)};
+}
+
+__device__ __forceinline__ int slice_inverse_code(const SliceArgs& a, int n) {
+  return a.nlev ? (int)(int8_t)(code_word(a.nlev + n) & 0xff) : 0;
+}
+
 // One slice forward; returns D_n = S_n - I in R. Every matrix near the identity
 // is carried as I + X with only X inside the MFMA accumulators: accumulating
 // small products onto O(1) diagonal entries in FP32 biases them by a fraction of
 // an ulp, and over a chain of thousands of slices that bias adds up linearly.
-// Stores go to the workspace when requested: A^2, Q^{-1} - I and r_m(A) - I
-// (before the squarings).
+// With ST, stores go to workspace ws: A^2, Q^{-1} - I and r_m(A) - I (before the
+// squarings).
 // A holds Omega_n / 2^s (loaded by the caller, which prefetches it during the
 // previous slice's chain product).
-template <typename T>
+template <typename T, bool ST>
 __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a,
                           int n, cpx<T>* ws, Clock& ck) {
-  const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
+  const SliceMS ms = slice_ms(a, n);
+  const int m = ms.m, s = ms.s;
   const double* b = pade_b<T>(a.pade, m);   // b[0] = 1
   ck.mark(0);
-  const bool st = ws != nullptr;
+  constexpr bool st = ST;   // compile-time, so that the stores are straight-line code
 
   __syncthreads();
   put<T, false>(A, slot<T, 0>(sh, gs));
@@ -346,7 +368,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   }
   ck.mark(2);
   // X_Q = Q^{-1} - I into V
-  const int K = a.nlev ? a.nlev[n] : 0;
+  const int K = slice_inverse_code(a, n);
   if (sizeof(T) == 4 && K >= 16) {
     // Q^{-1} = sum_{k<=D} c_k A^k, the power series of 1/q_m (D = K - 16; its
     // tail is below the unit roundoff by the selection rule); c_0 = 1
@@ -519,7 +541,11 @@ __device__ __forceinline__ int grab(Shared<T>& sh, int* counter) {
   return __builtin_amdgcn_readfirstlane(sh.sidx);
 }
 
-template <typename T>
+// ST: store the per-slice workspace for the adjoint. A separate instantiation:
+// with the stores behind a run-time test, the compiler's count of memory
+// operations in flight is that of the path without them, and the first use of
+// the prefetched Omega tile would also wait for every store.
+template <typename T, bool ST>
 __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
   __shared__ Shared<T> sh;
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
@@ -535,10 +561,10 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
     for (int k = 0; k < ch.count; ++k) {
       const int n = ch.first + k;
-      cpx<T>* ws = (a.store && a.ws_tiles) ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
-      if (ws) rp_store<T>(P, ws + WS_PLOC * TILE);
+      cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
+      if (ST) rp_store<T>(P, ws + WS_PLOC * TILE);
       RT<T> D;
-      fwd_slice<T>(D, A, sh, gs, a, n, ws, ck);
+      fwd_slice<T, ST>(D, A, sh, gs, a, n, ws, ck);
       __syncthreads();
       put<T, false>(D, slot<T, 3>(sh, gs));
       __syncthreads();
@@ -551,31 +577,46 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
   ck.flush(a.clk);
 }
 
+// Single precision carries P_loc^T from slice to slice: it is the first tile a
+// slice needs, so slice n requests slice n - 1's as soon as its own is used.
+// Double-precision tiles take twice the registers; there it is loaded in place.
+template <typename T> constexpr bool bwd_carry = sizeof(T) == 4;
+
 // One slice backward in the transposed frame. Z holds Z_n^T on entry and
-// Z_{n-1}^T on exit.
+// Z_{n-1}^T on exit. With bwd_carry, Pl holds slice n's P_loc^T on entry and the
+// one in workspace nx on exit (slice n - 1's; at the chunk's first slice, its
+// own again: an unconditional load keeps the compiler's count of loads in
+// flight exact, so later waits do not also wait for this one).
 // kpack: this thread's compact-K_n^T word (sparse basis), see SparseBasis.
 template <typename T>
-__device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a, int n,
-                          const cpx<T>* ws, Clock& ck, uint32_t kpack) {
-  const int m = a.ms[2 * (size_t)n], s = a.ms[2 * (size_t)n + 1];
+__device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a,
+                          int n, const cpx<T>* ws, const cpx<T>* nx, Clock& ck, uint32_t kpack) {
+  const SliceMS ms = slice_ms(a, n);
+  const int m = ms.m, s = ms.s;
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
+  // (Omega_n / 2^s)^T, D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T; single precision
+  // requests all three here, in the order they are used (vector loads complete
+  // in order), double precision where each is first needed
+  RT<T> A, R, Qi;
+  if constexpr (bwd_carry<T>) {
+    rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
+    rt_load<T, true>(R, ws + WS_S * TILE, 64);
+    rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
+  }
 
   // E = M_n^T / 2^s,  M_n^T = Z_n^T P_loc,n^T
   __syncthreads();
   put<T, false>(Z, slot<T, 0>(sh, gs));
   __syncthreads();
   RT<T> E;
-  {
-    RT<T> Pl;
-    rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
-    rt_zero(E);
-    mm(E, slot<T, 0>(sh, gs), Pl);
-  }
+  rt_zero(E);
+  if constexpr (!bwd_carry<T>) rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
+  mm(E, slot<T, 0>(sh, gs), Pl);
+  if constexpr (bwd_carry<T>) rt_load<T, true>(Pl, nx + WS_PLOC * TILE, 64);
   if (s) rt_scale(E, sc);
   ck.mark(1);
-  RT<T> A;
-  rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);   // (Omega_n / 2^s)^T
+  if constexpr (!bwd_carry<T>) rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
   __syncthreads();
   put<T, false>(A, slot<T, 0>(sh, gs));
   put<T, false>(E, slot<T, 1>(sh, gs));
@@ -641,18 +682,14 @@ __device__ void bwd_slice(RT<T>& Z, Shared<T>& sh, cpx<T>* gs, const SliceArgs& 
     LW.re[q] = vr - LU.re[q]; LW.im[q] = vi - LU.im[q];
     LU.re[q] = vr + LU.re[q]; LU.im[q] = vi + LU.im[q];
   }
-  RT<T> R;
-  rt_load<T, true>(R, ws + WS_S * TILE, 64);   // D^T = (r_m(A) - I)^T
+  if constexpr (!bwd_carry<T>) rt_load<T, true>(R, ws + WS_S * TILE, 64);
   // X = L_P - L_Q r_m(A) = (L_P - L_Q) - L_Q D
 #pragma unroll
   for (int q = 0; q < 4; ++q) { LU.re[q] -= LW.re[q]; LU.im[q] -= LW.im[q]; }
   __syncthreads();
   put<T, false>(LW, slot<T, 1>(sh, gs));
-  {
-    RT<T> Qi;   // (Q^{-1} - I)^T
-    rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
-    put<T, false>(Qi, slot<T, 2>(sh, gs));
-  }
+  if constexpr (!bwd_carry<T>) rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
+  put<T, false>(Qi, slot<T, 2>(sh, gs));
   __syncthreads();
   ck.mark(6);
   {
@@ -740,7 +777,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
         cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
         rp_store<T>(P, ws + WS_PLOC * TILE);
         RT<T> D;
-        fwd_slice<T>(D, A, sh, gs, a, ch.first + k, ws, ck);
+        fwd_slice<T, true>(D, A, sh, gs, a, ch.first + k, ws, ck);
         if (k + 1 < ch.count) {
           rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
           __syncthreads();
@@ -750,22 +787,33 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
         }
       }
     }
+    auto ws_of = [&](int k) -> const cpx<T>* {
+      return rs ? rs + (size_t)k * WS_TILES * TILE
+                : tile_at<T>(a.ws_tiles, (size_t)(ch.first + k) * WS_TILES);
+    };
     RT<T> Z;
     rt_load<T, true>(Z, tile_at<T>((void*)a.env, (size_t)ch.chunk), 64);
-    ck.mark(0);
-    for (int k = ch.count - 1; k >= 0; --k) {
-      const int n = ch.first + k;
-      const cpx<T>* ws = rs ? rs + (size_t)k * WS_TILES * TILE
-                            : tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES);
-      bwd_slice<T>(Z, sh, gs, a, n, ws, ck, kpack);
+    RT<T> Pl;
+    if constexpr (bwd_carry<T>) {
+      if (RC) __syncthreads();   // the recomputed tiles are read by other threads
+      rt_load<T, true>(Pl, ws_of(ch.count - 1) + WS_PLOC * TILE, 64);
     }
+    ck.mark(0);
+    for (int k = ch.count - 1; k >= 0; --k)
+      bwd_slice<T>(Z, Pl, sh, gs, a, ch.first + k, ws_of(k), ws_of(k > 0 ? k - 1 : 0), ck, kpack);
   }
   ck.flush(a.clk ? a.clk + 16 : nullptr);
 }
 
 hipError_t launch_slice_forward(int prec, const SliceArgs& a, int grid, hipStream_t s) {
-  if (prec == 32) hipLaunchKernelGGL(k_forward<float>, dim3(grid), dim3(WG), 0, s, a);
-  else hipLaunchKernelGGL(k_forward<double>, dim3(grid), dim3(WG), 0, s, a);
+  const bool st = a.store && a.ws_tiles;
+  if (prec == 32) {
+    if (st) hipLaunchKernelGGL((k_forward<float, true>), dim3(grid), dim3(WG), 0, s, a);
+    else hipLaunchKernelGGL((k_forward<float, false>), dim3(grid), dim3(WG), 0, s, a);
+  } else {
+    if (st) hipLaunchKernelGGL((k_forward<double, true>), dim3(grid), dim3(WG), 0, s, a);
+    else hipLaunchKernelGGL((k_forward<double, false>), dim3(grid), dim3(WG), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -842,7 +890,7 @@ __global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, Sl
   Clock ck(nullptr, sh.clk);
   RT<T> R, A;
   rt_load<T, false>(A, tile_at<T>(a.omega, 0), 64);
-  fwd_slice<T>(R, A, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
+  fwd_slice<T, false>(R, A, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
   rt_add_diag(R, T(1));
   rt_store<T, false>(R, C, 64);
 }
