@@ -578,15 +578,15 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
 }
 
 // Single precision carries P_loc^T from slice to slice: it is the first tile a
-// slice needs, so slice n requests slice n - 1's as soon as its own is used.
+// slice needs, so slice n requests slice n - 1's before its last product.
 // Double-precision tiles take twice the registers; there it is loaded in place.
 template <typename T> constexpr bool bwd_carry = sizeof(T) == 4;
 
 // One slice backward in the transposed frame. Z holds Z_n^T on entry and
 // Z_{n-1}^T on exit. With bwd_carry, Pl holds slice n's P_loc^T on entry and the
 // one in workspace nx on exit (slice n - 1's; at the chunk's first slice, its
-// own again: an unconditional load keeps the compiler's count of loads in
-// flight exact, so later waits do not also wait for this one).
+// own again: an unconditional load keeps the compiler's count of operations in
+// flight exact).
 // kpack: this thread's compact-K_n^T word (sparse basis), see SparseBasis.
 template <typename T>
 __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a,
@@ -595,26 +595,25 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   const int m = ms.m, s = ms.s;
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
-  // (Omega_n / 2^s)^T, D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T; single precision
-  // requests all three here, in the order they are used (vector loads complete
-  // in order), double precision where each is first needed
+  // (Omega_n / 2^s)^T, D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T. Single precision
+  // requests them one product ahead of their use, in that order (vector loads
+  // complete in order): a wave that requests all three tiles at once stalls on
+  // issue for about 4K cycles. Double precision loads each where it is needed.
   RT<T> A, R, Qi;
-  if constexpr (bwd_carry<T>) {
-    rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
-    rt_load<T, true>(R, ws + WS_S * TILE, 64);
-    rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
-  }
+  if constexpr (bwd_carry<T>) rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
+  ck.mark(10);
 
   // E = M_n^T / 2^s,  M_n^T = Z_n^T P_loc,n^T
   __syncthreads();
   put<T, false>(Z, slot<T, 0>(sh, gs));
   __syncthreads();
+  ck.mark(11);
   RT<T> E;
   rt_zero(E);
   if constexpr (!bwd_carry<T>) rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
   mm(E, slot<T, 0>(sh, gs), Pl);
-  if constexpr (bwd_carry<T>) rt_load<T, true>(Pl, nx + WS_PLOC * TILE, 64);
   if (s) rt_scale(E, sc);
+  if constexpr (bwd_carry<T>) rt_load<T, true>(R, ws + WS_S * TILE, 64);
   ck.mark(1);
   if constexpr (!bwd_carry<T>) rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
   __syncthreads();
@@ -626,6 +625,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   rt_zero(L2);
   mm(L2, slot<T, 0>(sh, gs), E);
   mm(L2, slot<T, 1>(sh, gs), A);
+  if constexpr (bwd_carry<T>) rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
   ck.mark(3);
   RT<T> W, LW, LV;
   const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
@@ -739,6 +739,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   } else {
     rt_store<T, false>(K, tile_at<T>(a.omega, (size_t)n), 64);
   }
+  // next P_loc^T, issued after the K stores: their number differs per lane, so
+  // the compiler counts none of them, and a load issued before them would make
+  // its wait also wait for them
+  if constexpr (bwd_carry<T>) rt_load<T, true>(Pl, nx + WS_PLOC * TILE, 64);
   ck.mark(8);
   // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T
   __syncthreads();
@@ -797,6 +801,11 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
     if constexpr (bwd_carry<T>) {
       if (RC) __syncthreads();   // the recomputed tiles are read by other threads
       rt_load<T, true>(Pl, ws_of(ch.count - 1) + WS_PLOC * TILE, 64);
+      // Wait here, once per chunk, for Z and P_loc. Otherwise the compiler's
+      // count of operations in flight at the loop head is that of this entry
+      // path, where nothing follows these loads, and every slice's first wait
+      // would also wait for the previous slice's K stores.
+      __builtin_amdgcn_s_waitcnt(0);
     }
     ck.mark(0);
     for (int k = ch.count - 1; k >= 0; --k)
