@@ -49,6 +49,76 @@ __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) 
   gemm_acc<T, false, PITCH, PIPE>(acc, A, B);
 }
 
+// mm with a hook that moves a share of a global tile at each k-step
+template <typename T, bool PIPE = true, typename H>
+__device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B, const H& hook) {
+  gemm_acc<T, false, PITCH, PIPE, H>(acc, A, B, hook);
+}
+
+// Product hooks: a transfer between a register tile and a row-major 64 x 64
+// global tile, spread over k-steps. A load runs at steps S0 .. S0 + 7, two
+// registers (q, r), (q, r + 1) per step (for a transposed single-precision
+// load these rows are adjacent in memory: one 16-byte access), so that the
+// tile has arrived well before the product that follows needs it. A store
+// moves register (q, r) = (st / 4, st % 4) at step st.
+template <typename T, bool TRANS, int S0 = 0>
+struct TileLoad {
+  RT<T>& X;
+  const cpx<T>* M;
+  __device__ __forceinline__ void operator()(int st) const {
+    if (st < S0 || st >= S0 + 8) return;
+    const Lane L;
+    const int e = 2 * (st - S0), q = e >> 2, r = e & 3, j = L.col;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = L.template row<T>(q, r + u);
+      const cpx<T> v = TRANS ? M[(size_t)j * 64 + i] : M[(size_t)i * 64 + j];
+      X.re[q][r + u] = v.re; X.im[q][r + u] = v.im;
+    }
+  }
+};
+
+template <typename T>
+struct TileStore {
+  const RT<T>& X;
+  cpx<T>* M;
+  __device__ __forceinline__ void operator()(int st) const {
+    const Lane L;
+    const int q = st >> 2, r = st & 3;
+    cpx<T> v; v.re = X.re[q][r]; v.im = X.im[q][r];
+    M[(size_t)L.template row<T>(q, r) * 64 + L.col] = v;
+  }
+};
+
+// Compact store of the support entries of a tile (sparse basis): kpack holds
+// this thread's 16-bit mask of support registers and, above it, the slot of its
+// first entry; entries go to consecutive slots in register order.
+template <typename T>
+struct SupportStore {
+  const RT<T>& X;
+  cpx<T>* M;
+  uint32_t kpack;
+  __device__ __forceinline__ void operator()(int st) const {
+    if ((kpack >> st) & 1u) {
+      const int q = st >> 2, r = st & 3;
+      cpx<T> v; v.re = X.re[q][r]; v.im = X.im[q][r];
+      M[(kpack >> 16) + __builtin_popcount(kpack & ((1u << st) - 1u))] = v;
+    }
+  }
+};
+
+template <typename H1, typename H2>
+struct Hooks2 {
+  H1 h1; H2 h2;
+  __device__ __forceinline__ void operator()(int st) const { h1(st); h2(st); }
+};
+
+template <typename H1, typename H2, typename H3>
+struct Hooks3 {
+  H1 h1; H2 h2; H3 h3;
+  __device__ __forceinline__ void operator()(int st) const { h1(st); h2(st); h3(st); }
+};
+
 template <typename T>
 __device__ __forceinline__ const double* pade_b(const PadeTable& pt, int m) {
   return m == 2 ? pt.b2 : (m == 3 ? pt.b3 : (m == 5 ? pt.b5 : pt.b7));
@@ -307,13 +377,18 @@ __device__ __forceinline__ int slice_inverse_code(const SliceArgs& a, int n) {
 // is carried as I + X with only X inside the MFMA accumulators: accumulating
 // small products onto O(1) diagonal entries in FP32 biases them by a fraction of
 // an ulp, and over a chain of thousands of slices that bias adds up linearly.
-// With ST, stores go to workspace ws: A^2, Q^{-1} - I and r_m(A) - I (before the
-// squarings).
+// With ST, stores go to workspace ws: P_loc (Pl, the chunk product before this
+// slice), A^2 (m > 2), Q^{-1} - I and r_m(A) - I (before the squarings). In
+// single precision P_loc, A^2 and Q^{-1} - I are stored spread over the k-steps
+// of a product that follows the tile's last change (see gemm_acc). r_m(A) - I
+// is stored at once: deferring it into the chain product kept it live there and
+// made that product spill.
 // A holds Omega_n / 2^s (loaded by the caller, which prefetches it during the
 // previous slice's chain product).
 template <typename T, bool ST>
-__device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a,
-                          int n, cpx<T>* ws, Clock& ck) {
+__device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& sh, cpx<T>* gs,
+                          const SliceArgs& a, int n, cpx<T>* ws, Clock& ck) {
+  constexpr bool hk = sizeof(T) == 4;   // stores inside products
   const SliceMS ms = slice_ms(a, n);
   const int m = ms.m, s = ms.s;
   const double* b = pade_b<T>(a.pade, m);   // b[0] = 1
@@ -325,10 +400,15 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   __syncthreads();
   RT<T> A2;
   rt_zero(A2);
-  mm(A2, slot<T, 0>(sh, gs), A);
+  if constexpr (st && hk) {
+    mm(A2, slot<T, 0>(sh, gs), A, TileStore<T>{Pl, ws + WS_PLOC * TILE});
+  } else {
+    if constexpr (st) rt_store<T, false>(Pl, ws + WS_PLOC * TILE, 64);
+    mm(A2, slot<T, 0>(sh, gs), A);
+  }
   ck.mark(1);
-  if (st && !(sizeof(T) == 4 && m == 2))   // the Pade-2 adjoint does not read A^2
-    rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
+  // the Pade-2 adjoint does not read A^2; single precision stores it below
+  if constexpr (st && !hk) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
   RT<T> V;   // the even part minus I
   RT<T> U;   // the odd part
   if (sizeof(T) == 4 && m == 2) {
@@ -357,7 +437,10 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
     }
   }
   rt_zero(U);
-  mm(U, slot<T, 0>(sh, gs), W);
+  if constexpr (st && hk)
+    mm(U, slot<T, 0>(sh, gs), W, TileStore<T>{A2, ws + WS_A2 * TILE});
+  else
+    mm(U, slot<T, 0>(sh, gs), W);
   }
   // P = I + X_P with X_P = (V - I) + U (in U); Q = I + E_Q with E_Q = (V - I) - U (in V)
 #pragma unroll
@@ -372,8 +455,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
   if (sizeof(T) == 4 && K >= 16) {
     // Q^{-1} = sum_{k<=D} c_k A^k, the power series of 1/q_m (D = K - 16; its
     // tail is below the unit roundoff by the selection rule); c_0 = 1
-    double c[8];
-    inv_series(b, m, c, 8);
+    const double* c = m == 2 ? a.pade.c2 : a.pade.c3;   // computed once on the host
     __syncthreads();
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
@@ -428,14 +510,17 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, Shared<T>& sh, cpx<T>* gs, c
     rt_add_diag(V, T(-1));
   }
   ck.mark(3);
-  if (st) rt_store<T, false>(V, ws + WS_QINV * TILE, 64);
+  if constexpr (st && !hk) rt_store<T, false>(V, ws + WS_QINV * TILE, 64);
   // D = r_m(A) - I = X_Q + X_P + X_Q X_P
   put<T, false>(V, slot<T, 1>(sh, gs));
   __syncthreads();
   rt_copy(R, U);
   rt_axpy(R, T(1), V);
-  mm(R, slot<T, 1>(sh, gs), U);
-  if (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
+  if constexpr (st && hk)
+    mm(R, slot<T, 1>(sh, gs), U, TileStore<T>{V, ws + WS_QINV * TILE});
+  else
+    mm(R, slot<T, 1>(sh, gs), U);
+  if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
   ck.mark(4);
   // squarings: (I + D)^2 = I + 2 D + D^2
   for (int k = 0; k < s; ++k) {
@@ -511,9 +596,12 @@ __device__ __forceinline__ void chain_step(RunProd<T>& P, const cpx<T>* Dm) {
   rp_add(P, Pn);
 }
 
-template <typename T>
-__device__ __forceinline__ void rp_store(const RunProd<T>& P, cpx<T>* M) {
-  rt_store<T, false>(P.hi, M, 64);
+template <typename T, typename H>
+__device__ __forceinline__ void chain_step(RunProd<T>& P, const cpx<T>* Dm, const H& hook) {
+  RT<T> Pn;
+  rt_zero(Pn);
+  mm<T, false>(Pn, Dm, P.hi, hook);
+  rp_add(P, Pn);
 }
 
 // stores P - I (the form of chunk totals): (hi - I) is exact near the identity
@@ -562,14 +650,15 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     for (int k = 0; k < ch.count; ++k) {
       const int n = ch.first + k;
       cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
-      if (ST) rp_store<T>(P, ws + WS_PLOC * TILE);
       RT<T> D;
-      fwd_slice<T, ST>(D, A, sh, gs, a, n, ws, ck);
+      fwd_slice<T, ST>(D, A, P.hi, sh, gs, a, n, ws, ck);
       __syncthreads();
       put<T, false>(D, slot<T, 3>(sh, gs));
       __syncthreads();
-      if (k + 1 < ch.count) rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)n + 1), 64);
-      chain_step<T>(P, slot<T, 3>(sh, gs));
+      // the next slice's Omega tile, spread over the chain product (the chunk's
+      // last slice reloads its own, so that the loads are unconditional)
+      chain_step<T>(P, slot<T, 3>(sh, gs),
+                    TileLoad<T, false>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
       ck.mark(6);
     }
     rp_store_delta<T>(P, tile_at<T>(a.totals, (size_t)ch.chunk));
@@ -583,24 +672,24 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
 template <typename T> constexpr bool bwd_carry = sizeof(T) == 4;
 
 // One slice backward in the transposed frame. Z holds Z_n^T on entry and
-// Z_{n-1}^T on exit. With bwd_carry, Pl holds slice n's P_loc^T on entry and the
-// one in workspace nx on exit (slice n - 1's; at the chunk's first slice, its
-// own again: an unconditional load keeps the compiler's count of operations in
-// flight exact).
+// Z_{n-1}^T on exit. With bwd_carry, Pl and A hold slice n's P_loc^T and
+// (Omega_n / 2^s)^T on entry, and on exit those of slice nn (n - 1; at the
+// chunk's first slice n itself again: unconditional loads keep the compiler's
+// count of operations in flight exact), nx being slice nn's workspace.
 // kpack: this thread's compact-K_n^T word (sparse basis), see SparseBasis.
 template <typename T>
-__device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const SliceArgs& a,
-                          int n, const cpx<T>* ws, const cpx<T>* nx, Clock& ck, uint32_t kpack) {
+__device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* gs,
+                          const SliceArgs& a, int n, const cpx<T>* ws, int nn, const cpx<T>* nx,
+                          Clock& ck, uint32_t kpack) {
   const SliceMS ms = slice_ms(a, n);
   const int m = ms.m, s = ms.s;
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
-  // (Omega_n / 2^s)^T, D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T. Single precision
-  // requests them one product ahead of their use, in that order (vector loads
-  // complete in order): a wave that requests all three tiles at once stalls on
-  // issue for about 4K cycles. Double precision loads each where it is needed.
-  RT<T> A, R, Qi;
-  if constexpr (bwd_carry<T>) rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
+  // D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T. Single precision requests each
+  // stored tile one product ahead of its use, spread over that product's
+  // k-steps: a wave that requests whole tiles at once stalls on issue (about 4K
+  // cycles for three tiles). Double precision loads each where it is needed.
+  RT<T> R, Qi;
   ck.mark(10);
 
   // E = M_n^T / 2^s,  M_n^T = Z_n^T P_loc,n^T
@@ -610,10 +699,13 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   ck.mark(11);
   RT<T> E;
   rt_zero(E);
-  if constexpr (!bwd_carry<T>) rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
-  mm(E, slot<T, 0>(sh, gs), Pl);
+  if constexpr (bwd_carry<T>) {
+    mm(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true>{R, ws + WS_S * TILE});
+  } else {
+    rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
+    mm(E, slot<T, 0>(sh, gs), Pl);
+  }
   if (s) rt_scale(E, sc);
-  if constexpr (bwd_carry<T>) rt_load<T, true>(R, ws + WS_S * TILE, 64);
   ck.mark(1);
   if constexpr (!bwd_carry<T>) rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
   __syncthreads();
@@ -624,8 +716,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   RT<T> L2;
   rt_zero(L2);
   mm(L2, slot<T, 0>(sh, gs), E);
-  mm(L2, slot<T, 1>(sh, gs), A);
-  if constexpr (bwd_carry<T>) rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
+  if constexpr (bwd_carry<T>)
+    mm(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true>{Qi, ws + WS_QINV * TILE});
+  else
+    mm(L2, slot<T, 1>(sh, gs), A);
   ck.mark(3);
   RT<T> W, LW, LV;
   const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
@@ -722,27 +816,18 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   }
   ck.mark(7);
   // K_n^T replaces A_n (whole tile, or only its support positions, compacted,
-  // with a sparse basis); the traces Re Tr(K_n B_j) are taken afterwards
-  if (a.sp.n_sup > 0) {
-    cpx<T>* kc = tile_at<T>(a.omega, (size_t)n) + (kpack >> 16);
-    int slot = 0;
+  // with a sparse basis); the traces Re Tr(K_n B_j) are taken afterwards.
+  // Single precision stores it during the last product, together with the
+  // next slice's P_loc^T and Omega tile loads.
+  cpx<T>* kt = tile_at<T>(a.omega, (size_t)n);
+  if constexpr (!bwd_carry<T>) {
+    if (a.sp.n_sup > 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if ((kpack >> (4 * q + r)) & 1u) {
-          cpx<T> x;
-          x.re = K.re[q][r];
-          x.im = K.im[q][r];
-          kc[slot++] = x;
-        }
-  } else {
-    rt_store<T, false>(K, tile_at<T>(a.omega, (size_t)n), 64);
+      for (int st = 0; st < 16; ++st) SupportStore<T>{K, kt, kpack}(st);
+    } else {
+      rt_store<T, false>(K, kt, 64);
+    }
   }
-  // next P_loc^T, issued after the K stores: their number differs per lane, so
-  // the compiler counts none of them, and a load issued before them would make
-  // its wait also wait for them
-  if constexpr (bwd_carry<T>) rt_load<T, true>(Pl, nx + WS_PLOC * TILE, 64);
   ck.mark(8);
   // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T
   __syncthreads();
@@ -750,7 +835,19 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, Shared<T>& sh, cpx<T>* gs, const 
   __syncthreads();
   RT<T> Zn;
   rt_copy(Zn, Z);
-  mm(Zn, slot<T, 0>(sh, gs), Z);
+  if constexpr (bwd_carry<T>) {
+    // P_loc^T (needed first) in the first half of the k-steps, Omega in the second
+    const TileLoad<T, true, 0> lp{Pl, nx + WS_PLOC * TILE};
+    const TileLoad<T, true, 8> la{A, tile_at<T>(a.omega, (size_t)nn)};
+    if (a.sp.n_sup > 0)
+      mm(Zn, slot<T, 0>(sh, gs), Z,
+         Hooks3<SupportStore<T>, TileLoad<T, true, 0>, TileLoad<T, true, 8>>{{K, kt, kpack}, lp, la});
+    else
+      mm(Zn, slot<T, 0>(sh, gs), Z,
+         Hooks3<TileStore<T>, TileLoad<T, true, 0>, TileLoad<T, true, 8>>{{K, kt}, lp, la});
+  } else {
+    mm(Zn, slot<T, 0>(sh, gs), Z);
+  }
   rt_copy(Z, Zn);
   ck.mark(9);
 }
@@ -779,9 +876,8 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
       for (int k = 0; k < ch.count; ++k) {
         cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
-        rp_store<T>(P, ws + WS_PLOC * TILE);
         RT<T> D;
-        fwd_slice<T, true>(D, A, sh, gs, a, ch.first + k, ws, ck);
+        fwd_slice<T, true>(D, A, P.hi, sh, gs, a, ch.first + k, ws, ck);
         if (k + 1 < ch.count) {
           rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
           __syncthreads();
@@ -797,11 +893,12 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
     };
     RT<T> Z;
     rt_load<T, true>(Z, tile_at<T>((void*)a.env, (size_t)ch.chunk), 64);
-    RT<T> Pl;
+    RT<T> Pl, A;
     if constexpr (bwd_carry<T>) {
       if (RC) __syncthreads();   // the recomputed tiles are read by other threads
       rt_load<T, true>(Pl, ws_of(ch.count - 1) + WS_PLOC * TILE, 64);
-      // Wait here, once per chunk, for Z and P_loc. Otherwise the compiler's
+      rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)ch.first + ch.count - 1), 64);
+      // Wait here, once per chunk, for Z, P_loc and Omega. Otherwise the compiler's
       // count of operations in flight at the loop head is that of this entry
       // path, where nothing follows these loads, and every slice's first wait
       // would also wait for the previous slice's K stores.
@@ -809,7 +906,8 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
     }
     ck.mark(0);
     for (int k = ch.count - 1; k >= 0; --k)
-      bwd_slice<T>(Z, Pl, sh, gs, a, ch.first + k, ws_of(k), ws_of(k > 0 ? k - 1 : 0), ck, kpack);
+      bwd_slice<T>(Z, Pl, A, sh, gs, a, ch.first + k, ws_of(k), ch.first + (k > 0 ? k - 1 : 0),
+                   ws_of(k > 0 ? k - 1 : 0), ck, kpack);
   }
   ck.flush(a.clk ? a.clk + 16 : nullptr);
 }
@@ -899,7 +997,7 @@ __global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, Sl
   Clock ck(nullptr, sh.clk);
   RT<T> R, A;
   rt_load<T, false>(A, tile_at<T>(a.omega, 0), 64);
-  fwd_slice<T, false>(R, A, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
+  fwd_slice<T, false>(R, A, A, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
   rt_add_diag(R, T(1));
   rt_store<T, false>(R, C, 64);
 }

@@ -16,6 +16,7 @@
 // K1 = (Ar + Ai) Br, Cr += K1 - Ai (Br + Bi), Ci += K1 + Ar (Bi - Br); its
 // normwise error bound is a small constant times that of the 4M method.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -144,13 +145,23 @@ __device__ __forceinline__ void rt_store(const RT<T>& X, cpx<T>* __restrict__ M,
     }
 }
 
+// No extra work inside a product (see gemm_acc's hook).
+struct NoHook {
+  __device__ __forceinline__ void operator()(int) const {}
+};
+
 // acc += alpha-free X * Y where X is read from memory (LDS or global) row-major
 // with pitch PA, in orientation TA (false: X = A, true: X = A^T), and Y is an RT.
 // acc and B must be different register tiles.
 // PIPE (single precision): issue the next k-step's A loads ahead of this
 // step's MFMAs and pin that order; off where registers are too tight for it.
-template <typename T, bool TA, int PA, bool PIPE = true>
-__device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ A, const RT<T>& B) {
+// hook(st) runs at each of the 16 k-steps st, ahead of that step's MFMAs: a
+// share of a global tile load or store placed there drains while the matrix
+// cores work, where the whole transfer issued at once would stall the wave.
+template <typename T, bool TA, int PA, bool PIPE = true, typename H = NoHook>
+__device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ A, const RT<T>& B,
+                                         const H& hook = H{}) {
+  constexpr bool hooked = !std::is_same<H, NoHook>::value;
   const Lane L;
   const int g = L.g, c = L.c;
   if constexpr (sizeof(T) == 4) {
@@ -176,6 +187,11 @@ __device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ 
           for (int t = 0; t < 4; ++t) a[q][t] = ld(4 * kb + t, q);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+          if constexpr (hooked) {
+            __builtin_amdgcn_sched_barrier(0);
+            hook(4 * kb + t);
+            __builtin_amdgcn_sched_barrier(0);
+          }
           const T br = B.re[kb][t], bi = B.im[kb][t];
           const T nsum = -(br + bi), diff = bi - br;
 #pragma unroll
@@ -199,6 +215,7 @@ __device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ 
 #pragma unroll
         for (int q = 0; q < 4; ++q) nxt[q] = ld(st + 1, q);
       }
+      hook(st);
       // keep the scheduler from sinking these loads next to their use
       __builtin_amdgcn_sched_barrier(0);
       const T br = B.re[st >> 2][st & 3], bi = B.im[st >> 2][st & 3];
@@ -229,6 +246,7 @@ __device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ 
                        : A[(16 * q + c) * PA + 16 * kb + Sub<T>::row(g, t)];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
+        hook(4 * kb + t);
         const T br = B.re[kb][t], bi = B.im[kb][t], nbi = -bi;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
