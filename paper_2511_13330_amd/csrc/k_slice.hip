@@ -55,6 +55,18 @@ __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B, 
   gemm_acc<T, false, PITCH, PIPE, H>(acc, A, B, hook);
 }
 
+// Element (row(q, r), col) of this thread in a row-major 64 x 64 tile at M
+// (TRANS: in its transpose). Rows split into a uniform part (16 q + the row of
+// register r) and a lane part (the row of lane group g); the address is the
+// uniform part folded into the base plus one 32-bit lane offset shared by all
+// sixteen registers, which keeps the hooks below to a register or two.
+template <typename T, bool TRANS>
+__device__ __forceinline__ cpx<T>* tile_elem(cpx<T>* M, int q, int r, const Lane& L) {
+  const int ru = 16 * q + Sub<T>::row(0, r), rl = Sub<T>::row(L.g, 0);
+  cpx<T>* base = M + (TRANS ? ru : ru * 64);
+  return base + (uint32_t)(TRANS ? L.col * 64 + rl : rl * 64 + L.col);
+}
+
 // Product hooks: a transfer between a register tile and a row-major 64 x 64
 // global tile, spread over k-steps. A load runs at steps S0 .. S0 + 7, two
 // registers (q, r), (q, r + 1) per step (for a transposed single-precision
@@ -68,11 +80,10 @@ struct TileLoad {
   __device__ __forceinline__ void operator()(int st) const {
     if (st < S0 || st >= S0 + 8) return;
     const Lane L;
-    const int e = 2 * (st - S0), q = e >> 2, r = e & 3, j = L.col;
+    const int e = 2 * (st - S0), q = e >> 2, r = e & 3;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int i = L.template row<T>(q, r + u);
-      const cpx<T> v = TRANS ? M[(size_t)j * 64 + i] : M[(size_t)i * 64 + j];
+      const cpx<T> v = *tile_elem<T, TRANS>(const_cast<cpx<T>*>(M), q, r + u, L);
       X.re[q][r + u] = v.re; X.im[q][r + u] = v.im;
     }
   }
@@ -86,7 +97,7 @@ struct TileStore {
     const Lane L;
     const int q = st >> 2, r = st & 3;
     cpx<T> v; v.re = X.re[q][r]; v.im = X.im[q][r];
-    M[(size_t)L.template row<T>(q, r) * 64 + L.col] = v;
+    *tile_elem<T, false>(M, q, r, L) = v;
   }
 };
 
@@ -511,7 +522,9 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   }
   ck.mark(3);
   if constexpr (st && !hk) rt_store<T, false>(V, ws + WS_QINV * TILE, 64);
-  // D = r_m(A) - I = X_Q + X_P + X_Q X_P
+  // D = r_m(A) - I = X_Q + X_P + X_Q X_P (slot 1 may still be read by the
+  // inverse's last product in other waves)
+  __syncthreads();
   put<T, false>(V, slot<T, 1>(sh, gs));
   __syncthreads();
   rt_copy(R, U);
