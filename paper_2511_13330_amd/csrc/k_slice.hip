@@ -406,7 +406,11 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   ck.mark(0);
   constexpr bool st = ST;   // compile-time, so that the stores are straight-line code
 
-  __syncthreads();
+  // Slot use: 0 holds A, 1 A^2 then X_Q, 2 Neumann and squaring operands, 3 the
+  // chain's D (written by the caller). A write to a slot needs a barrier after
+  // its last read only where no barrier has passed since: the previous slice's
+  // last reads of slots 0 and 1 (and of 3, by the chain) are all at least two
+  // barriers back when this slice first writes them.
   put<T, false>(A, slot<T, 0>(sh, gs));
   __syncthreads();
   RT<T> A2;
@@ -467,7 +471,6 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     // Q^{-1} = sum_{k<=D} c_k A^k, the power series of 1/q_m (D = K - 16; its
     // tail is below the unit roundoff by the selection rule); c_0 = 1
     const double* c = m == 2 ? a.pade.c2 : a.pade.c3;   // computed once on the host
-    __syncthreads();
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
     if (K - 16 == 4) {
@@ -665,8 +668,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
       cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
       RT<T> D;
       fwd_slice<T, ST>(D, A, P.hi, sh, gs, a, n, ws, ck);
-      __syncthreads();
-      put<T, false>(D, slot<T, 3>(sh, gs));
+      put<T, false>(D, slot<T, 3>(sh, gs));   // slot 3's last reader is the previous chain
       __syncthreads();
       // the next slice's Omega tile, spread over the chain product (the chunk's
       // last slice reloads its own, so that the loads are unconditional)
@@ -842,7 +844,8 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     }
   }
   ck.mark(8);
-  // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T
+  // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T (with s = 0 no wave still reads
+  // slot 0 here, but the barrier keeps the waves together: measured faster)
   __syncthreads();
   put<T, false>(R, slot<T, 0>(sh, gs));
   __syncthreads();
