@@ -183,20 +183,28 @@ const std::pair<int, int>* tuned_for(const lmag_ctx* c, long long total) {
   return nullptr;
 }
 
-int auto_chunk(const lmag_ctx* c, long long total) {
+// Automatic chunk length (slices per work unit): with up to 64 slices per
+// compute unit, one chunk each; above that about four chunks per workgroup (the
+// persistent kernels take chunks from a counter, which balances uneven items),
+// between 64 and 256 slices. Longer chunks mean fewer chunk totals to scan and
+// fewer environments (3-spin, 64 x 4096 slices: 256 measured 2 % faster than
+// 64, with the same accuracy against the FP64 oracle). Recompute mode stays at
+// 64: its per-workgroup scratch grows with the chunk.
+int auto_chunk(const lmag_ctx* c, long long total, bool recompute) {
   if (c->chunk > 0) return c->chunk;
   if (const auto* t = tuned_for(c, total)) return t->first;
   const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
-  return (int)std::min<long long>(64, std::max<long long>(1, per));
+  if (per <= 64) return (int)std::max<long long>(1, per);
+  return (int)std::min<long long>(recompute ? 64 : 256, std::max<long long>(64, per / 4));
 }
 
 // Plan of one wave: the caller's items `idx` (grouped calls: whole groups,
 // with wave-local group numbers).
 void plan_wave(const lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
-               const std::vector<int>& idx, Plan& p) {
+               const std::vector<int>& idx, Plan& p, bool recompute) {
   long long total = 0;
   for (int i : idx) total += b->n_slices[i];
-  const int C = auto_chunk(c, total);
+  const int C = auto_chunk(c, total, recompute);
   p.chunk_size = C;
   const int n = (int)idx.size();
   p.items.resize(n);
@@ -648,7 +656,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     const long long want_chunks = std::max<long long>(1, 2048 / ((long long)Tn * Tn));
     c->chunk = (int)std::max<long long>(1, (total + want_chunks - 1) / want_chunks);
   }
-  plan_wave(c, b, target_of_item, all, p);
+  plan_wave(c, b, target_of_item, all, p, false);
   c->chunk = saved_chunk;
   const int Ns = p.total_slices, Lc = p.total_chunks, C = p.chunk_size;
   BigPlan q;
@@ -1038,7 +1046,7 @@ lmag_status run_waves(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of
   const int nt = fidelity ? n_targets : 0;
   auto fits = [&](const std::vector<int>& idx, bool recompute, Plan& p, Layout& L, int& grid) {
     p = Plan();
-    plan_wave(c, b, target_of_item, idx, p);
+    plan_wave(c, b, target_of_item, idx, p, recompute);
     p.recompute = recompute;
     grid = std::max(1, std::min(p.total_chunks, c->n_cu));
     L = layout(c, p, nt, grad, grid);
@@ -1396,7 +1404,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     std::vector<int> chunks;
     for (int C : {2, 4, 8, 16, 32, 64, 128, 256})
       if (C <= std::max<long long>(2, 4 * per) && C >= std::min<long long>(per / 4, 64)) chunks.push_back(C);
-    if (chunks.empty()) chunks.push_back(auto_chunk(c, total));
+    if (chunks.empty()) chunks.push_back(auto_chunk(c, total, false));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);

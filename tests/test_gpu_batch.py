@@ -120,3 +120,25 @@ def test_nan_amplitudes_propagate_to_F():
                                   cfg["dt"], cfg["U_target"],
                                   static_coef=np.asarray(cfg["B"])[None, :])
     assert torch.isnan(F).all()
+
+
+def test_benchmark_batch_plan_and_consistency():
+    """The benchmark's batch, 64 config-1 pulses: the automatic chunk length is
+    256 slices (about four chunks per workgroup), and each pulse's F and
+    gradient equal those of the same pulse evaluated alone."""
+    B = 64
+    cfg = synth.config1_batch(B)
+    sysm = lib_system(cfg)
+    amps = cfg["amps_batch"].astype(np.float32)
+    st = np.tile(np.asarray(cfg["B"])[None, :], (B, 1))
+    a = torch.tensor(amps.reshape(B * 4096, 2), device="cuda")
+    F, g = sysm.fidelity_and_grad(a, [4096] * B, cfg["dt"], cfg["U_target"], static_coef=st)
+    plan = sysm.last_plan()
+    assert plan["total_slices"] == B * 4096 and plan["chunk_slices"] == 256
+    F = F.cpu().numpy()
+    g = g.cpu().numpy().reshape(B, 4096, 2).astype(np.float64)
+    for i in (0, 17, 63):
+        Fi, gi = sysm.fidelity_and_grad(torch.tensor(amps[i], device="cuda"), [4096], cfg["dt"],
+                                        cfg["U_target"], static_coef=st[:1])
+        assert abs(F[i] - Fi.cpu().numpy()[0]) <= 1e-6
+        assert rel(g[i], gi.cpu().numpy().astype(np.float64)) <= 1e-4

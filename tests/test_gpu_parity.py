@@ -142,6 +142,28 @@ def test_config1_gradient_sampled(config1_run):
     assert rel(ours, fd) <= 1e-3
 
 
+def test_config1_long_chunks():
+    """256-slice chunks, the length the automatic rule picks at the benchmark
+    size: longer FP32 adjoint chains per chunk, fewer chunk totals to scan."""
+    cfg = synth.config1()
+    sysm = lib_system(cfg, chunk=256)
+    amps = rounded(cfg["amps"], "f32")
+    F, g = lib_fid(sysm, cfg, amps)
+    assert sysm.last_plan()["chunk_slices"] == 256
+    U = sysm.propagate(to_dev(amps, sysm), [4096], cfg["dt"],
+                       static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    assert rel(U, U_ref) <= 1e-4
+    coords = np.asarray(cfg["fd_coords"])
+    rows = sorted(set(int(c) // 2 for c in coords))
+    F_ref, g_at = oracle.grad_adjoint_at(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"], rows)
+    assert abs(F[0] - F_ref) <= 1e-6
+    ours = np.array([g[int(c) // 2, int(c) % 2] for c in coords])
+    adj = np.array([g_at[int(c) // 2][int(c) % 2] for c in coords])
+    assert rel(ours, adj) <= 1e-3
+
+
 def test_config1_high_fidelity_closed_system():
     """F near 1 is where rounding along the 4096-slice chain shows most (the
     error of F is first order in any non-unitary drift of the product). The
