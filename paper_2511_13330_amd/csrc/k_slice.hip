@@ -427,9 +427,9 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   RT<T> V;   // the even part minus I
   RT<T> U;   // the odd part
   if (sizeof(T) == 4 && m == 2) {
-    // Pade-2: U = b_1 A (from the copy in LDS), V - I = b_2 A^2, no product
+    // Pade-2: U = b_1 A, V - I = b_2 A^2, no product
     rt_poly1(V, A2, (T)b[2], T(0));
-    rt_load<T, false>(U, slot<T, 0>(sh, gs), PITCH);
+    rt_copy(U, A);
     rt_scale(U, (T)b[1]);
   } else {
   RT<T> W;
@@ -476,7 +476,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     if (K - 16 == 4) {
       // degree 4 with A and A^2 at hand: X_Q = c_1 A + A^2 (c_2 I + c_3 A + c_4 A^2),
       // one product
-      RT<T> Bk;
+      RT<T> Bk;   // A again, from LDS: a register copy here makes this branch spill
       rt_load<T, false>(Bk, slot<T, 0>(sh, gs), PITCH);
       rt_copy(V, Bk);
       rt_scale(V, (T)c[1]);
