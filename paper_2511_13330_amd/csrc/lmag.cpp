@@ -1060,6 +1060,8 @@ lmag_status run_waves(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of
       if (cut >= grid) return false;
       grid -= cut;
       L = layout(c, p, nt, grad, grid);
+      // the estimate ignores buffer alignment: drop workgroups until it fits
+      while (L.total > budget && grid > 1) L = layout(c, p, nt, grad, --grid);
     }
     return L.total <= budget;
   };
