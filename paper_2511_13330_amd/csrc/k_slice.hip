@@ -317,6 +317,59 @@ __global__ void __launch_bounds__(WG) k_traces_sparse(SliceArgs a, int n_total) 
   }
 }
 
+// The same traces with the slice-invariant entry table and each slice's compact
+// K_n^T staged in LDS (dynamic shared memory, laid out by tr_lds_bytes). Lanes
+// are grouped by basis element, LPJ lanes each; lane sub of the group of j
+// sums the entries ptr_j[j] + sub + LPJ k in ascending k, in FP64, and the
+// group is reduced by shuffles in a fixed order, so the result is bitwise
+// deterministic. One wave per slice, TR_SPB slices per workgroup.
+constexpr int TR_SPB = 32;
+constexpr size_t TR_LDS_MAX = 64 * 1024;
+
+template <typename T>
+__host__ __device__ inline size_t tr_lds_bytes(int nnz, int n_sup, int nb) {
+  return (size_t)nnz * sizeof(cpx<T>) + (size_t)4 * n_sup * sizeof(cpx<T>) +
+         (size_t)((nnz + 1) & ~1) * 2 + (size_t)(nb + 1) * 4;
+}
+
+template <typename T, int LPJ>
+__global__ void __launch_bounds__(WG) k_traces_lds(SliceArgs a, int n_total) {
+  extern __shared__ __align__(16) char tr_smem[];
+  const SparseBasis& sp = a.sp;
+  const int nnz = sp.nnz, nsup = sp.n_sup, nb = a.nb;
+  cpx<T>* tval = reinterpret_cast<cpx<T>*>(tr_smem);          // [nnz]
+  cpx<T>* kbuf = tval + nnz;                                   // [4][n_sup]
+  uint16_t* tslot = reinterpret_cast<uint16_t*>(kbuf + 4 * nsup);   // [nnz]
+  int* tptr = reinterpret_cast<int*>(tslot + ((nnz + 1) & ~1));     // [nb + 1]
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const cpx<T>* ev = (const cpx<T>*)sp.ent_val;
+  for (int i = tid; i < nnz; i += WG) { tval[i] = ev[i]; tslot[i] = sp.ent_slot[i]; }
+  for (int i = tid; i <= nb; i += WG) tptr[i] = sp.ptr_j[i];
+  __syncthreads();
+  const int j = l / LPJ, sub = l % LPJ;
+  cpx<T>* kw = kbuf + w * nsup;
+  for (int r = 0; r < TR_SPB / 4; ++r) {
+    const int n = blockIdx.x * TR_SPB + 4 * r + w;   // wave-uniform
+    const bool valid = n < n_total;
+    if (valid) {
+      const cpx<T>* kc = tile_at<T>(a.omega, (size_t)n);
+      for (int i = l; i < nsup; i += 64) kw[i] = kc[i];
+    }
+    __syncthreads();   // every wave runs the same rounds
+    if (valid && j < nb) {
+      double t = 0.0;
+      for (int i = tptr[j] + sub; i < tptr[j + 1]; i += LPJ) {
+        const cpx<T> k = kw[tslot[i]], b = tval[i];
+        t += (double)(k.re * b.re - k.im * b.im);
+      }
+#pragma unroll
+      for (int off = 1; off < LPJ; off <<= 1) t += __shfl_xor(t, off);   // within the group
+      if (sub == 0) a.gtrace[(size_t)n * nb + j] = t;
+    }
+    __syncthreads();   // kw is overwritten next round
+  }
+}
+
 // g_{n,j} = Re sum_x K^T_n[x] B_j[x] over flat positions x (K^T stored where A_n was).
 // Each thread sums its 16 positions in FP32; lanes and waves are combined in FP64.
 constexpr int TRACE_SLICES = 4;
@@ -957,6 +1010,20 @@ hipError_t launch_omega(int prec, const SliceArgs& a, int n_total, hipStream_t s
 hipError_t launch_traces(int prec, const SliceArgs& a, int n_total, hipStream_t s) {
   if (n_total <= 0) return hipSuccess;
   if (a.sp.n_sup > 0) {
+    const size_t lds = prec == 32 ? tr_lds_bytes<float>(a.sp.nnz, a.sp.n_sup, a.nb)
+                                  : tr_lds_bytes<double>(a.sp.nnz, a.sp.n_sup, a.nb);
+    if (lds <= TR_LDS_MAX && a.nb <= 32) {
+      const dim3 g((n_total + TR_SPB - 1) / TR_SPB);
+      const bool four = a.nb <= 16;   // lanes per basis element: 64 / nb, a power of two
+      if (prec == 32) {
+        if (four) hipLaunchKernelGGL((k_traces_lds<float, 4>), g, dim3(WG), lds, s, a, n_total);
+        else hipLaunchKernelGGL((k_traces_lds<float, 2>), g, dim3(WG), lds, s, a, n_total);
+      } else {
+        if (four) hipLaunchKernelGGL((k_traces_lds<double, 4>), g, dim3(WG), lds, s, a, n_total);
+        else hipLaunchKernelGGL((k_traces_lds<double, 2>), g, dim3(WG), lds, s, a, n_total);
+      }
+      return hipGetLastError();
+    }
     const dim3 g((n_total + 3) / 4);
     if (prec == 32) hipLaunchKernelGGL(k_traces_sparse<float>, g, dim3(WG), 0, s, a, n_total);
     else hipLaunchKernelGGL(k_traces_sparse<double>, g, dim3(WG), 0, s, a, n_total);
