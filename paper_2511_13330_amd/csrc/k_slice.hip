@@ -231,12 +231,17 @@ __global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
 // Omega_n / 2^s from the sparse basis: one wave per slice, lane c owns column c.
 // Each support entry is summed over its basis terms in ascending j (the order of
 // the dense kernel, whose other terms are exact zeros) into registers; the FP64
-// column 1-norm selects (m, s); the lane then writes its column: zeros with
-// row-coalesced stores, followed (same lane, same addresses, program order) by
-// its support values.
+// column 1-norm selects (m, s). The tile goes out in blocks of OM_RB rows: the
+// lane writes its column of the block into LDS (zeros, then its support values
+// at their rows: LDS stands in for a register array indexed by row), reads it
+// back and stores row-coalesced, so every line of the tile is written once.
+template <typename T> struct OmRows { static constexpr int RB = sizeof(T) == 4 ? 8 : 4; };
+
 template <typename T>
 __global__ void __launch_bounds__(WG) k_omega_sparse(SliceArgs a, int n_total) {
+  constexpr int RB = OmRows<T>::RB;
   __shared__ T al_sh[4][MAXNB];
+  __shared__ cpx<T> blk[4][RB][64];   // per wave; each lane uses only its own column
   const int w = threadIdx.x >> 6, c = threadIdx.x & 63;
   const int n = blockIdx.x * 4 + w;
   const bool valid = n < n_total;
@@ -280,16 +285,22 @@ __global__ void __launch_bounds__(WG) k_omega_sparse(SliceArgs a, int n_total) {
   }
   const T f = (T)ldexp(1.0, -sc);
   cpx<T>* out = tile_at<T>(a.omega, (size_t)n);
+  cpx<T>(*col)[64] = blk[w];
   const cpx<T> zero{T(0), T(0)};
-  for (int r = 0; r < 64; ++r) out[r * 64 + c] = zero;
+  for (int b = 0; b < 64 / RB; ++b) {
 #pragma unroll
-  for (int q = 0; q < SP_COLCAP; ++q)
-    if (q < cnt) {
-      cpx<T> x;
-      x.re = v[q].re * f;
-      x.im = v[q].im * f;
-      out[row[q] * 64 + c] = x;
-    }
+    for (int r = 0; r < RB; ++r) col[r][c] = zero;
+#pragma unroll
+    for (int q = 0; q < SP_COLCAP; ++q)
+      if (q < cnt && row[q] / RB == b) {
+        cpx<T> x;
+        x.re = v[q].re * f;
+        x.im = v[q].im * f;
+        col[row[q] % RB][c] = x;
+      }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) out[(b * RB + r) * 64 + c] = col[r][c];
+  }
 }
 
 // Traces from the compact K_n^T (its support positions, stored at the start of
