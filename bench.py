@@ -138,7 +138,7 @@ def record_traffic(fetch_csv, write_csv, slices, copy_bytes):
         scales[counter] = kib / max(copies)
         for name, vals in rows.items():
             for kern in ("k_forward", "k_backward", "k_omega", "k_traces", "k_omega_sparse",
-                         "k_traces_sparse"):
+                         "k_traces_sparse", "k_traces_lds"):
                 if f"lmag::{kern}<" in name:
                     out.setdefault(kern, {})[counter] = float(np.mean(vals))
     h = hashlib.sha256()
