@@ -118,12 +118,6 @@ struct SupportStore {
   }
 };
 
-template <typename H1, typename H2>
-struct Hooks2 {
-  H1 h1; H2 h2;
-  __device__ __forceinline__ void operator()(int st) const { h1(st); h2(st); }
-};
-
 template <typename H1, typename H2, typename H3>
 struct Hooks3 {
   H1 h1; H2 h2; H3 h3;
