@@ -591,7 +591,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   rt_copy(R, U);
   rt_axpy(R, T(1), V);
   if constexpr (st && hk)
-    mm(R, slot<T, 1>(sh, gs), U, TileStore<T>{V, ws + WS_QINV * TILE});
+    mm<T, false>(R, slot<T, 1>(sh, gs), U, TileStore<T>{V, ws + WS_QINV * TILE});
   else
     mm(R, slot<T, 1>(sh, gs), U);
   if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
@@ -773,7 +773,8 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   RT<T> E;
   rt_zero(E);
   if constexpr (bwd_carry<T>) {
-    mm(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true>{R, ws + WS_S * TILE});
+    // (this product and the D product run unpipelined: measured faster here)
+    mm<T, false>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true>{R, ws + WS_S * TILE});
   } else {
     rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
     mm(E, slot<T, 0>(sh, gs), Pl);
