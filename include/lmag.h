@@ -95,7 +95,11 @@ typedef struct {
   int hold;                     /* LMAG_ZOH (u constant per slice) or LMAG_FOH        */
                                 /* (u linear from u_n to u_{n+1}; u_N := u_{N-1})   */
   size_t workspace_bytes_max;   /* 0 = no limit beyond device memory                 */
-  int chunk_slices;             /* slices per work unit; 0 = automatic               */
+  int chunk_slices;             /* slices per work unit; 0 = automatic: the autotuned */
+                                /* length if one is cached for this call's size, else */
+                                /* one chunk per compute unit up to 64 slices per unit,*/
+                                /* above that about four chunks per workgroup within  */
+                                /* 64..256 slices (64 when the adjoint recomputes)    */
 } lmag_system_desc;
 
 /* Install (or replace) the system. Builds the superoperator basis on the
