@@ -10,8 +10,8 @@ namespace lmag {
 // scaling thresholds theta_m, for the degrees this library evaluates.
 struct PadeTable {
   double b2[3], b3[4], b5[6], b7[8];
-  double ser_max32_2, ser_max32_3;   // largest ||A||_1 for the series inverse of q_2, q_3 (FP32)
-  double c2[8], c3[8];               // power series of 1/q_2, 1/q_3 (c_0 = 1), degrees 0..7
+  double ser_max32_2, ser_max32_3;   // largest ||A||_1 for the series of r_2, of 1/q_3 (FP32)
+  double r2[8], c3[8];               // power series of r_2, of 1/q_3 (both 1 at degree 0), degrees 0..7
 };
 
 // Sparse form of a 64 x 64 basis (built by set_system from its nonzero entries

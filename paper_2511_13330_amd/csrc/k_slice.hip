@@ -467,8 +467,8 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   // Slot use: 0 holds A, 1 A^2 then X_Q, 2 Neumann and squaring operands, 3 the
   // chain's D (written by the caller). A write to a slot needs a barrier after
   // its last read only where no barrier has passed since: the previous slice's
-  // last reads of slots 0 and 1 (and of 3, by the chain) are all at least two
-  // barriers back when this slice first writes them.
+  // last reads of slots 0 and 1 (and of 3, by the chain) are all at least one
+  // barrier back when this slice first writes them.
   put<T, false>(A, slot<T, 0>(sh, gs));
   __syncthreads();
   RT<T> A2;
@@ -480,8 +480,31 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     mm(A2, slot<T, 0>(sh, gs), A);
   }
   ck.mark(1);
-  // the Pade-2 adjoint does not read A^2; single precision stores it below
+  // single precision stores A^2 during the next product
   if constexpr (st && !hk) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
+  const int K = slice_inverse_code(a, n);
+  if (sizeof(T) == 4 && m == 2 && K >= 16) {
+    // r_2(A) by its power series, truncated at degree 4 (the selection rule keeps
+    // the tail below u/2): D = r_2(A) - I = rho_1 A + A^2 (rho_2 I + rho_3 A + rho_4 A^2),
+    // one product, during which A^2 is stored for the adjoint
+    const double* r = a.pade.r2;   // computed once on the host
+    put<T, false>(A2, slot<T, 1>(sh, gs));
+    __syncthreads();
+    ck.mark(2);
+    RT<T> Bk;   // A again, from LDS: a register copy here makes this branch spill
+    rt_load<T, false>(Bk, slot<T, 0>(sh, gs), PITCH);
+    rt_copy(R, Bk);
+    rt_scale(R, (T)r[1]);
+    rt_scale(Bk, (T)r[3]);
+    rt_axpy(Bk, (T)r[4], A2);
+    rt_add_diag(Bk, (T)r[2]);
+    ck.mark(3);
+    if constexpr (st)
+      mm<T, false>(R, slot<T, 1>(sh, gs), Bk, TileStore<T>{A2, ws + WS_A2 * TILE});
+    else
+      mm<T, false>(R, slot<T, 1>(sh, gs), Bk);
+    if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
+  } else {
   RT<T> V;   // the even part minus I
   RT<T> U;   // the odd part
   if (sizeof(T) == 4 && m == 2) {
@@ -524,25 +547,12 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   }
   ck.mark(2);
   // X_Q = Q^{-1} - I into V
-  const int K = slice_inverse_code(a, n);
   if (sizeof(T) == 4 && K >= 16) {
-    // Q^{-1} = sum_{k<=D} c_k A^k, the power series of 1/q_m (D = K - 16; its
-    // tail is below the unit roundoff by the selection rule); c_0 = 1
-    const double* c = m == 2 ? a.pade.c2 : a.pade.c3;   // computed once on the host
+    // Pade-3: Q^{-1} = sum_{k<=5} c_k A^k, the power series of 1/q_3 (its tail
+    // is below the unit roundoff by the selection rule); c_0 = 1
+    const double* c = a.pade.c3;   // computed once on the host
     put<T, false>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
-    if (K - 16 == 4) {
-      // degree 4 with A and A^2 at hand: X_Q = c_1 A + A^2 (c_2 I + c_3 A + c_4 A^2),
-      // one product
-      RT<T> Bk;   // A again, from LDS: a register copy here makes this branch spill
-      rt_load<T, false>(Bk, slot<T, 0>(sh, gs), PITCH);
-      rt_copy(V, Bk);
-      rt_scale(V, (T)c[1]);
-      rt_scale(Bk, (T)c[3]);
-      rt_axpy(Bk, (T)c[4], A2);
-      rt_add_diag(Bk, (T)c[2]);
-      mm(V, slot<T, 1>(sh, gs), Bk);
-    } else {
     RT<T> A4;
     rt_zero(A4);
     mm(A4, slot<T, 1>(sh, gs), A2);
@@ -552,7 +562,6 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     rt_poly1(V, A2, (T)c[2], T(0));
     rt_axpy(V, (T)c[4], A4);
     mm(V, slot<T, 0>(sh, gs), odd);   // X_Q = even - I + A odd
-    }
   } else if (K > 0 && K < 16) {
     // binary Neumann product on MFMA: Q^{-1} = (I + F)(I + F^2)(I + F^4)...,
     // F = I - Q = -E_Q; with X = Q^{-1} - I each level is X += F2 + F2 X
@@ -595,6 +604,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   else
     mm(R, slot<T, 1>(sh, gs), U);
   if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
+  }
   ck.mark(4);
   // squarings: (I + D)^2 = I + 2 D + D^2
   for (int k = 0; k < s; ++k) {
@@ -758,7 +768,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   const int m = ms.m, s = ms.s;
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
-  // D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T. Single precision requests each
+  // r_2 by its degree-4 series in the forward: the adjoint differentiates that
+  // polynomial and reads A^2 in place of Q^{-1}
+  const bool ser2 = sizeof(T) == 4 && m == 2 && slice_inverse_code(a, n) >= 16;
+  // D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T (or A^2). Single precision requests each
   // stored tile one product ahead of its use, spread over that product's
   // k-steps: a wave that requests whole tiles at once stalls on issue (about 4K
   // cycles for three tiles). Double precision loads each where it is needed.
@@ -791,10 +804,38 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   rt_zero(L2);
   mm(L2, slot<T, 0>(sh, gs), E);
   if constexpr (bwd_carry<T>)
-    mm(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true>{Qi, ws + WS_QINV * TILE});
+    mm(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
   else
     mm(L2, slot<T, 1>(sh, gs), A);
   ck.mark(3);
+  RT<T> K;
+  if (ser2) {
+    // the Frechet derivative of the degree-4 polynomial sum_k rho_k A^k:
+    // L = rho_1 E + rho_2 L_2 + rho_3 L_3 + rho_4 L_4 with L_3 = L_2 A + A^2 E and
+    // L_4 = L_2 A^2 + A^2 L_2, i.e.
+    // L = rho_1 E + rho_2 L_2 + L_2 (rho_3 A + rho_4 A^2) + A^2 (rho_3 E + rho_4 L_2).
+    // A polynomial's derivative commutes with transposition, so the same formula
+    // holds for the transposed operands held here (Qi holds (A^2)^T).
+    const double* r = a.pade.r2;
+    put<T, false>(L2, slot<T, 2>(sh, gs));
+    put<T, false>(Qi, slot<T, 3>(sh, gs));
+    __syncthreads();
+    ck.mark(4);
+    RT<T> Bq, Lq;
+    rt_copy(Bq, A);
+    rt_scale(Bq, (T)r[3]);
+    rt_axpy(Bq, (T)r[4], Qi);
+    rt_load<T, false>(Lq, slot<T, 1>(sh, gs), PITCH);   // E
+    rt_copy(K, Lq);
+    rt_scale(K, (T)r[1]);
+    rt_axpy(K, (T)r[2], L2);
+    rt_scale(Lq, (T)r[3]);
+    rt_axpy(Lq, (T)r[4], L2);
+    ck.mark(5);
+    mm(K, slot<T, 2>(sh, gs), Bq);
+    ck.mark(6);
+    mm(K, slot<T, 3>(sh, gs), Lq);
+  } else {
   RT<T> W, LW, LV;
   const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
   if (pade2) {
@@ -868,9 +909,9 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     for (int q = 0; q < 4; ++q) { LU.re[q] -= Tm.re[q]; LU.im[q] -= Tm.im[q]; }
   }
   // L = Q^{-1} X = X + (Q^{-1} - I) X
-  RT<T> K;
   rt_copy(K, LU);
   mm(K, slot<T, 2>(sh, gs), LU);
+  }
   for (int k = 0; k < s; ++k) {
     __syncthreads();
     put<T, false>(R, slot<T, 0>(sh, gs));

@@ -1151,9 +1151,9 @@ lmag_status lmag_create(lmag_ctx** out, int hip_device) {
     pade_coeffs(5, c->pade.b5);
     pade_coeffs(7, c->pade.b7);
     pade_coeffs(2, c->pade.b2);
-    c->pade.ser_max32_2 = series_limit32(c->pade.b2, 2, series_degree(2));
-    c->pade.ser_max32_3 = series_limit32(c->pade.b3, 3, series_degree(3));
-    inv_series(c->pade.b2, 2, c->pade.c2, 8);
+    c->pade.ser_max32_2 = series_limit32(c->pade.b2, 2, series_degree(2), true);
+    c->pade.ser_max32_3 = series_limit32(c->pade.b3, 3, series_degree(3), false);
+    pade_series(c->pade.b2, 2, c->pade.r2, 8);
     inv_series(c->pade.b3, 3, c->pade.c3, 8);
     *out = c;
     return LMAG_OK;

@@ -85,29 +85,60 @@ __host__ __device__ inline double inv_series_tail(const double* b, int m, int D,
   return tail;
 }
 
-// Largest ||A||_1 for which the degree-D series of 1/q_m has tail <= u / 2 in
-// single precision. The tail increases with ||A||_1, so a slice may use the
-// series exactly when its norm is at most this limit (bisection, host side).
-inline double series_limit32(const double* b, int m, int D) {
+// Power series of r_m(x) = p_m(x) / q_m(x), p_m(x) = sum_j b_j x^j:
+// rho_k = sum_{j=0}^{min(k,m)} b_j c_{k-j} with c the series of 1/q_m. The
+// [m/m] approximant matches e^x through degree 2m, so rho_k = 1/k! for k <= 2m.
+__host__ __device__ inline void pade_series(const double* b, int m, double* rho, int K) {
+  double c[48];
+  inv_series(b, m, c, K < 48 ? K : 48);
+  for (int k = 0; k < K && k < 48; ++k) {
+    double v = 0.0;
+    for (int j = 0; j <= m && j <= k; ++j) v += b[j] * c[k - j];
+    rho[k] = v;
+  }
+}
+
+// Tail sum_{k > D} |rho_k| x^k of the series of r_m (48 terms, as above).
+__host__ __device__ inline double pade_series_tail(const double* b, int m, int D, double x) {
+  double rho[48];
+  pade_series(b, m, rho, 48);
+  double tail = 0.0, p = 1.0;
+  for (int k = 1; k < 48; ++k) {
+    p *= x;
+    if (k > D) tail += fabs(rho[k]) * p;
+  }
+  return tail;
+}
+
+// Largest ||A||_1 for which a truncated series has tail <= u / 2 in single
+// precision: the degree-D series of r_m (of_r = true) or of 1/q_m. The tail
+// increases with ||A||_1, so a slice may use the series exactly when its norm
+// is at most this limit (bisection, host side).
+inline double series_limit32(const double* b, int m, int D, bool of_r) {
   const double u = 5.9604644775390625e-8;
   double lo = 0.0, hi = 1.0;
   for (int it = 0; it < 200; ++it) {
     const double mid = 0.5 * (lo + hi);
-    if (inv_series_tail(b, m, D, mid) <= 0.5 * u) lo = mid; else hi = mid;
+    const double t = of_r ? pade_series_tail(b, m, D, mid) : inv_series_tail(b, m, D, mid);
+    if (t <= 0.5 * u) lo = mid; else hi = mid;
   }
   return lo;
 }
 
-// Series degree used for each single-precision Pade degree: 1/q_2 needs degree
-// 4 (its c_5 is zero), 1/q_3 degree 5; both take A^4 and one product with A.
+// Series degree used for each single-precision Pade degree. m = 2: r_2 itself
+// at degree 4 (r_2 agrees with e^x through degree 4, so the truncation is the
+// degree-4 Taylor polynomial; beyond theta_2 = 0.0809 it is not used), one
+// product after A^2. m = 3: 1/q_3 at degree 5, A^4 and one product with A.
 constexpr int series_degree(int m) { return m == 2 ? 4 : 5; }
 
-// Inverse of the Pade denominator, per slice (code stored with the slice):
-//   16 + D  power series of 1/q_m truncated at degree D = series_degree(m)
-//           (single precision, m in {2, 3}), when sum_{k > D} |c_k| ||A||_1^k
-//           <= u / 2, i.e. when ||A||_1 <= the limit for that m;
-//   1..5    binary Neumann product with that many levels;
-//   0       Gauss-Jordan.
+// How a slice evaluates r_m(A) (code stored with the slice):
+//   16 + D  single precision, D = series_degree(m): m = 2, r_2(A) by its
+//           power series truncated at degree D; m = 3, r_3 = q_3^{-1} p_3 with
+//           q_3^{-1} by its series truncated at degree D. Used when the tail
+//           of that series at ||A||_1 is <= u / 2, i.e. when ||A||_1 <= the
+//           limit for that m;
+//   1..5    r_m = q_m^{-1} p_m, binary Neumann product with that many levels;
+//   0       r_m = q_m^{-1} p_m, Gauss-Jordan.
 template <typename T>
 __device__ __forceinline__ int inverse_code(double nA, const double* b, int m, int allow_series,
                                             double ser_max2, double ser_max3) {
