@@ -31,7 +31,11 @@ PI_M = {2: 1, 3: 2, 5: 3, 7: 4}       # products to evaluate the Pade-m numerato
 
 
 def forward_flops_per_slice(m, s):
-    # Pade products + squarings + one n x n solve (4/3) + the ordered product (1)
+    # m = 2 (single precision, r_2 by its degree-4 series): A^2, one product,
+    # squarings, the ordered product; otherwise Pade products + squarings + one
+    # n x n solve (4/3) + the ordered product (1)
+    if m == 2:
+        return (2.0 + s + 1.0) * M_FLOPS
     return (PI_M[m] + s + 4.0 / 3.0 + 1.0) * M_FLOPS
 
 
@@ -198,7 +202,9 @@ def robust_sweep(args):
     dt = (time.perf_counter() - t0) / steps
     plan = sysm.last_plan()
     slices = int(ns.sum())
-    flops = slices * (forward_flops_per_slice(3, 0) + backward_flops_per_slice(3, 0))
+    hist = sysm.selection_histogram()   # of the call's last wave: its (m, s) mix stands for all
+    flops = (flops_from_hist(hist, forward_flops_per_slice)
+             + flops_from_hist(hist, backward_flops_per_slice)) * slices / max(1, int(hist.sum()))
     return {"metric": "robust sweep: candidates x noise samples fwd+grad, seconds per sweep",
             "value": dt, "unit": "s/sweep", "n_gpus": 1, "higher_is_better": False,
             "vs_baseline": None, "dtype": "f32",
@@ -239,12 +245,8 @@ def large_system(args):
     prof = sysm.read_profile()
     hist = sysm.selection_histogram()
     n = 4 ** cfg["n_spins"]
-    Mf = 8.0 * n ** 3
-    flops = 0.0
-    for mi, m in enumerate((2, 3, 5, 7)):
-        for s in range(hist.shape[1]):
-            if hist[mi, s]:
-                flops += hist[mi, s] * (3 * PI_M[m] + 3 * s + 19.0 / 3.0) * Mf
+    flops = (flops_from_hist(hist, forward_flops_per_slice)
+             + flops_from_hist(hist, backward_flops_per_slice)) * (n / N_SUPER) ** 3
     return {"metric": f"fwd+grad evaluations/s ({cfg['n_spins']} spins, {N} slices)",
             "value": 1.0 / dt, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
             "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded config-3 draws)",

@@ -109,3 +109,63 @@ def test_create_without_gpu_reports_device_error(L):
         pytest.skip("a GPU is present")
     ctx = ctypes.c_void_p()
     assert L.lmag_create(ctypes.byref(ctx), 0) == -4
+
+
+def _pade_power_series(m, K):
+    """Power series of r_m = p_m / q_m in exact rationals: p_m times the series
+    of 1 / q_m (from q_m(x) * sum_k c_k x^k = 1)."""
+    b = exact_pade(m)
+    q = [bj * (-1) ** j for j, bj in enumerate(b)]
+    c = [Fr(1)] + [Fr(0)] * (K - 1)
+    for k in range(1, K):
+        c[k] = -sum(q[j] * c[k - j] for j in range(1, min(k, m) + 1))
+    return _series_mul(b + [Fr(0)] * K, c, K)
+
+
+def test_pade2_series_path_covers_every_pade2_slice(L):
+    # single precision evaluates r_2(A) by its power series cut at degree 4:
+    # through degree 4 that series is e^x's (the [2/2] approximant matches e^x
+    # to order 4), and the dropped tail sum_{k>4} |rho_k| x^k stays below u/2 at
+    # theta_2, so every slice that selects Pade-2 qualifies
+    rho = _pade_power_series(2, 60)
+    assert rho[:5] == [Fr(1, factorial(k)) for k in range(5)]
+    assert rho[5] == Fr(1, 144)   # not 1/120: beyond degree 4 it is no longer e^x's
+    t = ctypes.c_double()
+    assert L.lmag_pade_theta(32, 2, ctypes.byref(t)) == 0
+    tail = sum(abs(float(r)) * t.value ** k for k, r in enumerate(rho) if k > 4)
+    assert tail <= 2.0 ** -25
+    # and the cut is not vacuous: at 1.2 theta_2 the tail exceeds u/2
+    assert sum(abs(float(r)) * (1.2 * t.value) ** k for k, r in enumerate(rho) if k > 4) > 2.0 ** -25
+
+
+def test_degree4_frechet_factorisation():
+    # the adjoint of the degree-4 path forms
+    #   L = r1 E + r2 L2 + L2 (r3 A + r4 A^2) + A^2 (r3 E + r4 L2),  L2 = A E + E A,
+    # which must be the Frechet derivative of p(A) = sum_k r_k A^k: the upper right
+    # block of p([[A, E], [0, A]]) (exact for polynomials); and L(A^T, E^T) = L(A, E)^T,
+    # which lets the adjoint run on transposed tiles
+    rng = np.random.default_rng(7)
+    n = 6
+    r = [1.0, 1.0, 0.5, 1 / 6, 1 / 24]
+    A = 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    E = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+
+    def poly(X):
+        out, P = r[0] * np.eye(len(X)), np.eye(len(X))
+        for k in range(1, 5):
+            P = P @ X
+            out = out + r[k] * P
+        return out
+
+    def factored(A, E):
+        A2, L2 = A @ A, A @ E + E @ A
+        return r[1] * E + r[2] * L2 + L2 @ (r[3] * A + r[4] * A2) + A2 @ (r[3] * E + r[4] * L2)
+
+    big = np.block([[A, E], [np.zeros((n, n)), A]])
+    ref = poly(big)[:n, n:]
+    assert np.abs(factored(A, E) - ref).max() < 1e-12 * np.abs(ref).max()
+    assert np.abs(factored(A.T, E.T) - ref.T).max() < 1e-12 * np.abs(ref).max()
+    # a dropped term fails it
+    A2, L2 = A @ A, A @ E + E @ A
+    bad = r[1] * E + r[2] * L2 + L2 @ (r[3] * A + r[4] * A2) + A2 @ (r[4] * L2)
+    assert np.abs(bad - ref).max() > 1e-3 * np.abs(ref).max()
