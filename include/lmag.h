@@ -165,10 +165,12 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
 /* Autotuner of the persistent slice kernels: times lmag_fidelity_and_grad on
  * this batch (reps timed calls after one warm-up, HIP events on the stream) for
  * every candidate chunk length (slices per work unit) and the inverse variants
- * of the Pade denominator (0: per slice the cheapest whose error bound holds --
- * truncated power series of 1/q_3 (single precision), MFMA binary-Neumann
- * product, else Gauss-Jordan; 1: Gauss-Jordan always; 2: Neumann where its
- * bound allows, else Gauss-Jordan). The fastest pair is kept
+ * of the Pade step (0: per slice the cheapest whose error bound holds -- in
+ * single precision r_2 itself by its power series truncated at degree 4
+ * (Pade-2) or 1/q_3 by its truncated power series (Pade-3), else the MFMA
+ * binary-Neumann product, else Gauss-Jordan; 1: Gauss-Jordan always; 2: Neumann
+ * where its bound allows, else Gauss-Jordan; 1 and 2 always form
+ * r_m = q_m^{-1} p_m). The fastest pair is kept
  * for calls with chunk_slices = 0 whose precision, order, d and total slice
  * count (power-of-two bucket) match, and appended as one JSON line to the file
  * named by the environment variable LMAG_TUNE_CACHE if it is set.
