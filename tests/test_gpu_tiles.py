@@ -49,7 +49,7 @@ def test_tile_inverse(ctx_system, prec):
 
 
 @pytest.mark.parametrize("prec,norm,m,s", [
-    ("f32", 0.05, 2, 0), ("f32", 0.4, 3, 0), ("f32", 3.0, 3, 3),
+    ("f32", 0.05, 2, 0), ("f32", 0.08, 2, 0), ("f32", 0.4, 3, 0), ("f32", 3.0, 3, 3),
     ("f64", 0.01, 3, 0), ("f64", 0.2, 5, 0), ("f64", 0.9, 7, 0), ("f64", 6.0, 7, 3)])
 def test_tile_expm(ctx_system, prec, norm, m, s):
     rng = np.random.default_rng(3)
