@@ -832,9 +832,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_scale(Lq, (T)r[3]);
     rt_axpy(Lq, (T)r[4], L2);
     ck.mark(5);
-    mm(K, slot<T, 2>(sh, gs), Bq);
+    // both unpipelined: measured faster here
+    mm<T, false>(K, slot<T, 2>(sh, gs), Bq);
     ck.mark(6);
-    mm(K, slot<T, 3>(sh, gs), Lq);
+    mm<T, false>(K, slot<T, 3>(sh, gs), Lq);
   } else {
   RT<T> W, LW, LV;
   const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
