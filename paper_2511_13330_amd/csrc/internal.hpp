@@ -54,7 +54,10 @@ struct Item {
   int32_t src;         // index of the item in the caller's batch
 };
 
-// Per-slice workspace tiles (row-major 64x64 complex of the compute type).
+// Per-slice workspace tiles (row-major 64x64 complex of the compute type):
+// D = r_m(A) - I before the squarings, the chunk's running product before the
+// slice, Q^{-1} - I (not written where single precision evaluates r_2 by its
+// series), and A^2.
 enum { WS_S = 0, WS_PLOC = 1, WS_QINV = 2, WS_A2 = 3, WS_TILES = 4 };
 
 struct SliceArgs {
