@@ -621,33 +621,33 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
 }
 
 // The chunk's running product P_loc, kept beyond the compute precision: in FP32
-// as an unevaluated sum hi + lo of two register tiles (double-float, about 48
-// bits), where hi is also the FP32 operand the MFMA needs; in FP64 as one tile.
-// With the slice in the form I + D the step is P <- P + D hi, so the O(1) part
-// of P is never rounded to the compute precision along the chain.
+// as an FP64 register tile (dre, dim) together with hi, its rounding to FP32,
+// which is the operand the MFMA needs; in FP64 as one tile (hi). With the slice
+// in the form I + D the step is P <- P + D hi, so the O(1) part of P is never
+// rounded to the compute precision along the chain. (A double-float pair of
+// FP32 tiles does the same in fewer registers but needs about five times the
+// VALU work per step; measured 1.8 % slower on the forward.)
 template <typename T> struct RunProd {
-  RT<T> hi, lo;
+  RT<T> hi;
+  double dre[4][4], dim[4][4];   // single precision only
 };
 
 template <typename T>
 __device__ __forceinline__ void rp_identity(RunProd<T>& P) {
   rt_identity(P.hi);
-  rt_zero(P.lo);
+  if constexpr (sizeof(T) == 4) {
+    const Lane L;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        P.dre[q][r] = (L.template row<T>(q, r) == L.col) ? 1.0 : 0.0;
+        P.dim[q][r] = 0.0;
+      }
+  }
 }
 
-// (h, l) <- renormalised (h + l + x): Knuth's two-sum of h and x, its error
-// folded into l, then a fast two-sum so that h is the rounding of the total
-__device__ __forceinline__ void df_add(float& h, float& l, float x) {
-  const float s = h + x;
-  const float bb = s - h;
-  const float e = (h - (s - bb)) + (x - bb);
-  const float lo = l + e;
-  const float hn = s + lo;
-  l = lo - (hn - s);
-  h = hn;
-}
-
-// hi + lo += X (float: double-float addition; double: hi += X)
+// P += X (float: accumulated in FP64, hi re-rounded; double: hi += X)
 template <typename T>
 __device__ __forceinline__ void rp_add(RunProd<T>& P, const RT<T>& X) {
 #pragma unroll
@@ -655,15 +655,10 @@ __device__ __forceinline__ void rp_add(RunProd<T>& P, const RT<T>& X) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if constexpr (sizeof(T) == 4) {
-        float h = P.hi.re[q][r], l = P.lo.re[q][r];
-        df_add(h, l, X.re[q][r]);
-        P.hi.re[q][r] = h;
-        P.lo.re[q][r] = l;
-        h = P.hi.im[q][r];
-        l = P.lo.im[q][r];
-        df_add(h, l, X.im[q][r]);
-        P.hi.im[q][r] = h;
-        P.lo.im[q][r] = l;
+        P.dre[q][r] += (double)X.re[q][r];
+        P.dim[q][r] += (double)X.im[q][r];
+        P.hi.re[q][r] = (float)P.dre[q][r];
+        P.hi.im[q][r] = (float)P.dim[q][r];
       } else {
         P.hi.re[q][r] += X.re[q][r];
         P.hi.im[q][r] += X.im[q][r];
@@ -688,8 +683,8 @@ __device__ __forceinline__ void chain_step(RunProd<T>& P, const cpx<T>* Dm, cons
   rp_add(P, Pn);
 }
 
-// stores P - I (the form of chunk totals): (hi - I) is exact near the identity
-// (Sterbenz), then lo is added
+// stores P - I (the form of chunk totals), rounded once from the FP64 tile in
+// single precision
 template <typename T>
 __device__ __forceinline__ void rp_store_delta(const RunProd<T>& P, cpx<T>* M) {
   const Lane L;
@@ -699,8 +694,13 @@ __device__ __forceinline__ void rp_store_delta(const RunProd<T>& P, cpx<T>* M) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const T d = (L.template row<T>(q, r) == L.col) ? T(1) : T(0);
-      X.re[q][r] = (P.hi.re[q][r] - d) + P.lo.re[q][r];
-      X.im[q][r] = P.hi.im[q][r] + P.lo.im[q][r];
+      if constexpr (sizeof(T) == 4) {
+        X.re[q][r] = (T)(P.dre[q][r] - (double)d);
+        X.im[q][r] = (T)P.dim[q][r];
+      } else {
+        X.re[q][r] = P.hi.re[q][r] - d;
+        X.im[q][r] = P.hi.im[q][r];
+      }
     }
   rt_store<T, false>(X, M, 64);
 }
