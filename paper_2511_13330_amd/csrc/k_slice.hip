@@ -480,11 +480,12 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   __syncthreads();
   RT<T> A2;
   rt_zero(A2);
+  // unpipelined: measured faster, and it leaves the kernel without spills
   if constexpr (st && hk) {
-    mm(A2, slot<T, 0>(sh, gs), A, TileStore<T>{Pl, ws + WS_PLOC * TILE});
+    mm<T, false>(A2, slot<T, 0>(sh, gs), A, TileStore<T>{Pl, ws + WS_PLOC * TILE});
   } else {
     if constexpr (st) rt_store<T, false>(Pl, ws + WS_PLOC * TILE, 64);
-    mm(A2, slot<T, 0>(sh, gs), A);
+    mm<T, false>(A2, slot<T, 0>(sh, gs), A);
   }
   ck.mark(1);
   // single precision stores A^2 during the next product
