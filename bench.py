@@ -188,8 +188,10 @@ def robust_sweep(args):
     ns = np.repeat(ns_c, S)
     off = np.repeat(off_c, S)
     groups = np.repeat(np.arange(n_cand), S)
-    static = np.tile(np.asarray(cfg["B"])[None, :] + cfg["dB"], (n_cand, 1))
-    scale = np.tile(cfg["eps"], (n_cand, 1))
+    # per-item fields resident on the device, like the amplitudes
+    static = torch.as_tensor(np.tile(np.asarray(cfg["B"])[None, :] + cfg["dB"], (n_cand, 1)),
+                             dtype=torch.float64, device="cuda")
+    scale = torch.as_tensor(np.tile(cfg["eps"], (n_cand, 1)), dtype=torch.float64, device="cuda")
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     kw = dict(slice_offset=off, static_coef=static, ctrl_scale=scale, groups=groups)
     F, g = sysm.fidelity_and_grad(a, ns, cfg["dt"], cfg["U_target"], **kw)   # warm-up
@@ -334,8 +336,12 @@ def main():
     amps = torch.tensor(cfg["amps_batch"].reshape(B * 4096, 2), dtype=torch.float32,
                         device=dev).contiguous()
     n_slices = np.full(B, 4096, dtype=np.int32)
-    static = np.tile(np.asarray(cfg["B"])[None, :], (B, 1))
-    UT = cfg["U_target"]
+    # the target and the static fields are resident like the amplitudes: a copy
+    # from pageable host memory inside the step would wait for the previous
+    # step's kernels and leave the device idle while the next step is launched
+    static = torch.as_tensor(np.tile(np.asarray(cfg["B"])[None, :], (B, 1)),
+                             dtype=torch.float64, device=dev)
+    UT = torch.as_tensor(cfg["U_target"], dtype=torch.complex128, device=dev)
 
     def step(a=amps, ns=n_slices, st=static):
         return sysm.fidelity_and_grad(a, ns, cfg["dt"], UT, static_coef=st)
