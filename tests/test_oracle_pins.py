@@ -374,3 +374,63 @@ def test_mlp_backward_matches_finite_differences():
         pm = list(params); pm[li] = (W, bm)
         fd = (loss(pp) - loss(pm)) / (2 * h)
         assert abs(fd - grads[li][1][0]) < 1e-7 * max(1.0, abs(fd)) + 1e-10
+
+
+# -------------------------------------------- control-scale (quasi-static J) pins
+def test_exchange_with_control_scale_is_swap_power():
+    # H = eps J S1.S2: the exchange angle is eps J t, so eps J t = pi gives SWAP
+    # up to a phase and eps J t = pi / 2 gives sqrt(SWAP)
+    SWAP = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
+                    dtype=complex)
+    eps = 0.37
+    sysm = System(2, [0.0, 0.0], eps=[eps])
+    J = 2 * np.pi * 5.0
+    for phi in (np.pi, np.pi / 2):
+        N = 8
+        t = phi / (eps * J)
+        S = propagate(sysm.omegas(np.full((N, 1), J), t / N, 1, "zoh"))
+        U = np.exp(1j * phi / 4) * (np.cos(phi / 2) * np.eye(4) - 1j * np.sin(phi / 2) * SWAP)
+        assert np.allclose(S, np.kron(U.conj(), U), atol=1e-12)
+    S = propagate(sysm.omegas(np.full((4, 1), J), np.pi / (eps * J) / 4, 1, "zoh"))
+    assert abs(fidelity(S, SWAP)[0] - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("order,hold", [(2, "foh"), (1, "zoh")])
+def test_gradient_with_control_scale_and_field_offset_matches_fd(order, hold):
+    # every coordinate, with eps != 1 and a field offset dB != 0
+    cfg = synth.small_case(19, n_slices=6, dt=5e-4)
+    eps = np.array([1.013, 0.981])
+    dB = np.array([0.8, -1.7, 2.3])
+    sysm = System.from_cfg(cfg, eps=eps, dB=dB)
+    amps = cfg["amps"]
+    F, g = oracle.grad_adjoint(sysm, amps, cfg["dt"], order, hold, cfg["U_target"])
+    fd = oracle.grad_fd(sysm, amps, cfg["dt"], order, hold, cfg["U_target"],
+                        np.arange(amps.size))
+    assert np.linalg.norm(g.reshape(-1) - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_control_scale_equals_scaled_amplitudes():
+    # eps_c enters H only as eps_c u_c: F(u; eps) = F(eps u; 1), and by the
+    # chain rule dF/du(u; eps) = eps * dF/du(eps u; 1)
+    cfg = synth.small_case(20, n_slices=5)
+    eps = np.array([0.7, 1.4])
+    s_eps = System.from_cfg(cfg, eps=eps)
+    s_one = System.from_cfg(cfg)
+    F1, g1 = oracle.grad_adjoint(s_eps, cfg["amps"], cfg["dt"], 2, "foh", cfg["U_target"])
+    F2, g2 = oracle.grad_adjoint(s_one, cfg["amps"] * eps[None, :], cfg["dt"], 2, "foh",
+                                 cfg["U_target"])
+    assert abs(F1 - F2) < 1e-13
+    assert np.allclose(g1, g2 * eps[None, :], rtol=1e-10, atol=1e-14)
+
+
+def test_mse_loss_hand_computed():
+    # sigmoid(0) = 1/2, sigmoid(+-ln 3) = 3/4, 1/4
+    from oracle.mlp import mse_loss
+    z = np.array([[0.0, np.log(3.0)], [-np.log(3.0), 0.0]])
+    y = np.array([[0.0, 1.0], [0.0, 1.0]])
+    loss, dz = mse_loss(z, y)
+    # differences 1/2, -1/4, 1/4, -1/2: mean of squares = (1/4 + 1/16 + 1/16 + 1/4) / 4
+    assert abs(loss - 0.15625) < 1e-15
+    # d/dz mean = 2 diff p (1 - p) / 4
+    want = np.array([[0.0625, -0.0234375], [0.0234375, -0.0625]])
+    assert np.allclose(dz, want, rtol=1e-14, atol=0)
