@@ -32,14 +32,24 @@
  *    output has been written (argument errors are detected on the host before
  *    any launch).
  *  - Compute calls are asynchronous on the caller's HIP stream (hipStream_t
- *    passed as void*, NULL = default stream). Errors raised by the device
- *    surface on a later call or on lmag_sync().
+ *    passed as void*, NULL = default stream), with one exception: on the
+ *    block-tiled path (n > 64) the call blocks the host once per call, after
+ *    the slice exponents, to read the largest scaling exponent and Neumann
+ *    level count that size its squaring and inverse loops. Errors raised by
+ *    the device surface on a later call or on lmag_sync().
+ *  - A context may be used from several streams: every compute call shares
+ *    the context's workspace, so a call on a stream other than the previous
+ *    call's first waits, on the device (hipStreamWaitEvent, the host does not
+ *    block), for the previous call to finish.
  *  - Reductions are deterministic (no floating-point atomics): repeated calls
  *    on the same inputs give bitwise-identical results.
  *  - The library owns only its workspace, which lmag_destroy() frees. The
  *    caller owns every pointer it passes in.
- *  - Supported superoperator size: n = d^2 <= 64 (d = 2, 4 or 8). Smaller
- *    systems are embedded in 64 x 64 tiles with zero padding.
+ *  - Supported superoperator sizes: n = d^2 <= 64 (d = 2, 4 or 8; smaller
+ *    systems are embedded in 64 x 64 tiles with zero padding), FP32 or FP64;
+ *    and n a multiple of 64 up to 4096 (d = 16, 32 or 64), FP32 only, on the
+ *    block-tiled path.
+ *  - Test and instrumentation entry points are declared in lmag_debug.h.
  */
 #ifndef LMAG_H
 #define LMAG_H
@@ -83,7 +93,8 @@ const char *lmag_last_error(const lmag_ctx *ctx);
 /* System description (Sec. II-B, Eq. 6 and 8). All pointers are HOST pointers;
  * the arrays are copied before the call returns and the caller keeps them. */
 typedef struct {
-  int d;                        /* Hilbert dimension, d*d <= 64                        */
+  int d;                        /* Hilbert dimension: d*d <= 64, or d*d a multiple of  */
+                                /* 64 up to 4096 (FP32 only)                          */
   int n_static;                 /* number of static Hamiltonian terms               */
   const double *H_static;       /* [n_static][d][d] complex (e.g. sigma_z_i / 2)     */
   int n_ctrl;                   /* number of control terms, <= 8                     */
@@ -94,7 +105,11 @@ typedef struct {
   int magnus_order;             /* 1 (Eq. 13) or 2 (adds the Gauss-Legendre term)    */
   int hold;                     /* LMAG_ZOH (u constant per slice) or LMAG_FOH        */
                                 /* (u linear from u_n to u_{n+1}; u_N := u_{N-1})   */
-  size_t workspace_bytes_max;   /* 0 = no limit beyond device memory                 */
+  size_t workspace_bytes_max;   /* 0 = 85 % of free device memory. Gradient calls    */
+                                /* over it split into waves and, where one item (or  */
+                                /* group) alone exceeds it, re-run each chunk's      */
+                                /* forward in the adjoint instead of storing the     */
+                                /* per-slice tiles (the suffix side is recomputed)   */
   int chunk_slices;             /* slices per work unit; 0 = automatic: the autotuned */
                                 /* length if one is cached for this call's size, else */
                                 /* one chunk per compute unit up to 64 slices per unit,*/
@@ -122,17 +137,30 @@ typedef struct {
                                    must share slice_offset and n_slices              */
 } lmag_batch;
 
-/* S_out: DEVICE [n_items][n][n] complex of the compute type: U of every item. */
+/* The propagator of every item (Eq. 13-15): per slice the Magnus exponent
+ * Omega_n (Eq. 13, plus the Gauss-Legendre commutator term at second order),
+ * S_n = exp(Omega_n) by scale-and-square Pade (Eq. 14), and the ordered product
+ * U = S_N ... S_1, later slices on the left (Eq. 15).
+ * S_out: DEVICE [n_items][n][n] complex of the compute type: U of every item.
+ * Items may share amplitude rows. */
 lmag_status lmag_propagate(lmag_ctx *ctx, const lmag_batch *batch, void *S_out,
                            void *hip_stream);
 
-/* Fidelity and (optionally) its gradient.
+/* Score and gradient for the pulse optimiser (Sec. III-C: the coefficient
+ * matrix of slices x controls and a target unitary in, a score and its
+ * gradient out): the process fidelity F = Re Tr(S_T^dag U) / d^2 against
+ * S_T = conj(U_T) (x) U_T, with U as in lmag_propagate, and dF/du from the
+ * hand-written adjoint (Frechet derivative of every slice exponential with the
+ * prefix and suffix products of Eq. 15).
  * U_target:       DEVICE [n_targets][d][d] complex128
  * target_of_item: HOST [n_items] in [0, n_targets) or NULL (= target 0)
  * F_out:          DEVICE double [n_items] (or [n_groups] when grouped)
  * grad_out:       DEVICE like amps (compute type) or NULL for F only. With
  *                 groups, the group mean of dF/du is written at the rows of the
- *                 group's shared amplitudes. */
+ *                 group's shared amplitudes. Rows that belong to no item are
+ *                 left unchanged. With grad_out, the row ranges of different
+ *                 items (of different groups, when grouped) must not overlap
+ *                 (LMAG_E_INVALID): items that share a pulse go into one group. */
 lmag_status lmag_fidelity_and_grad(lmag_ctx *ctx, const lmag_batch *batch,
                                    const void *U_target, int n_targets,
                                    const int32_t *target_of_item, double *F_out,
@@ -268,23 +296,6 @@ lmag_status lmag_read_profile(lmag_ctx *ctx, double *ms_out /*[LMAG_STAGES]*/,
  * dense and the dense Omega and trace kernels are used; also 0 for systems
  * larger than one tile). */
 lmag_status lmag_last_plan(lmag_ctx *ctx, int64_t *out /*[8]*/);
-
-/* Instrumentation: per-phase shader-clock cycles of workgroup 0 of the slice
- * kernels, summed over the calls made while enabled. enable = 1 clears and
- * starts recording, 0 stops, -1 leaves the state; out (if not NULL) receives
- * 32 counters (0-6 forward phases, 16-25 backward phases). Blocks. */
-lmag_status lmag_debug_phase_cycles(lmag_ctx *ctx, int enable, int64_t *out /*[32]*/);
-
-/* Unit-test kernels on single 64 x 64 complex tiles of the given precision,
- * DEVICE pointers, row-major. C = op(A) B (op = transpose when transA != 0);
- * C = A^{-1} (no pivoting; A must be column diagonally dominant);
- * C = exp(A) by the library's scaled Pade path, ms_out[0..1] = (m, s). */
-lmag_status lmag_debug_tile_gemm(lmag_ctx *ctx, int precision, const void *A, const void *B,
-                                 void *C, int transA, void *hip_stream);
-lmag_status lmag_debug_tile_inverse(lmag_ctx *ctx, int precision, const void *A, void *C,
-                                    void *hip_stream);
-lmag_status lmag_debug_tile_expm(lmag_ctx *ctx, int precision, const void *A, void *C,
-                                 int8_t *ms_out, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -48,7 +48,7 @@ class Batch(ctypes.Structure):
                 ("dt", c_double), ("n_groups", c_int), ("group_of_item", c_int32_p)]
 
 
-# name -> (restype, argtypes); every symbol include/lmag.h declares
+# name -> (restype, argtypes); every symbol include/lmag.h and include/lmag_debug.h declare
 SIGNATURES = {
     "lmag_version": (ctypes.c_char_p, []),
     "lmag_create": (c_int, [ctypes.POINTER(c_void_p), c_int]),

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/lmag.h: context, validation,
 // system set-up, work planning, workspace and kernel sequencing.
 #include "../../include/lmag.h"
+#include "../../include/lmag_debug.h"
 #include "internal.hpp"
 #include "tile.hpp"
 #include "pade.hpp"
@@ -78,6 +79,10 @@ struct lmag_ctx {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   hipStream_t last_stream = nullptr;
+  // completion of the last compute call: a call on another stream waits for it
+  // on the device, since every call shares the workspace
+  hipEvent_t call_done = nullptr;
+  bool call_pending = false;
   int8_t* last_ms = nullptr;
   int last_total_slices = 0;
   void* dbg_scratch = nullptr;
@@ -135,7 +140,7 @@ struct Layout {
 
 // Checks every argument of a compute call on the host before anything runs.
 lmag_status validate_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
-                           int n_targets) {
+                           int n_targets, bool writes_grad) {
   if (!b) return c->fail(LMAG_E_INVALID, "batch is NULL");
   if (b->n_items < 1) return c->fail(LMAG_E_INVALID, "n_items must be >= 1");
   if (!b->n_slices || !b->slice_offset) return c->fail(LMAG_E_INVALID, "n_slices/slice_offset NULL");
@@ -165,6 +170,26 @@ lmag_status validate_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* targ
     }
     for (int gi = 0; gi < b->n_groups; ++gi)
       if (first[gi] < 0) return c->fail(LMAG_E_INVALID, "empty group");
+  }
+  if (writes_grad) {
+    // each gradient row belongs to one item (or one group): ranges of different
+    // units must not overlap, else two writers would race for the same rows
+    std::vector<std::pair<int64_t, int64_t>> r;
+    if (b->n_groups > 0) {
+      std::vector<int> first(b->n_groups, -1);
+      for (int i = 0; i < b->n_items; ++i)
+        if (first[b->group_of_item[i]] < 0) {
+          first[b->group_of_item[i]] = i;
+          r.push_back({b->slice_offset[i], b->slice_offset[i] + b->n_slices[i]});
+        }
+    } else {
+      for (int i = 0; i < b->n_items; ++i) r.push_back({b->slice_offset[i], b->slice_offset[i] + b->n_slices[i]});
+    }
+    std::sort(r.begin(), r.end());
+    for (size_t k = 1; k < r.size(); ++k)
+      if (r[k].first < r[k - 1].second)
+        return c->fail(LMAG_E_INVALID, "amplitude rows of two items (groups) overlap in a gradient call; "
+                                       "put items that share a pulse into one group");
   }
   return LMAG_OK;
 }
@@ -1026,11 +1051,34 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
 // Splits the batch into waves that fit the workspace budget (groups stay
 // whole). A wave whose stored per-slice tiles do not fit runs in recompute
 // mode; a unit that does not fit even then is LMAG_E_NOMEM.
+lmag_status run_waves_body(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+                           int n_targets, bool grad, bool fidelity, const void* U_target,
+                           double* F_out, void* grad_out, void* S_out, hipStream_t s);
+
+// Every compute call shares the context's workspace (plan, coefficients, tiles,
+// work counters). A call on a stream other than the previous call's first makes
+// its stream wait, on the device, for the previous call's completion event; the
+// host does not block. The event is recorded again at the end of the call.
 lmag_status run_waves(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
                       int n_targets, bool grad, bool fidelity, const void* U_target,
                       double* F_out, void* grad_out, void* S_out, hipStream_t s) {
-  lmag_status st = validate_batch(c, b, target_of_item, fidelity ? n_targets : 1);
+  lmag_status st = validate_batch(c, b, target_of_item, fidelity ? n_targets : 1, grad);
   if (st != LMAG_OK) return st;
+  if (c->call_pending && s != c->last_stream)
+    HIPCHK(hipStreamWaitEvent(s, c->call_done, 0), "hipStreamWaitEvent");
+  c->last_stream = s;
+  st = run_waves_body(c, b, target_of_item, n_targets, grad, fidelity, U_target, F_out, grad_out,
+                      S_out, s);
+  hipError_t e = hipEventRecord(c->call_done, s);
+  if (e != hipSuccess && st == LMAG_OK) return c->hip_fail(e, "hipEventRecord");
+  c->call_pending = true;
+  return st;
+}
+
+lmag_status run_waves_body(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
+                           int n_targets, bool grad, bool fidelity, const void* U_target,
+                           double* F_out, void* grad_out, void* S_out, hipStream_t s) {
+  lmag_status st = LMAG_OK;
   if (c->n > 64)
     return run_big(c, b, target_of_item, n_targets, grad, fidelity, U_target, F_out, grad_out, S_out, s);
   // units: whole groups (grouped calls) or single items, in order
@@ -1143,7 +1191,9 @@ lmag_status lmag_create(lmag_ctx** out, int hip_device) {
     if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess ||
         c->n_cu <= 0)
       c->n_cu = 256;
-    if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->call_done, hipEventDisableTiming) != hipSuccess) {
+      if (c->upload_done) (void)hipEventDestroy(c->upload_done);
       delete c;
       return LMAG_E_DEVICE;
     }
@@ -1176,6 +1226,7 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->mse_part) (void)hipFree(c->mse_part);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  if (c->call_done) (void)hipEventDestroy(c->call_done);
   for (auto& pe : c->ev_pending) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
@@ -1321,7 +1372,6 @@ lmag_status lmag_propagate(lmag_ctx* c, const lmag_batch* b, void* S_out, void* 
     if (b && b->n_groups) return c->fail(LMAG_E_INVALID, "groups apply to fidelity calls only");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    c->last_stream = s;
     return run_waves(c, b, nullptr, 0, false, false, nullptr, nullptr, nullptr, S_out, s);
   } catch (const std::bad_alloc&) {
     return c->fail(LMAG_E_NOMEM, "host allocation failed");
@@ -1340,7 +1390,6 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx* c, const lmag_batch* b, const void*
     if (!F_out) return c->fail(LMAG_E_INVALID, "F_out is NULL");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    c->last_stream = s;
     return run_waves(c, b, target_of_item, n_targets, grad_out != nullptr, true, U_target, F_out,
                      grad_out, nullptr, s);
   } catch (const std::bad_alloc&) {
@@ -1381,7 +1430,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
     if (!U_target || n_targets < 1) return c->fail(LMAG_E_INVALID, "U_target NULL or n_targets < 1");
     if (reps < 1) return c->fail(LMAG_E_INVALID, "reps must be >= 1");
-    lmag_status st = validate_batch(c, b, target_of_item, n_targets);
+    lmag_status st = validate_batch(c, b, target_of_item, n_targets, true);
     if (st != LMAG_OK) return st;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1577,7 +1626,6 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx* c, const lmag_batch* b, int ki
     if (!finite_array(P, (size_t)c->n * L * 2)) return c->fail(LMAG_E_INVALID, "non-finite P");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    c->last_stream = s;
     if (!c->logP_dev) {
       hipError_t e = hipMalloc((void**)&c->logP_dev, (size_t)64 * MAX_LOGICAL * 16);
       if (e != hipSuccess) { c->logP_dev = nullptr; return c->hip_fail(e, "hipMalloc(P)"); }

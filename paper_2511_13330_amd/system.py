@@ -125,7 +125,7 @@ class System:
             keep.append(toi)
             tp = toi.ctypes.data_as(_lib.c_int32_p)
         F = torch.empty(ng if ng else n_items, dtype=torch.float64, device=self.device)
-        grad = torch.empty_like(amps) if want_grad else None
+        grad = torch.zeros_like(amps) if want_grad else None
         check(lib().lmag_fidelity_and_grad(
             self._ctx, ctypes.byref(b), ctypes.c_void_p(UT.data_ptr()), UT.shape[0], tp,
             ctypes.c_void_p(F.data_ptr()),
@@ -157,7 +157,7 @@ class System:
             tp = toi.ctypes.data_as(_lib.c_int32_p)
         kinds = {"projected": _lib.LMAG_SCORE_PROJECTED, "linear": _lib.LMAG_SCORE_LINEAR}
         S = torch.empty(ng if ng else n_items, dtype=torch.float64, device=self.device)
-        grad = torch.empty_like(amps) if want_grad else None
+        grad = torch.zeros_like(amps) if want_grad else None
         check(lib().lmag_logical_score_and_grad(
             self._ctx, ctypes.byref(b), kinds[kind], L,
             Ph.ctypes.data_as(_lib.c_double_p), ctypes.c_void_p(Td.data_ptr()), Td.shape[0], tp,
@@ -306,6 +306,7 @@ class PulseFidelity(torch.autograd.Function):
     def backward(ctx, gF):
         (grad,) = ctx.saved_tensors
         idx = ctx.row_of.clamp(min=0)
-        scale = torch.where(ctx.row_of >= 0, gF[idx].to(grad.dtype),
-                            torch.zeros((), dtype=grad.dtype, device=grad.device))
-        return grad * scale[:, None], None, None, None, None, None
+        covered = (ctx.row_of >= 0)[:, None]
+        g = torch.where(covered, grad * gF[idx].to(grad.dtype)[:, None],
+                        torch.zeros((), dtype=grad.dtype, device=grad.device))
+        return g, None, None, None, None, None

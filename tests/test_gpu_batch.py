@@ -142,3 +142,68 @@ def test_benchmark_batch_plan_and_consistency():
                                         cfg["U_target"], static_coef=st[:1])
         assert abs(F[i] - Fi.cpu().numpy()[0]) <= 1e-6
         assert rel(g[i], gi.cpu().numpy().astype(np.float64)) <= 1e-4
+
+
+def test_two_streams_different_inputs_back_to_back():
+    """Two calls with different inputs on two streams, issued back to back with
+    no host synchronisation: they share the context's workspace, so the second
+    waits on the device for the first; each equals the same call made alone."""
+    cfg_a = synth.small_case(35, n_slices=4096)
+    cfg_b = synth.small_case(36, n_slices=300)
+    sysm = lib_system(cfg_a, chunk=16)
+    runs = []
+    for cfg in (cfg_a, cfg_b):
+        a = torch.tensor(rounded(cfg["amps"], "f32"), dtype=torch.float32, device="cuda")
+        runs.append((a, [cfg["n_slices"]], cfg["dt"], cfg["U_target"],
+                     np.asarray(cfg["B"])[None, :]))
+    ref = [sysm.fidelity_and_grad(a, n, dt, U, static_coef=b) for a, n, dt, U, b in runs]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for s in (s1, s2):
+        s.wait_stream(torch.cuda.current_stream())
+    out = []
+    for s, (a, n, dt, U, b) in zip((s1, s2), runs):
+        with torch.cuda.stream(s):
+            out.append(sysm.fidelity_and_grad(a, n, dt, U, static_coef=b, stream=s))
+    torch.cuda.synchronize()
+    for (F, g), (Fr, gr) in zip(out, ref):
+        assert torch.equal(F, Fr) and torch.equal(g, gr)
+
+
+def test_overlapping_items_rejected_only_with_gradient():
+    from paper_2511_13330_amd import LmagError
+    cfg = synth.small_case(37, n_slices=16)
+    sysm = lib_system(cfg, chunk=4)
+    a = torch.tensor(rounded(cfg["amps"], "f32"), dtype=torch.float32, device="cuda")
+    b = np.tile(np.asarray(cfg["B"])[None, :], (2, 1))
+    with pytest.raises(LmagError, match="INVALID"):
+        sysm.fidelity_and_grad(a, [10, 10], cfg["dt"], cfg["U_target"], slice_offset=[0, 5],
+                               static_coef=b)
+    F, _ = sysm.fidelity_and_grad(a, [10, 10], cfg["dt"], cfg["U_target"], slice_offset=[0, 5],
+                                  static_coef=b, want_grad=False)
+    for i, o in enumerate((0, 5)):
+        Fi, _ = sysm.fidelity_and_grad(a[o:o + 10].contiguous(), [10], cfg["dt"], cfg["U_target"],
+                                       static_coef=b[:1], want_grad=False)
+        assert F[i].item() == Fi.item()
+
+
+def test_rows_outside_items_get_zero_gradient():
+    """Rows of amps that no item reads (here NaN) get a zero gradient from the
+    binding and from the autograd backward."""
+    from paper_2511_13330_amd import PulseFidelity
+    cfg = synth.small_case(38, n_slices=20)
+    sysm = lib_system(cfg, chunk=4)
+    a = rounded(cfg["amps"], "f32").copy()
+    a[[0, 1, 10, 11, 18, 19]] = np.nan
+    amps = torch.tensor(a, dtype=torch.float32, device="cuda", requires_grad=True)
+    b = np.tile(np.asarray(cfg["B"])[None, :], (2, 1))
+    opts = {"slice_offset": [2, 12], "static_coef": b}
+    F, g = sysm.fidelity_and_grad(amps.detach(), [8, 6], cfg["dt"], cfg["U_target"], **opts)
+    assert torch.isfinite(F).all()
+    outside = [0, 1, 10, 11, 18, 19]
+    assert torch.count_nonzero(g[outside]) == 0
+    F2 = PulseFidelity.apply(amps, sysm, [8, 6], cfg["dt"], cfg["U_target"], opts)
+    (1.0 - F2).sum().backward()
+    assert torch.isfinite(amps.grad).all()
+    assert torch.count_nonzero(amps.grad[outside]) == 0
+    assert torch.equal(amps.grad[2:10], -g[2:10])

@@ -108,3 +108,35 @@ def test_training_reduces_loss():
     hist = net.train(torch.tensor(X, device="cuda"), torch.tensor(Y, dtype=torch.float32, device="cuda"),
                      epochs=15, batch=128, lr=3e-3)
     assert hist[-1] < 0.3 * hist[0]
+
+
+def test_full_size_network_forward_backward():
+    """The proposal network at its real shapes, 133 -> 512 -> 512 -> 512 -> 512,
+    on 300 rows (several row tiles and a ragged tail): every layer's
+    pre-activation, the head and all weight and bias gradients against the
+    oracle fed the same bfloat16 operands."""
+    from paper_2511_13330_amd import spin_chain_system
+    from paper_2511_13330_amd.mlp import ProposalMLP
+    s = spin_chain_system(3, precision="f32", magnus_order=1, hold="zoh")
+    amax = 2 * np.pi * 20
+    big = ProposalMLP(s, n_in=133, width=512, n_out=512, depth=4, amax=amax, seed=7)
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((300, 133)).astype(np.float32)
+    Yt = rng.uniform(0, 1, (300, 512)).astype(np.float32)
+    X16 = big.to_bf16(torch.tensor(X, device="cuda"))
+    Y, (acts, pres) = big.forward(X16, keep=True)
+    P = oracle_params(big)
+    for li, (W, b) in enumerate(P):
+        xin = acts[li].float().cpu().numpy().astype(np.float64)
+        z = xin @ om.bf16_round(W).T + b
+        assert np.allclose(pres[li].cpu().numpy(), z, rtol=1e-4, atol=1e-4), li
+    zo = pres[-1].cpu().numpy().astype(np.float64)
+    assert np.allclose(Y.cpu().numpy(), amax * om.sigmoid(zo), rtol=1e-5, atol=1e-5)
+    loss, grads = big.loss_and_grads(X16, torch.tensor(Yt, device="cuda"))
+    pre, acts_o = om.forward(P, X16.float().cpu().numpy().astype(np.float64), round_bf16=True)
+    lo, dz = om.mse_loss(pre[-1], Yt.astype(np.float64))
+    g_or = om.backward(P, pre, acts_o, dz, round_bf16=True)
+    assert abs(loss.item() - lo) < 1e-3 * lo
+    for (dW, db), (oW, ob) in zip(grads, g_or):
+        assert np.linalg.norm(dW.cpu().numpy() - oW) < 2e-2 * np.linalg.norm(oW)
+        assert np.linalg.norm(db.cpu().numpy() - ob) < 2e-2 * np.linalg.norm(ob)

@@ -196,3 +196,40 @@ def test_config1_high_fidelity_closed_system():
     ours = np.array([g2[int(c) // 2, int(c) % 2] for c in coords])
     adj = np.array([g_at[int(c) // 2][int(c) % 2] for c in coords])
     assert rel(ours, adj) <= 1e-3
+
+
+# ------------------------------------------- scale-and-square path (s > 0)
+@pytest.mark.parametrize("prec,dt,m_min,tol_F,tol_g", [
+    ("f32", 1e-2, 3, 1e-7, 1e-4), ("f64", 2e-2, 7, 1e-12, 1e-9)])
+def test_forced_squarings_forward_and_adjoint(prec, dt, m_min, tol_F, tol_g):
+    """Slices long enough that ||Omega||_1 exceeds the largest Pade degree's
+    theta (FP32: theta_3, FP64: theta_7), so every slice is scaled by 2^-s with
+    s > 0 and squared back: the forward squarings D <- 2D + D^2 and the
+    adjoint's squaring recurrence run in the 64 x 64 pipeline."""
+    cfg = synth.small_case(300, n_slices=26, dt=dt)
+    sysm = lib_system(cfg, prec, 2, "foh", chunk=6)
+    amps = rounded(cfg["amps"], prec)
+    osys = oracle_system(cfg)
+    oms = osys.omegas(amps, dt, 2, "foh")
+    theta = float(np.max([np.abs(o).sum(axis=0).max() for o in oms]))
+    assert min(np.abs(o).sum(axis=0).max() for o in oms) > (0.43 if prec == "f32" else 0.96)
+    U_ref = oracle.propagate(oms)
+    U = sysm.propagate(to_dev(amps, sysm), [26], dt,
+                       static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    hist = sysm.selection_histogram()
+    row = {3: 1, 7: 3}[m_min]
+    assert hist[row, 1:].sum() == 26 and hist[:, 0].sum() == 0, (theta, hist[:, :8])
+    assert rel(U, U_ref) < (2e-6 if prec == "f32" else 1e-12)
+    F_ref, g_ref = oracle.grad_adjoint(osys, amps, dt, 2, "foh", cfg["U_target"])
+    F, g = lib_fid(sysm, cfg, amps)
+    assert abs(F[0] - F_ref) <= tol_F
+    assert rel(g, g_ref) <= tol_g
+
+
+def test_config1_gradient_all_coordinates(config1_run):
+    """The whole 2 x 4096 gradient against the oracle's exact adjoint, norm-wise."""
+    cfg, amps, F, g, U, sysm = config1_run
+    osys = oracle_system(cfg)
+    F_ref, g_ref = oracle.grad_adjoint(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    assert abs(F[0] - F_ref) <= 1e-6
+    assert rel(g, g_ref) <= 1e-3
