@@ -17,7 +17,10 @@ in plain numpy float64 / complex128, in the order the paper states it:
   finite differences, and an RK4 integrator of Eq. 9;
 * logical-subspace scores (Eq. 16-17) and the adjoint for any score of U;
 * RK4 evolution of a state and the Uhlmann fidelity (the accuracy study);
-* MLP and Adam references for the learned proposal and the optimiser.
+* MLP and Adam references for the learned proposal and the optimiser;
+* the closed-system reduction to Hilbert space (conj(V) (x) V) and the action
+  of slice exponentials on a few columns, for superoperators too large for
+  the dense path.
 """
 from .model import (pauli, spin_op, exchange_terms, zeeman_terms, jump_ops,
                     hamiltonian)
@@ -28,6 +31,7 @@ from .optim import adam_project
 from . import mlp
 from . import logical
 from . import states
+from . import hilbert
 from .propagator import (System, propagate, superop_of_unitary, fidelity,
                          grad_adjoint, grad_adjoint_at, grad_adjoint_seed, grad_adjoint_seed_at, grad_fd, grad_fd_cached, rk4_propagator,
                          slice_products)

@@ -51,6 +51,10 @@ class System:
     def liouv(self, u):
         return liouvillian(self.H(u), self.Ls)
 
+    def ctrl_generator(self, c):
+        """d L / d (eps_c u_c): the lifted control term of Eq. 8."""
+        return lift_hamiltonian(self.Hc[c])
+
     def omegas(self, amps, dt, order, hold):
         return [slice_omega(self.liouv, amps, n, dt, order, hold)
                 for n in range(amps.shape[0])]
@@ -71,7 +75,7 @@ class System:
         out = {}
         for m, (w1, w2) in w.items():
             for c in range(self.n_ctrl):
-                G = self.eps[c] * lift_hamiltonian(self.Hc[c])
+                G = self.eps[c] * self.ctrl_generator(c)
                 d1, d2 = w1 * G, w2 * G
                 dom = 0.5 * dt * (d1 + d2)
                 if order == 2:
