@@ -1,10 +1,15 @@
-"""Block-tiled path (superoperators larger than one 64x64 tile): 4 spins,
-256 x 256 superoperator, FP32, against the FP64 oracle; full-size 4-spin
-configuration through invariants."""
+"""Block-tiled path (superoperators larger than one 64x64 tile), FP32, against
+the FP64 oracle: 4 spins (256 x 256) element by element on short pulses and, at
+the full 8192-slice size, through invariants and the closed-system reduction
+(the superoperator of a closed system is conj(V) (x) V, V computed by the oracle
+in Hilbert space); 5 spins (1024 x 1024) element by element; 6 spins
+(4096 x 4096) through the closed-system reduction (propagator, F, every
+gradient coordinate) and sampled propagator columns of the dissipative system."""
 import numpy as np
 import pytest
 
 import oracle
+from oracle import hilbert as hb
 import synth
 from helpers import oracle_system, lib_system, rounded, rel
 
@@ -99,3 +104,90 @@ def test_four_spin_high_fidelity_closed_system():
     sysm, U, F, _ = run({**cfg, "U_target": tgt}, amps, want_grad=False, dissipative=False)
     assert rel(U, S_ref) < 1e-4
     assert abs(F - F_ref) <= 1e-6
+
+
+def test_four_spin_full_size_closed_system():
+    """All 8192 slices of the 4-spin configuration without dissipation: the
+    whole 256 x 256 propagator against conj(V) (x) V and F against
+    |Tr(U_T^dag V)|^2 / d^2."""
+    cfg = synth.config3_four()
+    amps = rounded(cfg["amps"], "f32")
+    V = hb.unitary(hb.HilbertSystem.from_cfg(cfg), amps, cfg["dt"], 2, "foh")
+    sysm, U, F, _ = run(cfg, amps, want_grad=False, dissipative=False)
+    assert rel(U, hb.superop(V)) <= 1e-4
+    assert abs(F - hb.fidelity(V, cfg["U_target"])) <= 1e-6
+
+
+def test_four_spin_closed_gradient_all_coordinates():
+    """Every gradient coordinate (3 controls x 2048 slices of the 4-spin pulse)
+    against the oracle's Hilbert-space adjoint, norm-wise."""
+    cfg = synth.config3_four()
+    amps = rounded(cfg["amps"][:2048], "f32")
+    F_ref, g_ref = hb.grad(hb.HilbertSystem.from_cfg(cfg), amps, cfg["dt"], 2, "foh",
+                           cfg["U_target"])
+    sysm, U, F, g = run(cfg, amps, dissipative=False)
+    assert abs(F - F_ref) <= 1e-6
+    assert rel(g, g_ref) <= 1e-3
+
+
+def test_four_spin_dissipative_512_slices():
+    """The dissipative 4-spin system on the first 512 slices of its pulse: the
+    whole propagator and F against the dense oracle, the gradient on sampled
+    rows against the oracle's adjoint."""
+    cfg = synth.config3_four()
+    amps = rounded(cfg["amps"][:512], "f32")
+    osys = oracle_system(cfg)
+    sysm, U, F, g = run(cfg, amps)
+    rows = [0, 1, 137, 300, 510, 511]
+    F_ref, g_at = oracle.grad_adjoint_at(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"], rows)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    assert rel(U, U_ref) <= 1e-4
+    assert abs(F - F_ref) <= 1e-6
+    ours = np.concatenate([g[r] for r in rows])
+    ref = np.concatenate([g_at[r] for r in rows])
+    assert rel(ours, ref) <= 1e-3
+
+
+@pytest.fixture(scope="module")
+def six_closed():
+    cfg = synth.config3_six()
+    amps = rounded(cfg["amps"][:2], "f32")
+    sysm, U, F, g = run(cfg, amps, dissipative=False)
+    return cfg, amps, U, F, g
+
+
+def test_six_spin_closed_propagator_and_fidelity(six_closed):
+    """6 spins (superoperator 4096 x 4096), two 1 ns slices, FOH second order:
+    the whole propagator against conj(V) (x) V and F against the reduction."""
+    cfg, amps, U, F, g = six_closed
+    V = hb.unitary(hb.HilbertSystem.from_cfg(cfg), amps, cfg["dt"], 2, "foh")
+    assert rel(U, hb.superop(V)) <= 1e-4
+    assert abs(F - hb.fidelity(V, cfg["U_target"])) <= 1e-6
+
+
+def test_six_spin_closed_gradient(six_closed):
+    """All 2 x 5 gradient coordinates against the reduction's adjoint and its
+    FP64 central differences."""
+    cfg, amps, U, F, g = six_closed
+    hs = hb.HilbertSystem.from_cfg(cfg)
+    F_ref, g_ref = hb.grad(hs, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    assert rel(g, g_ref) <= 1e-3
+    fd = hb.grad_fd(hs, amps, cfg["dt"], 2, "foh", cfg["U_target"], np.arange(amps.size))
+    assert rel(g.reshape(-1), fd) <= 1e-3
+
+
+def test_six_spin_dissipative_sampled_columns():
+    """The dissipative 6-spin propagator of two 1 ns slices: eight sampled
+    columns against the oracle's slice-exponential action (Omega_n applied
+    through the dense Eq. 8 node matrices), and trace preservation of the
+    whole propagator."""
+    cfg = synth.config3_six()
+    amps = rounded(cfg["amps"][:2], "f32")
+    sysm, U, F, _ = run(cfg, amps, want_grad=False)
+    d = 64
+    vI = np.eye(d).T.reshape(-1)
+    assert np.abs(vI @ U - vI).max() < 1e-4
+    cols = np.random.default_rng(6).choice(d * d, 8, replace=False)
+    cols[0] = 0                                   # |0><0|: populations
+    ref = hb.propagator_columns(oracle_system(cfg), amps, cfg["dt"], 2, "foh", list(cols))
+    assert rel(U[:, cols], ref) <= 2e-5
