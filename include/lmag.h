@@ -166,6 +166,27 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx *ctx, const lmag_batch *batch,
                                    const int32_t *target_of_item, double *F_out,
                                    void *grad_out, void *hip_stream);
 
+/* lmag_fidelity_and_grad without any allocation, for callers that cannot
+ * allocate device memory during the call: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. Same arguments, results and
+ * kernels as lmag_fidelity_and_grad, for systems with n = d*d <= 64 (else
+ * LMAG_E_UNSUPPORTED). The call makes no hipMalloc, hipFree, pinned-host or
+ * other device allocation: its workspace is a fixed scratch array of 64 MiB
+ * compiled into the library, one copy per GPU (held from the first context on
+ * that GPU until the process ends); the plan metadata is staged through a
+ * pageable host buffer of the context. A batch whose workspace exceeds the
+ * scratch (about 160 KiB per slice and 192 KiB per chunk in FP32 with the
+ * gradient; twice that in FP64) is rejected with LMAG_E_INVALID and nothing is
+ * launched; it is never split into waves or recomputed. Every call on one GPU,
+ * from any context, shares that GPU's scratch and leaves its contents behind
+ * (the work counters are cleared by a kernel at the start of each call): calls
+ * that overlap in time on one GPU race and must be ordered by the caller.
+ * Calls on one context are ordered as for the other compute calls. */
+lmag_status lmag_fidelity_and_grad_noalloc(lmag_ctx *ctx, const lmag_batch *batch,
+                                           const void *U_target, int n_targets,
+                                           const int32_t *target_of_item, double *F_out,
+                                           void *grad_out, void *hip_stream);
+
 /* Logical-subspace score of the propagator and (optionally) its gradient
  * (Sec. III-C, Eq. 16-17). With P the n x L matrix whose columns are the
  * vectorised (column-stacked) logical operators, every item's U is projected to

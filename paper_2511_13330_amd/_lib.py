@@ -58,6 +58,8 @@ SIGNATURES = {
     "lmag_propagate": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_void_p]),
     "lmag_fidelity_and_grad": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_int,
                                        c_int32_p, c_void_p, c_void_p, c_void_p]),
+    "lmag_fidelity_and_grad_noalloc": (c_int, [c_void_p, ctypes.POINTER(Batch), c_void_p, c_int,
+                                               c_int32_p, c_void_p, c_void_p, c_void_p]),
     "lmag_logical_score_and_grad": (c_int, [c_void_p, ctypes.POINTER(Batch), c_int, c_int, c_double_p,
                                             c_void_p, c_int, c_int32_p, c_void_p, c_void_p, c_void_p]),
     "lmag_sync": (c_int, [c_void_p, c_void_p]),

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -76,6 +77,8 @@ struct lmag_ctx {
   size_t ws_size = 0;
   char* pinned = nullptr;
   size_t pinned_size = 0;
+  std::vector<char> meta_host;     // pageable plan staging of the no-allocation entry point
+  char* scratch = nullptr;         // this device's copy of the static scratch array
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   hipStream_t last_stream = nullptr;
@@ -362,10 +365,26 @@ lmag_status ensure_pinned(lmag_ctx* c, size_t bytes) {
   return LMAG_OK;
 }
 
-lmag_status upload_plan(lmag_ctx* c, const Plan& p, const Layout& L, hipStream_t s) {
-  lmag_status st = ensure_pinned(c, L.meta_end);
-  if (st != LMAG_OK) return st;
-  char* h = c->pinned;
+// Copies the plan metadata to dst (the start of the call's workspace). The host
+// staging buffer is the context's pinned buffer, or with pinned = false a
+// pageable host buffer of the context (the entry point that allocates no device
+// or pinned memory); either is reused only after the previous upload finished.
+lmag_status upload_plan(lmag_ctx* c, const Plan& p, const Layout& L, hipStream_t s, char* dst,
+                        bool pinned = true) {
+  char* h = nullptr;
+  if (pinned) {
+    lmag_status st = ensure_pinned(c, L.meta_end);
+    if (st != LMAG_OK) return st;
+    h = c->pinned;
+  } else {
+    if (c->upload_pending) {
+      hipError_t e = hipEventSynchronize(c->upload_done);
+      if (e != hipSuccess) return c->hip_fail(e, "hipEventSynchronize");
+      c->upload_pending = false;
+    }
+    if (c->meta_host.size() < L.meta_end) c->meta_host.resize(L.meta_end);
+    h = c->meta_host.data();
+  }
   std::memset(h, 0, L.meta_end);
   auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(h + off, src, bytes); };
   put(L.items, p.items.data(), p.items.size() * sizeof(Item));
@@ -376,7 +395,7 @@ lmag_status upload_plan(lmag_ctx* c, const Plan& p, const Layout& L, hipStream_t
   put(L.group_first, p.group_first.data(), p.group_first.size() * 4);
   put(L.group_items, p.group_items.data(), p.group_items.size() * 4);
   put(L.group_global, p.group_global.data(), p.group_global.size() * 4);
-  hipError_t e = hipMemcpyAsync(c->ws, h, L.meta_end, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(dst, h, L.meta_end, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return c->hip_fail(e, "hipMemcpyAsync(plan)");
   e = hipEventRecord(c->upload_done, s);
   if (e != hipSuccess) return c->hip_fail(e, "hipEventRecord");
@@ -413,8 +432,8 @@ struct StageTimer {
 
 lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L, bool grad,
                 bool fidelity, const void* U_target, int n_targets, double* F_out, void* grad_out,
-                void* S_out, hipStream_t s, int grid) {
-  char* w = c->ws;
+                void* S_out, hipStream_t s, int grid, char* base) {
+  char* w = base;
   auto at = [&](size_t off) { return (void*)(w + off); };
   const Item* items = (const Item*)at(L.items);
   const size_t es = (c->prec == 32 ? 8 : 16);
@@ -534,6 +553,39 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     { StageTimer t(c, 7, s); HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad"); }
   }
   return LMAG_OK;
+}
+
+// Workspace of lmag_fidelity_and_grad_noalloc: a file-scope device array. Each
+// GPU the library runs on holds its own copy, at its own address, until the
+// process ends. Host code never passes the array's name to a kernel or copy (in
+// host code it is a host-side stand-in); it uses the address that
+// hipGetSymbolAddress returns with the device current, taken once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 256;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of this context's copy of `scratch` (the context's device must
+// be current). Returns nullptr and leaves a message if the lookup fails.
+char* scratch_address(lmag_ctx* c) {
+  if (c->device < 0 || c->device >= kMaxDevices) {
+    c->err = "device index beyond the scratch table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[c->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      c->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_addr[c->device] = (char*)ptr;
+  }
+  return g_scratch_addr[c->device];
 }
 
 size_t device_budget(lmag_ctx* c) {
@@ -1153,7 +1205,7 @@ lmag_status run_waves_body(lmag_ctx* c, const lmag_batch* b, const int32_t* targ
     }
     st = ensure_ws(c, L.total);
     if (st != LMAG_OK) return st;
-    st = upload_plan(c, p, L, s);
+    st = upload_plan(c, p, L, s, c->ws);
     if (st != LMAG_OK) return st;
     c->plan_info[0] = p.total_slices;
     c->plan_info[1] = p.total_chunks;
@@ -1161,7 +1213,7 @@ lmag_status run_waves_body(lmag_ctx* c, const lmag_batch* b, const int32_t* targ
     c->plan_info[3] = grid;
     c->plan_info[4] = (int64_t)L.total;
     c->plan_recompute = p.recompute;
-    st = run(c, b, p, L, grad, fidelity, U_target, n_targets, F_out, grad_out, S_out, s, grid);
+    st = run(c, b, p, L, grad, fidelity, U_target, n_targets, F_out, grad_out, S_out, s, grid, c->ws);
     if (st != LMAG_OK) return st;
     u = v;
     ++waves;
@@ -1197,6 +1249,7 @@ lmag_status lmag_create(lmag_ctx** out, int hip_device) {
       delete c;
       return LMAG_E_DEVICE;
     }
+    c->scratch = scratch_address(c);   // checked again by the entry point that uses it
     pade_coeffs(3, c->pade.b3);
     pade_coeffs(5, c->pade.b5);
     pade_coeffs(7, c->pade.b7);
@@ -1392,6 +1445,57 @@ lmag_status lmag_fidelity_and_grad(lmag_ctx* c, const lmag_batch* b, const void*
     hipStream_t s = (hipStream_t)hip_stream;
     return run_waves(c, b, target_of_item, n_targets, grad_out != nullptr, true, U_target, F_out,
                      grad_out, nullptr, s);
+  } catch (const std::bad_alloc&) {
+    return c->fail(LMAG_E_NOMEM, "host allocation failed");
+  } catch (...) {
+    return c->fail(LMAG_E_DEVICE, "unknown error");
+  }
+}
+
+lmag_status lmag_fidelity_and_grad_noalloc(lmag_ctx* c, const lmag_batch* b, const void* U_target,
+                                           int n_targets, const int32_t* target_of_item,
+                                           double* F_out, void* grad_out, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  try {
+    if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
+    if (!U_target || n_targets < 1) return c->fail(LMAG_E_INVALID, "U_target NULL or n_targets < 1");
+    if (!F_out) return c->fail(LMAG_E_INVALID, "F_out is NULL");
+    if (c->n > 64)
+      return c->fail(LMAG_E_UNSUPPORTED, "the no-allocation entry point covers superoperators up to 64 x 64");
+    if (!c->scratch) return c->fail(LMAG_E_DEVICE, "no address for the scratch array on this device");
+    const bool grad = grad_out != nullptr;
+    lmag_status st = validate_batch(c, b, target_of_item, n_targets, grad);
+    if (st != LMAG_OK) return st;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::vector<int> all(b->n_items);
+    for (int i = 0; i < b->n_items; ++i) all[i] = i;
+    Plan p;
+    plan_wave(c, b, target_of_item, all, p, false);
+    p.recompute = false;
+    const int grid = std::max(1, std::min(p.total_chunks, c->n_cu));
+    const Layout L = layout(c, p, n_targets, grad, grid);
+    if (L.total > kScratchBytes)
+      return c->fail(LMAG_E_INVALID, "the call needs " + std::to_string(L.total) +
+                                         " bytes of workspace, over the fixed scratch of " +
+                                         std::to_string(kScratchBytes) +
+                                         " bytes: split the batch, or use lmag_fidelity_and_grad");
+    if (c->call_pending && s != c->last_stream)
+      HIPCHK(hipStreamWaitEvent(s, c->call_done, 0), "hipStreamWaitEvent");
+    c->last_stream = s;
+    st = upload_plan(c, p, L, s, c->scratch, false);
+    if (st == LMAG_OK) {
+      c->plan_info[0] = p.total_slices; c->plan_info[1] = p.total_chunks;
+      c->plan_info[2] = p.chunk_size; c->plan_info[3] = grid; c->plan_info[4] = (int64_t)L.total;
+      c->plan_recompute = false;
+      c->plan_waves = 1;
+      st = run(c, b, p, L, grad, true, U_target, n_targets, F_out, grad_out, nullptr, s, grid,
+               c->scratch);
+    }
+    const hipError_t e = hipEventRecord(c->call_done, s);
+    if (e != hipSuccess && st == LMAG_OK) return c->hip_fail(e, "hipEventRecord");
+    c->call_pending = true;
+    return st;
   } catch (const std::bad_alloc&) {
     return c->fail(LMAG_E_NOMEM, "host allocation failed");
   } catch (...) {

@@ -115,6 +115,22 @@ class System:
                           static_coef=None, ctrl_scale=None, target_of_item=None,
                           groups=None, want_grad=True, stream=None):
         """(F [n_items or n_groups] float64, dF/du like amps or None)."""
+        return self._fidelity(lib().lmag_fidelity_and_grad, amps, n_slices, dt, U_target,
+                              slice_offset, static_coef, ctrl_scale, target_of_item, groups,
+                              want_grad, stream)
+
+    def fidelity_and_grad_noalloc(self, amps, n_slices, dt, U_target, F_out, grad_out=None,
+                                  slice_offset=None, static_coef=None, ctrl_scale=None,
+                                  target_of_item=None, groups=None, stream=None):
+        """lmag_fidelity_and_grad_noalloc: the caller passes the outputs F_out
+        (float64 CUDA tensor [n_items or n_groups]) and grad_out (like amps, or
+        None); the library allocates nothing during the call."""
+        return self._fidelity(lib().lmag_fidelity_and_grad_noalloc, amps, n_slices, dt,
+                              U_target, slice_offset, static_coef, ctrl_scale, target_of_item,
+                              groups, grad_out is not None, stream, F_out, grad_out)
+
+    def _fidelity(self, fn, amps, n_slices, dt, U_target, slice_offset, static_coef, ctrl_scale,
+                  target_of_item, groups, want_grad, stream, F=None, grad=None):
         b, keep, n_items, ng = self._batch(amps, n_slices, slice_offset, dt, static_coef,
                                            ctrl_scale, groups)
         UT = torch.as_tensor(U_target, dtype=torch.complex128, device=self.device)
@@ -124,9 +140,17 @@ class System:
             toi = np.ascontiguousarray(target_of_item, dtype=np.int32).reshape(-1)
             keep.append(toi)
             tp = toi.ctypes.data_as(_lib.c_int32_p)
-        F = torch.empty(ng if ng else n_items, dtype=torch.float64, device=self.device)
-        grad = torch.zeros_like(amps) if want_grad else None
-        check(lib().lmag_fidelity_and_grad(
+        if F is None:
+            F = torch.empty(ng if ng else n_items, dtype=torch.float64, device=self.device)
+            grad = torch.zeros_like(amps) if want_grad else None
+        else:
+            if not (F.is_cuda and F.dtype == torch.float64 and F.is_contiguous()
+                    and F.numel() == (ng if ng else n_items)):
+                raise TypeError("F_out must be a contiguous float64 CUDA tensor [n_items or n_groups]")
+            if grad is not None and not (grad.is_cuda and grad.dtype == amps.dtype
+                                         and grad.is_contiguous() and grad.shape == amps.shape):
+                raise TypeError("grad_out must be a contiguous CUDA tensor like amps")
+        check(fn(
             self._ctx, ctypes.byref(b), ctypes.c_void_p(UT.data_ptr()), UT.shape[0], tp,
             ctypes.c_void_p(F.data_ptr()),
             ctypes.c_void_p(grad.data_ptr()) if grad is not None else None,
