@@ -235,6 +235,12 @@ hipError_t launch_cast_bf16(const float* in, uint16_t* out, int64_t n, hipStream
 
 // block-tiled path (n = 64 T)
 constexpr int MAX_BIG_NB = 64;
+// Block-tiled path: Neumann levels of the Pade-3 denominator inverse (the
+// single-precision bound of neumann_levels; a slice whose bound does not hold
+// takes all of them) and the largest supported scaling exponent.
+constexpr int kBigNeumannLevels = 4;
+constexpr int kBigMaxSquarings = 64;
+
 struct BigGemmArgs {
   int n, batch;
   const void* A; const int32_t* Ai;

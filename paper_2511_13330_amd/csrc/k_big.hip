@@ -193,7 +193,10 @@ __global__ void __launch_bounds__(256) k_bnorm(BigOmegaArgs g) {
     big_choose_ms<T>(v, m, s);
     g.ms[2 * (size_t)slice] = (int8_t)m;
     g.ms[2 * (size_t)slice + 1] = (int8_t)s;
-    if (g.nlev) g.nlev[slice] = (int8_t)big_neumann_levels<T>(ldexp(v, -s), g.b3);
+    if (g.nlev) {
+      const int lv = big_neumann_levels<T>(ldexp(v, -s), g.b3);
+      g.nlev[slice] = (int8_t)(lv > 0 ? lv : kBigNeumannLevels);
+    }
     sc_sh = s;
   }
   __syncthreads();

@@ -716,36 +716,132 @@ bool build_sparse(lmag_ctx* c, const std::vector<double>& hb, int nb, int prec) 
   return true;
 }
 
+// Layout of a block-tiled call: metadata and index lists, per-slice scalars,
+// then the matrices. `window` is the number of slices whose per-slice matrices
+// are held at once (all of them when the adjoint stores them).
+struct BigLayout {
+  size_t meta_end = 0, alpha = 0, gtrace = 0, ms = 0, nlev = 0, F_items = 0, part = 0, st64 = 0,
+         st = 0, sq = 0, mats = 0, cmats = 0, total = 0;
+};
+
+BigLayout big_layout(const lmag_ctx* c, size_t meta_bytes, int Ns, int Lc, int n_items, int window,
+                     int n_targets, bool grad) {
+  const int n = c->n, Tn = n / 64;
+  const size_t mb = (size_t)n * n * 8;
+  BigLayout L;
+  size_t o = align_up(meta_bytes);
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  L.meta_end = o;
+  L.alpha = take((size_t)Ns * c->nb * 8);
+  L.gtrace = take((size_t)Ns * c->nb * 8);
+  L.ms = take((size_t)Ns * 2);
+  L.nlev = take((size_t)Ns);
+  L.F_items = take((size_t)n_items * 8);
+  L.part = take(std::max((size_t)window * Tn * n * 8, (size_t)window * Tn * Tn * c->nb * 8));
+  L.st64 = take((size_t)std::max(1, n_targets) * n * n * 16);
+  L.st = take((size_t)std::max(1, n_targets) * mb);
+  L.sq = take((size_t)Ns * kBigMaxSquarings * 4 + 4);   // squaring lists of every window
+  L.mats = take((size_t)(grad ? 11 : 7) * window * mb);
+  L.cmats = take((size_t)8 * Lc * mb);
+  L.total = o;
+  return L;
+}
+
+// One slice window of a block-tiled call: whole chunks [c0, c1), slices
+// [s0, s0 + ns), its chain steps, and the squaring lists read back after its
+// slice exponents.
+struct BigWindow {
+  int c0 = 0, c1 = 0, s0 = 0, ns = 0;
+  size_t koff = 0;                      // first entry of its chain-step offsets
+  int smax = 0;
+  size_t sq_base = 0;                   // first entry of its squaring lists
+  std::vector<int32_t> sq_list, sq_off;
+};
+
 lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
                     int n_targets, bool grad, bool fidelity, const void* U_target, double* F_out,
                     void* grad_out, void* S_out, hipStream_t s) {
   const int n = c->n, Tn = n / 64;
-  const size_t nn = (size_t)n * n, es = 8, mb = nn * es;   // FP32 complex matrices
+  const size_t nn = (size_t)n * n, mb = nn * 8;   // FP32 complex matrices
   std::vector<int> all(b->n_items);
   for (int i = 0; i < b->n_items; ++i) all[i] = i;
-  Plan p;
-  // chunk length: enough independent chunks to fill the device in the chains
   long long total = 0;
-  int maxN = 0;
-  for (int i = 0; i < b->n_items; ++i) { total += b->n_slices[i]; maxN = std::max(maxN, b->n_slices[i]); }
-  const int saved_chunk = c->chunk;
-  if (c->chunk <= 0) {
+  for (int i = 0; i < b->n_items; ++i) total += b->n_slices[i];
+  const int nt = fidelity ? n_targets : 0;
+  const size_t budget = device_budget(c);
+  // chunk length: enough independent chunks to fill the device in the chains
+  int C_auto = c->chunk;
+  if (C_auto <= 0) {
     const long long want_chunks = std::max<long long>(1, 2048 / ((long long)Tn * Tn));
-    c->chunk = (int)std::max<long long>(1, (total + want_chunks - 1) / want_chunks);
+    C_auto = (int)std::max<long long>(1, (total + want_chunks - 1) / want_chunks);
   }
-  plan_wave(c, b, target_of_item, all, p, false);
-  c->chunk = saved_chunk;
+  // metadata estimate (items, chunks, per-slice maps, index lists): bounded by
+  // a few words per slice and chunk; the exact size is taken after planning
+  auto plan_for = [&](int C, Plan& p) {
+    p = Plan();
+    const int saved = c->chunk;
+    c->chunk = C;
+    plan_wave(c, b, target_of_item, all, p, false);
+    c->chunk = saved;
+  };
+  auto meta_estimate = [&](const Plan& p, int C) {
+    return (size_t)p.items.size() * (sizeof(Item) + 64) + (size_t)p.chunks.size() * (sizeof(Chunk) + 64) +
+           (size_t)p.total_slices * 16 + (size_t)std::max(1, (int)std::ceil(std::log2(std::max(2, p.max_chunks)))) *
+           p.total_chunks * 32 + (size_t)(C + 2) * 64 + (1 << 16);
+  };
+  // stored: every slice's matrices at once; otherwise the largest window that
+  // fits, with chunks no longer than the window
+  Plan p;
+  plan_for(C_auto, p);
+  int W = p.total_slices;
+  BigLayout BL = big_layout(c, meta_estimate(p, C_auto), p.total_slices, p.total_chunks,
+                            (int)p.items.size(), W, nt, grad);
+  if (BL.total > budget) {
+    int lo = 0, hi = W;   // largest fitting window in (lo, hi]
+    while (hi - lo > 1) {
+      const int mid = lo + (hi - lo) / 2;
+      Plan pm;
+      const int Cm = std::min(C_auto, mid);
+      plan_for(Cm, pm);
+      const BigLayout Lm = big_layout(c, meta_estimate(pm, Cm), pm.total_slices, pm.total_chunks,
+                                      (int)pm.items.size(), mid, nt, grad);
+      if (Lm.total + ((size_t)1 << 20) <= budget) lo = mid; else hi = mid;
+    }
+    if (lo == 0)
+      return c->fail(LMAG_E_NOMEM, "block-tiled call does not fit the workspace budget of " +
+                                       std::to_string(budget) + " bytes even one slice at a time");
+    W = lo;
+    plan_for(std::min(C_auto, W), p);
+  }
   const int Ns = p.total_slices, Lc = p.total_chunks, C = p.chunk_size;
-  BigPlan q;
-  q.C = C;
-  // forward chain lists (chunks in original order, not the persistent sort)
+  const bool windowed = W < Ns;
+  // chunks in chain order, grouped into windows of whole chunks of at most W slices
   std::vector<Chunk> chs(Lc);
   for (const Chunk& ch : p.chunks) chs[ch.chunk] = ch;
-  q.chain_off.push_back(0);
-  for (int k = 0; k < C; ++k) {
-    for (const Chunk& ch : chs)
-      if (ch.count > k) { q.chain_slice.push_back(ch.first + k); q.chain_chunk.push_back(ch.chunk); }
+  std::vector<BigWindow> win;
+  for (int ci = 0; ci < Lc;) {
+    BigWindow w;
+    w.c0 = ci; w.s0 = chs[ci].first;
+    int cnt = 0;
+    while (ci < Lc && cnt + chs[ci].count <= W) cnt += chs[ci++].count;
+    w.c1 = ci; w.ns = cnt;
+    win.push_back(std::move(w));
+  }
+  BigPlan q;
+  q.C = C;
+  // chain steps per window: step k advances the window's chunks longer than k
+  // (window-local slice index, global chunk index)
+  for (BigWindow& w : win) {
+    w.koff = q.chain_off.size();
     q.chain_off.push_back((int32_t)q.chain_slice.size());
+    for (int k = 0; k < C; ++k) {
+      for (int ci = w.c0; ci < w.c1; ++ci)
+        if (chs[ci].count > k) {
+          q.chain_slice.push_back(chs[ci].first + k - w.s0);
+          q.chain_chunk.push_back(ci);
+        }
+      q.chain_off.push_back((int32_t)q.chain_slice.size());
+    }
   }
   // scan levels: inclusive prefix P[c] = P[c] P[c - st]; suffix S[c] = S[c + st] S[c]
   q.scan_off.push_back(0);
@@ -781,7 +877,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   }
   for (int i = 0; i < std::max(Ns, Lc); ++i) q.ident.push_back(i);
 
-  // ---- workspace: metadata, int lists, then matrices
+  // ---- workspace: metadata, int lists, then scalars and matrices
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
   Layout L{};
@@ -802,24 +898,12 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
                o_est = list(q.env_suf_t), o_ent = list(q.env_nosuf_t),
                o_il = list(q.item_last_chunk), o_it = list(q.item_target),
                o_is = list(q.item_src), o_id = list(q.ident);
-  L.meta_end = o;
-  L.alpha = take((size_t)Ns * c->nb * 8);
-  L.gtrace = take((size_t)Ns * c->nb * 8);
-  L.ms = take((size_t)Ns * 2);
-  L.nlev = take((size_t)Ns);
-  L.F_items = take(p.items.size() * 8);
-  const size_t o_part = take(std::max((size_t)Ns * Tn * n * 8, (size_t)Ns * Tn * Tn * c->nb * 8));
-  L.st64 = take((size_t)std::max(1, n_targets) * nn * 16);
-  L.st = take((size_t)std::max(1, n_targets) * mb);
-  const size_t o_sq = take((size_t)Ns * 64 * 4 + 4);   // slices with s > k, per k
-  const int nslice_mats = grad ? 11 : 7;
-  const size_t o_mats = take((size_t)nslice_mats * Ns * mb);
-  const size_t o_cmats = take((size_t)8 * Lc * mb);
-  L.total = o;
-  if (L.total > device_budget(c))
-    return c->fail(LMAG_E_NOMEM, "block-tiled call needs " + std::to_string(L.total) +
-                                     " bytes of workspace, over the budget");
-  lmag_status st = ensure_ws(c, L.total);
+  BL = big_layout(c, o, Ns, Lc, (int)p.items.size(), W, nt, grad);
+  L.meta_end = BL.meta_end;
+  if (BL.total > budget)
+    return c->fail(LMAG_E_NOMEM, "block-tiled call needs " + std::to_string(BL.total) +
+                                     " bytes of workspace, over the budget of " + std::to_string(budget));
+  lmag_status st = ensure_ws(c, BL.total);
   if (st != LMAG_OK) return st;
   // upload metadata + lists in one copy
   st = ensure_pinned(c, L.meta_end);
@@ -839,15 +923,17 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   HIPCHK(hipEventRecord(c->upload_done, s), "event");
   c->upload_pending = true;
 
-  char* w = c->ws;
-  auto at = [&](size_t off) { return (void*)(w + off); };
-  auto ip = [&](size_t off) { return (const int32_t*)(w + off); };
-  auto M = [&](int k) { return at(o_mats + (size_t)k * Ns * mb); };     // per-slice matrix array k
-  auto CM = [&](int k) { return at(o_cmats + (size_t)k * Lc * mb); };   // per-chunk matrix array k
+  char* w_ = c->ws;
+  auto at = [&](size_t off) { return (void*)(w_ + off); };
+  auto ip = [&](size_t off) { return (const int32_t*)(w_ + off); };
+  auto M = [&](int k) { return at(BL.mats + (size_t)k * W * mb); };     // per-slice matrix array k (window)
+  auto CM = [&](int k) { return at(BL.cmats + (size_t)k * Lc * mb); };  // per-chunk matrix array k
   void *A = M(0), *A2 = M(1), *R0 = M(2), *S = M(3), *Qi = M(4), *T1 = M(5), *T2 = M(6);
   void *Pl = grad ? M(7) : nullptr, *Em = grad ? M(8) : nullptr, *T3 = grad ? M(9) : nullptr,
        *T4 = grad ? M(10) : nullptr;
   const Item* items = (const Item*)at(L.items);
+  int8_t* ms_all = (int8_t*)at(BL.ms);
+  int8_t* nlev_all = (int8_t*)at(BL.nlev);
 
   auto gemm = [&](int batch, const void* Ap, const int32_t* Ai, const void* Bp, const int32_t* Bi,
                   const void* Cp, const int32_t* Ci, double alpha, const void* Dp = nullptr,
@@ -856,22 +942,26 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     BigGemmArgs g{};
     g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
     g.D = Dp; g.Di = Di; g.alpha = alpha; g.beta = beta; g.gamma = gamma; g.transA = tA; g.transB = tB;
-    g.pred = pred; g.pred_stride = 2; g.pred_thresh = thresh;
+    g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh;
     return launch_bgemm(32, g, s);
   };
   // C = alpha A B + beta D + beta2 D2 with index maps (null: the batch index)
   auto gemmx = [&](int batch, const void* Ap, const int32_t* Ai, const void* Bp, const int32_t* Bi,
                    const void* Cp, const int32_t* Ci, double alpha, const void* Dp, const int32_t* Di,
-                   double beta, const void* D2p, const int32_t* D2i, double beta2) {
+                   double beta, const void* D2p, const int32_t* D2i, double beta2,
+                   const int8_t* pred = nullptr, int thresh = 0) {
     BigGemmArgs g{};
     g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
     g.D = Dp; g.Di = Di; g.D2 = D2p; g.D2i = D2i;
-    g.alpha = alpha; g.beta = beta; g.beta2 = beta2; g.pred_stride = 2;
+    g.alpha = alpha; g.beta = beta; g.beta2 = beta2;
+    g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh;
     return launch_bgemm(32, g, s);
   };
   auto gemm2 = [&](int batch, const void* Ap, const void* Bp, const void* Cp, double alpha,
-                   const void* Dp, double beta, const void* D2p, double beta2) {
-    return gemmx(batch, Ap, nullptr, Bp, nullptr, Cp, nullptr, alpha, Dp, nullptr, beta, D2p, nullptr, beta2);
+                   const void* Dp, double beta, const void* D2p, double beta2,
+                   const int8_t* pred = nullptr, int thresh = 0) {
+    return gemmx(batch, Ap, nullptr, Bp, nullptr, Cp, nullptr, alpha, Dp, nullptr, beta, D2p, nullptr,
+                 beta2, pred, thresh);
   };
   auto axpby = [&](int batch, const void* X, const int32_t* Xi, void* Y, const int32_t* Yi, double a,
                    const void* Z = nullptr, const int32_t* Zi = nullptr, double cc = 0.0, double d = 0.0,
@@ -883,91 +973,114 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   };
   const double* b3 = c->pade.b3;
 
-  // ---- coefficients and exponents
+  // ---- coefficients of every slice
   AlphaArgs aa{};
   aa.prec = 32; aa.amps = b->amps; aa.item_amp_offset = (const int64_t*)at(L.amp_off);
   aa.items = items; aa.n_items = (int)p.items.size(); aa.static_coef = b->static_coef;
   aa.ctrl_scale = b->ctrl_scale; aa.n_ctrl = c->nc; aa.n_static = c->ns; aa.order = c->order;
   aa.hold_foh = c->hold == LMAG_FOH; aa.nb = c->nb; aa.dt = b->dt;
-  aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(L.alpha);
+  aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(BL.alpha);
   aa.n_slices_total = Ns;
   { StageTimer t(c, 0, s); HIPCHK(launch_alpha(aa, s), "alpha"); }
-  BigOmegaArgs om{};
-  om.n = n; om.n_slices = Ns; om.nb = c->nb; om.basis = c->basis32; om.alpha = (const double*)at(L.alpha);
-  om.omega = A; om.part = (double*)at(o_part); om.ms = (int8_t*)at(L.ms); om.nlev = (int8_t*)at(L.nlev);
-  for (int i = 0; i < 4; ++i) om.b3[i] = b3[i];
-  { StageTimer t(c, 1, s); HIPCHK(launch_bomega(32, om, s), "omega"); }
-  c->last_ms = (int8_t*)at(L.ms);
+  c->last_ms = ms_all;
   c->last_total_slices = Ns;
-  // the host needs the largest scaling exponent and Neumann level count
-  std::vector<int8_t> msh((size_t)Ns * 2), nlh(Ns);
-  HIPCHK(hipMemcpyAsync(msh.data(), at(L.ms), msh.size(), hipMemcpyDeviceToHost, s), "ms");
-  HIPCHK(hipMemcpyAsync(nlh.data(), at(L.nlev), nlh.size(), hipMemcpyDeviceToHost, s), "nlev");
-  HIPCHK(hipStreamSynchronize(s), "sync");
-  int smax = 0, kmax = 1;
-  for (int i = 0; i < Ns; ++i) {
-    smax = std::max<int>(smax, msh[2 * i + 1]);
-    kmax = std::max<int>(kmax, nlh[i] > 0 ? nlh[i] : 4);
-  }
-  // per-k lists of the slices that take a k-th squaring
-  std::vector<int32_t> sq_list, sq_off(1, 0);
-  for (int k = 0; k < smax; ++k) {
-    for (int i = 0; i < Ns; ++i)
-      if (msh[2 * i + 1] > k) sq_list.push_back(i);
-    sq_off.push_back((int32_t)sq_list.size());
-  }
-  if (!sq_list.empty())
-    HIPCHK(hipMemcpy(at(o_sq), sq_list.data(), sq_list.size() * 4, hipMemcpyHostToDevice), "squaring lists");
-  const int8_t* ms_dev = (const int8_t*)at(L.ms);
 
-  // ---- forward: Pade 3 with the Neumann inverse, squarings. Matrices near the
-  // identity are carried as I + X with only X inside the products (see the
-  // 64 x 64 slice kernel): P = I + X_P, Q = I - E, Q^{-1} = I + X_Q, r = I + D.
-  {
-    StageTimer t(c, 2, s);
-    HIPCHK(gemm(Ns, A, nullptr, A, nullptr, A2, nullptr, 1.0), "A2");
-    HIPCHK(axpby(Ns, A2, nullptr, T1, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");
-    HIPCHK(gemm(Ns, A, nullptr, T1, nullptr, T2, nullptr, 1.0), "U");                  // T2 = U
-    HIPCHK(axpby(Ns, A2, nullptr, T1, nullptr, b3[2], T2, nullptr, 1.0), "X_P");        // T1 = b2 A2 + U
-    HIPCHK(axpby(Ns, A2, nullptr, S, nullptr, -b3[2], T2, nullptr, 1.0), "E");         // S = E = U - b2 A2
-    HIPCHK(axpby(Ns, S, nullptr, T2, nullptr, 1.0), "X = E");                           // T2 = X
-    // (I + X)(I + F2) - I = X + F2 + F2 X
-    void *F = S, *X = T2, *F2 = R0, *Xn = Qi;
-    for (int k = 1; k < kmax; ++k) {
-      HIPCHK(gemm(Ns, F, nullptr, F, nullptr, F2, nullptr, 1.0), "F2");
-      HIPCHK(gemm2(Ns, F2, X, Xn, 1.0, X, 1.0, F2, 1.0), "X + F2 + F2 X");
-      std::swap(F, F2);
-      std::swap(X, Xn);
-    }
-    if (X != Qi) HIPCHK(axpby(Ns, X, nullptr, Qi, nullptr, 1.0), "X_Q");
-    HIPCHK(gemm2(Ns, Qi, T1, R0, 1.0, Qi, 1.0, T1, 1.0), "D");   // R0 = X_Q + X_P + X_Q X_P
-    HIPCHK(axpby(Ns, R0, nullptr, S, nullptr, 1.0), "S");
-    // (I + D)^2 = I + 2 D + D^2
-    for (int k = 0; k < smax; ++k) {
-      const int cnt = sq_off[k + 1] - sq_off[k];
-      const int32_t* li = ip(o_sq) + sq_off[k];
-      if (!cnt) continue;
-      HIPCHK(gemm(cnt, S, li, S, li, T1, li, 1.0, S, li, 2.0), "square");
-      HIPCHK(axpby(cnt, T1, li, S, li, 1.0), "square copy");
-    }
-  }
-  // ---- ordered products inside chunks (forward chain), storing P_loc. Chunk
-  // products, prefixes and suffixes are kept as M - I: (I + D)(I + Q) - I = Q + D + D Q.
+  // Forward of one window: exponents, Pade 3 with the Neumann inverse,
+  // squarings, then the chain of its chunks (storing P_loc when asked).
+  // Matrices near the identity are carried as I + X with only X inside the
+  // products (see the 64 x 64 slice kernel): P = I + X_P, Q = I - E,
+  // Q^{-1} = I + X_Q, r = I + D. The first pass over a window reads its
+  // scaling exponents back to size the squaring loop (one host wait).
   void* Pc[2] = {CM(0), CM(1)};
-  {
-    StageTimer t(c, 2, s);
-    HIPCHK(axpby(Lc, Pc[0], nullptr, Pc[0], nullptr, 0.0), "P - I = 0");
-    int cur = 0;
-    for (int k = 0; k < C; ++k) {
-      const int a0 = q.chain_off[k], cnt = q.chain_off[k + 1] - a0;
-      if (cnt == 0) continue;
-      const int32_t* sl = ip(o_cs) + a0;
-      const int32_t* chn = ip(o_cc) + a0;
-      if (grad) HIPCHK(axpby(cnt, Pc[cur], chn, Pl, sl, 1.0, nullptr, nullptr, 0.0, 1.0), "store P_loc");
-      HIPCHK(gemmx(cnt, S, sl, Pc[cur], chn, Pc[cur ^ 1], chn, 1.0, Pc[cur], chn, 1.0, S, sl, 1.0), "chain");
-      // chunks not advanced at this step keep their product in the other buffer too
-      HIPCHK(axpby(cnt, Pc[cur ^ 1], chn, Pc[cur], chn, 1.0), "chain sync");
+  auto forward_window = [&](BigWindow& w, bool first_pass, bool store_ploc) -> lmag_status {
+    const int Wn = w.ns;
+    int8_t* ms_w = ms_all + 2 * (size_t)w.s0;
+    int8_t* nlev_w = nlev_all + w.s0;
+    BigOmegaArgs om{};
+    om.n = n; om.n_slices = Wn; om.nb = c->nb; om.basis = c->basis32;
+    om.alpha = (const double*)at(BL.alpha) + (size_t)w.s0 * c->nb;
+    om.omega = A; om.part = (double*)at(BL.part); om.ms = ms_w; om.nlev = nlev_w;
+    for (int i = 0; i < 4; ++i) om.b3[i] = b3[i];
+    { StageTimer t(c, 1, s); HIPCHK(launch_bomega(32, om, s), "omega"); }
+    if (first_pass) {
+      std::vector<int8_t> msh((size_t)Wn * 2);
+      HIPCHK(hipMemcpyAsync(msh.data(), ms_w, msh.size(), hipMemcpyDeviceToHost, s), "ms");
+      HIPCHK(hipStreamSynchronize(s), "sync");
+      w.smax = 0;
+      for (int i = 0; i < Wn; ++i) w.smax = std::max<int>(w.smax, msh[2 * i + 1]);
+      if (w.smax > kBigMaxSquarings)
+        return c->fail(LMAG_E_UNSUPPORTED, "a slice exponent needs more than " +
+                                               std::to_string(kBigMaxSquarings) + " squarings");
+      // per-k lists of the window's slices that take a k-th squaring
+      w.sq_list.clear();
+      w.sq_off.assign(1, 0);
+      for (int k = 0; k < w.smax; ++k) {
+        for (int i = 0; i < Wn; ++i)
+          if (msh[2 * i + 1] > k) w.sq_list.push_back(i);
+        w.sq_off.push_back((int32_t)w.sq_list.size());
+      }
+      w.sq_base = 0;
+      for (const BigWindow& v : win) {
+        if (&v == &w) break;
+        w.sq_base += v.sq_list.size();
+      }
+      if (!w.sq_list.empty())
+        HIPCHK(hipMemcpyAsync((int32_t*)at(BL.sq) + w.sq_base, w.sq_list.data(), w.sq_list.size() * 4,
+                              hipMemcpyHostToDevice, s), "squaring lists");
     }
+    const int32_t* sq = ip(BL.sq) + w.sq_base;
+    {
+      StageTimer t(c, 2, s);
+      HIPCHK(gemm(Wn, A, nullptr, A, nullptr, A2, nullptr, 1.0), "A2");
+      HIPCHK(axpby(Wn, A2, nullptr, T1, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");
+      HIPCHK(gemm(Wn, A, nullptr, T1, nullptr, T2, nullptr, 1.0), "U");                  // T2 = U
+      HIPCHK(axpby(Wn, A2, nullptr, T1, nullptr, b3[2], T2, nullptr, 1.0), "X_P");        // T1 = b2 A2 + U
+      HIPCHK(axpby(Wn, A2, nullptr, S, nullptr, -b3[2], T2, nullptr, 1.0), "E");         // S = E = U - b2 A2
+      HIPCHK(axpby(Wn, S, nullptr, T2, nullptr, 1.0), "X = E");                           // T2 = X
+      // (I + X)(I + F2) - I = X + F2 + F2 X; level k runs for the slices whose
+      // Neumann level count exceeds k (the others copy F and X through)
+      void *F = S, *X = T2, *F2 = R0, *Xn = Qi;
+      for (int k = 1; k < kBigNeumannLevels; ++k) {
+        HIPCHK(gemm(Wn, F, nullptr, F, nullptr, F2, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, 0, 0,
+                    nlev_w, k), "F2");
+        HIPCHK(gemm2(Wn, F2, X, Xn, 1.0, X, 1.0, F2, 1.0, nlev_w, k), "X + F2 + F2 X");
+        std::swap(F, F2);
+        std::swap(X, Xn);
+      }
+      if (X != Qi) HIPCHK(axpby(Wn, X, nullptr, Qi, nullptr, 1.0), "X_Q");
+      HIPCHK(gemm2(Wn, Qi, T1, R0, 1.0, Qi, 1.0, T1, 1.0), "D");   // R0 = X_Q + X_P + X_Q X_P
+      HIPCHK(axpby(Wn, R0, nullptr, S, nullptr, 1.0), "S");
+      // (I + D)^2 = I + 2 D + D^2
+      for (int k = 0; k < w.smax; ++k) {
+        const int cnt = w.sq_off[k + 1] - w.sq_off[k];
+        const int32_t* li = sq + w.sq_off[k];
+        if (!cnt) continue;
+        HIPCHK(gemm(cnt, S, li, S, li, T1, li, 1.0, S, li, 2.0), "square");
+        HIPCHK(axpby(cnt, T1, li, S, li, 1.0), "square copy");
+      }
+    }
+    // ordered products inside the window's chunks, kept as M - I:
+    // (I + D)(I + Q) - I = Q + D + D Q
+    {
+      StageTimer t(c, 2, s);
+      HIPCHK(axpby(w.c1 - w.c0, Pc[0], ip(o_id) + w.c0, Pc[0], ip(o_id) + w.c0, 0.0), "P - I = 0");
+      for (int k = 0; k < C; ++k) {
+        const int a0 = q.chain_off[w.koff + k], cnt = q.chain_off[w.koff + k + 1] - a0;
+        if (cnt == 0) continue;
+        const int32_t* sl = ip(o_cs) + a0;
+        const int32_t* chn = ip(o_cc) + a0;
+        if (store_ploc)
+          HIPCHK(axpby(cnt, Pc[0], chn, Pl, sl, 1.0, nullptr, nullptr, 0.0, 1.0), "store P_loc");
+        HIPCHK(gemmx(cnt, S, sl, Pc[0], chn, Pc[1], chn, 1.0, Pc[0], chn, 1.0, S, sl, 1.0), "chain");
+        HIPCHK(axpby(cnt, Pc[1], chn, Pc[0], chn, 1.0), "chain sync");
+      }
+    }
+    return LMAG_OK;
+  };
+  const bool store_now = grad && !windowed;
+  for (BigWindow& w : win) {
+    st = forward_window(w, true, store_now);
+    if (st != LMAG_OK) return st;
   }
   // ---- scan over chunk totals
   void* pre[2] = {CM(2), CM(3)};
@@ -995,20 +1108,26 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       bsel ^= 1;
     }
   }
+  auto finish_plan = [&]() {
+    c->plan_info[0] = Ns; c->plan_info[1] = Lc; c->plan_info[2] = C; c->plan_info[3] = 0;
+    c->plan_info[4] = (int64_t)BL.total;
+    c->plan_recompute = grad && windowed;
+    c->plan_waves = (int)win.size();
+  };
   if (S_out)   // U of every item = I + inclusive prefix at its last chunk
     HIPCHK(axpby((int)p.items.size(), pre_cur, ip(o_il), S_out, ip(o_is), 1.0, nullptr, nullptr, 0.0, 1.0),
            "extract");
-  if (!fidelity) return LMAG_OK;
+  if (!fidelity) { finish_plan(); return LMAG_OK; }
   // ---- targets, fidelity, environments
-  HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, (double*)at(L.st64), (float*)at(L.st), s),
+  HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, (double*)at(BL.st64), (float*)at(BL.st), s),
          "targets");
   const bool grouped = p.n_groups > 0;
-  double* F_items = grouped ? (double*)at(L.F_items) : F_out;
+  double* F_items = grouped ? (double*)at(BL.F_items) : F_out;
   {
     StageTimer t(c, 4, s);
     BigFidArgs fa{};
     fa.n = n; fa.n_items = (int)p.items.size(); fa.d = c->d; fa.U = pre_cur; fa.U_index = ip(o_il);
-    fa.st64 = (const double*)at(L.st64); fa.target = ip(o_it); fa.F = F_items;
+    fa.st64 = (const double*)at(BL.st64); fa.target = ip(o_it); fa.F = F_items;
     fa.F_index = grouped ? nullptr : ip(o_is);
     HIPCHK(launch_bfidelity(32, fa, s), "fidelity");
   }
@@ -1017,69 +1136,82 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     void* env = CM(7);
     {
       StageTimer t(c, 4, s);
-      const void* st = at(L.st);
+      const void* stt = at(BL.st);
       if (!q.env_suf_c.empty())
-        HIPCHK(gemm((int)q.env_suf_c.size(), st, ip(o_est), suf_cur, ip(o_en), X, ip(o_es), 1.0, st,
+        HIPCHK(gemm((int)q.env_suf_c.size(), stt, ip(o_est), suf_cur, ip(o_en), X, ip(o_es), 1.0, stt,
                     ip(o_est), 1.0), "env X");   // S_T^dag (I + Suf)
       if (!q.env_nosuf_c.empty())
-        HIPCHK(axpby((int)q.env_nosuf_c.size(), st, ip(o_ent), X, ip(o_ens), 1.0), "env X copy");
+        HIPCHK(axpby((int)q.env_nosuf_c.size(), stt, ip(o_ent), X, ip(o_ens), 1.0), "env X copy");
       if (!q.env_pre_c.empty())
         HIPCHK(gemm((int)q.env_pre_c.size(), pre_cur, ip(o_epp), X, ip(o_ep), env, ip(o_ep), 1.0, X,
                     ip(o_ep), 1.0), "env W");   // (I + Pre) X
       if (!q.env_nopre_c.empty())
         HIPCHK(axpby((int)q.env_nopre_c.size(), X, ip(o_enp), env, ip(o_enp), 1.0), "env W copy");
     }
-    // ---- backward chain: M_n = P_loc,n Z, Z <- Z S_n = Z + Z D_n (normal orientation)
-    {
-      StageTimer t(c, 5, s);
-      void* Z[2] = {env, X};
-      int cur = 0;
-      for (int k = C - 1; k >= 0; --k) {
-        const int a0 = q.chain_off[k], cnt = q.chain_off[k + 1] - a0;
-        if (cnt == 0) continue;
-        const int32_t* sl = ip(o_cs) + a0;
-        const int32_t* chn = ip(o_cc) + a0;
-        HIPCHK(gemm(cnt, Pl, sl, Z[cur], chn, Em, sl, 1.0), "M");
-        HIPCHK(gemm(cnt, Z[cur], chn, S, sl, Z[cur ^ 1], chn, 1.0, Z[cur], chn, 1.0), "Z");
-        HIPCHK(axpby(cnt, Z[cur ^ 1], chn, Z[cur], chn, 1.0), "Z sync");
+    // ---- adjoint, window by window (last first). A windowed call re-runs the
+    // window's forward first (recomputation instead of storage: the chunk
+    // totals and environments are already known, only P_loc, D, Q^{-1}, A and
+    // A^2 of its slices are rebuilt, bitwise as in the first pass).
+    for (int wi = (int)win.size() - 1; wi >= 0; --wi) {
+      BigWindow& w = win[wi];
+      const int Wn = w.ns;
+      if (windowed) {
+        st = forward_window(w, false, true);
+        if (st != LMAG_OK) return st;
       }
-      // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
-      HIPCHK(axpby(Ns, Em, nullptr, Em, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, ms_dev), "E scale");
-      HIPCHK(gemm(Ns, A, nullptr, Em, nullptr, T1, nullptr, 1.0), "AE");
-      HIPCHK(gemm(Ns, Em, nullptr, A, nullptr, T1, nullptr, 1.0, T1, nullptr, 1.0), "L2");       // T1 = L2
-      HIPCHK(axpby(Ns, A2, nullptr, T2, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");      // T2 = W
-      HIPCHK(axpby(Ns, T1, nullptr, T3, nullptr, b3[3]), "LW");                                    // T3 = L_W
-      HIPCHK(gemm(Ns, A, nullptr, T3, nullptr, T4, nullptr, 1.0), "A LW");
-      HIPCHK(gemm(Ns, Em, nullptr, T2, nullptr, T4, nullptr, 1.0, T4, nullptr, 1.0), "LU");       // T4 = L_U
-      HIPCHK(axpby(Ns, T1, nullptr, T3, nullptr, b3[2], T4, nullptr, -1.0), "LQ");                 // T3 = L_Q
-      HIPCHK(axpby(Ns, T1, nullptr, T2, nullptr, b3[2], T4, nullptr, 1.0), "LP");                  // T2 = L_P
-      // r = I + D (R0 = D), Q^{-1} = I + X_Q (Qi = X_Q)
-      HIPCHK(gemm2(Ns, T3, R0, T1, -1.0, T2, 1.0, T3, -1.0), "X");   // T1 = L_P - L_Q - L_Q D
-      HIPCHK(gemm(Ns, Qi, nullptr, T1, nullptr, T3, nullptr, 1.0, T1, nullptr, 1.0), "K");   // T3 = K
-      // squaring recurrence K <- R K + K R = 2 K + D K + K D, D <- 2 D + D D for the
-      // slices with s > k
-      for (int k = 0; k < smax; ++k) {
-        const int cnt = sq_off[k + 1] - sq_off[k];
-        const int32_t* li = ip(o_sq) + sq_off[k];
-        if (!cnt) continue;
-        HIPCHK(gemm(cnt, R0, li, T3, li, T4, li, 1.0, T3, li, 2.0), "2K + DK");
-        HIPCHK(gemm(cnt, T3, li, R0, li, T2, li, 1.0, T4, li, 1.0), "+ KD");
-        HIPCHK(gemm(cnt, R0, li, R0, li, T1, li, 1.0, R0, li, 2.0), "2D + D^2");
-        HIPCHK(axpby(cnt, T2, li, T3, li, 1.0), "K");
-        HIPCHK(axpby(cnt, T1, li, R0, li, 1.0), "R");
+      const int32_t* sq = ip(BL.sq) + w.sq_base;
+      {
+        StageTimer t(c, 5, s);
+        // backward chain: M_n = P_loc,n Z, Z <- Z S_n = Z + Z D_n (normal orientation)
+        void* Z[2] = {env, X};
+        for (int k = C - 1; k >= 0; --k) {
+          const int a0 = q.chain_off[w.koff + k], cnt = q.chain_off[w.koff + k + 1] - a0;
+          if (cnt == 0) continue;
+          const int32_t* sl = ip(o_cs) + a0;
+          const int32_t* chn = ip(o_cc) + a0;
+          HIPCHK(gemm(cnt, Pl, sl, Z[0], chn, Em, sl, 1.0), "M");
+          HIPCHK(gemm(cnt, Z[0], chn, S, sl, Z[1], chn, 1.0, Z[0], chn, 1.0), "Z");
+          HIPCHK(axpby(cnt, Z[1], chn, Z[0], chn, 1.0), "Z sync");
+        }
+        // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
+        HIPCHK(axpby(Wn, Em, nullptr, Em, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, ms_all + 2 * (size_t)w.s0),
+               "E scale");
+        HIPCHK(gemm(Wn, A, nullptr, Em, nullptr, T1, nullptr, 1.0), "AE");
+        HIPCHK(gemm(Wn, Em, nullptr, A, nullptr, T1, nullptr, 1.0, T1, nullptr, 1.0), "L2");       // T1 = L2
+        HIPCHK(axpby(Wn, A2, nullptr, T2, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");      // T2 = W
+        HIPCHK(axpby(Wn, T1, nullptr, T3, nullptr, b3[3]), "LW");                                    // T3 = L_W
+        HIPCHK(gemm(Wn, A, nullptr, T3, nullptr, T4, nullptr, 1.0), "A LW");
+        HIPCHK(gemm(Wn, Em, nullptr, T2, nullptr, T4, nullptr, 1.0, T4, nullptr, 1.0), "LU");       // T4 = L_U
+        HIPCHK(axpby(Wn, T1, nullptr, T3, nullptr, b3[2], T4, nullptr, -1.0), "LQ");                 // T3 = L_Q
+        HIPCHK(axpby(Wn, T1, nullptr, T2, nullptr, b3[2], T4, nullptr, 1.0), "LP");                  // T2 = L_P
+        // r = I + D (R0 = D), Q^{-1} = I + X_Q (Qi = X_Q)
+        HIPCHK(gemm2(Wn, T3, R0, T1, -1.0, T2, 1.0, T3, -1.0), "X");   // T1 = L_P - L_Q - L_Q D
+        HIPCHK(gemm(Wn, Qi, nullptr, T1, nullptr, T3, nullptr, 1.0, T1, nullptr, 1.0), "K");   // T3 = K
+        // squaring recurrence K <- R K + K R = 2 K + D K + K D, D <- 2 D + D D for the
+        // slices with s > k
+        for (int k = 0; k < w.smax; ++k) {
+          const int cnt = w.sq_off[k + 1] - w.sq_off[k];
+          const int32_t* li = sq + w.sq_off[k];
+          if (!cnt) continue;
+          HIPCHK(gemm(cnt, R0, li, T3, li, T4, li, 1.0, T3, li, 2.0), "2K + DK");
+          HIPCHK(gemm(cnt, T3, li, R0, li, T2, li, 1.0, T4, li, 1.0), "+ KD");
+          HIPCHK(gemm(cnt, R0, li, R0, li, T1, li, 1.0, R0, li, 2.0), "2D + D^2");
+          HIPCHK(axpby(cnt, T2, li, T3, li, 1.0), "K");
+          HIPCHK(axpby(cnt, T1, li, R0, li, 1.0), "R");
+        }
       }
-    }
-    {
-      StageTimer t(c, 6, s);
-      BigTraceArgs ta{};
-      ta.n = n; ta.n_slices = Ns; ta.nb = c->nb; ta.first_slice = 0; ta.trans_basis = 1;
-      ta.K = T3; ta.basis = c->basis32; ta.part = (double*)at(o_part); ta.gtrace = (double*)at(L.gtrace);
-      HIPCHK(launch_btraces(32, ta, s), "traces");
+      {
+        StageTimer t(c, 6, s);
+        BigTraceArgs ta{};
+        ta.n = n; ta.n_slices = Wn; ta.nb = c->nb; ta.first_slice = w.s0; ta.trans_basis = 1;
+        ta.K = T3; ta.basis = c->basis32; ta.part = (double*)at(BL.part); ta.gtrace = (double*)at(BL.gtrace);
+        HIPCHK(launch_btraces(32, ta, s), "traces");
+      }
     }
   }
   if (grad || grouped) {
     GradArgs ga{};
-    ga.prec = 32; ga.gtrace = grad ? (const double*)at(L.gtrace) : nullptr;
+    ga.prec = 32; ga.gtrace = grad ? (const double*)at(BL.gtrace) : nullptr;
     ga.amps = b->amps; ga.item_amp_offset = (const int64_t*)at(L.amp_off); ga.items = items;
     ga.n_items = (int)p.items.size(); ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
     ga.n_ctrl = c->nc; ga.n_static = c->ns; ga.order = c->order; ga.hold_foh = c->hold == LMAG_FOH;
@@ -1092,10 +1224,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     StageTimer t(c, 7, s);
     HIPCHK(launch_grad(ga, grad ? p.max_slices : 1, s), "grad");
   }
-  c->plan_info[0] = Ns; c->plan_info[1] = Lc; c->plan_info[2] = C; c->plan_info[3] = 0;
-  c->plan_info[4] = (int64_t)L.total;
-  c->plan_recompute = false;
-  c->plan_waves = 1;
+  finish_plan();
   return LMAG_OK;
 }
 
@@ -1395,6 +1524,10 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     }
     HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
     HIPCHK(hipDeviceSynchronize(), "set_system sync");
+    if (big) {   // the block-tiled path (FP32) reads only the FP32 copy
+      (void)hipFree(c->basis64);
+      c->basis64 = nullptr;
+    }
     if (!big) {
       std::vector<double> hb((size_t)nb * TILE * 2);
       HIPCHK(hipMemcpy(hb.data(), c->basis64, hb.size() * 8, hipMemcpyDeviceToHost), "basis copy");

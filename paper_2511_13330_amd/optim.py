@@ -6,8 +6,6 @@ synchronisation."""
 import numpy as np
 import torch
 
-from .synth_free import box_uniform
-
 
 def refine(system, amps, n_slices, dt, U_target, max_steps=50, lr=None, amax=None,
            target=0.999, static_coef=None, ctrl_scale=None, target_of_item=None,
@@ -46,5 +44,5 @@ def refine(system, amps, n_slices, dt, U_target, max_steps=50, lr=None, amax=Non
 
 def cold_start(n_items, n_slices, n_ctrl, amax, seed, device="cuda", dtype=torch.float32):
     """Uniform random amplitudes in [0, amax] (the plain method's start)."""
-    a = box_uniform(seed, (n_items * n_slices, n_ctrl), 0.0, amax)
+    a = np.random.default_rng(seed).uniform(0.0, amax, (n_items * n_slices, n_ctrl))
     return torch.tensor(a, dtype=dtype, device=device).contiguous()

@@ -37,3 +37,18 @@ def test_flops_from_histogram():
     h[1, 3] = 2    # m = 3, s = 3
     f = bench.flops_from_hist(h, bench.forward_flops_per_slice)
     assert f == 10 * 3 * M + 2 * (2 + 3 + 4.0 / 3.0 + 1) * M
+
+
+def test_pooled_cpu_baseline_is_the_oracle_adjoint():
+    """The benchmark's CPU baseline runs the oracle's per-slice steps in a
+    process pool; its F and gradient are those of oracle.grad_adjoint."""
+    import oracle
+    import synth
+    cfg = synth.small_case(77, n_slices=37)
+    cb, F, g = bench.cpu_baseline(cfg)
+    amps = cfg["amps"].astype(np.float32).astype(np.float64)
+    F_ref, g_ref = oracle.grad_adjoint(oracle.System.from_cfg(cfg), amps, cfg["dt"], 2, "foh",
+                                       cfg["U_target"])
+    assert abs(F - F_ref) < 1e-14
+    assert np.allclose(g, g_ref, rtol=1e-12, atol=1e-16)
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0

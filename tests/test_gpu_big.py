@@ -191,3 +191,55 @@ def test_six_spin_dissipative_sampled_columns():
     cols[0] = 0                                   # |0><0|: populations
     ref = hb.propagator_columns(oracle_system(cfg), amps, cfg["dt"], 2, "foh", list(cols))
     assert rel(U[:, cols], ref) <= 2e-5
+
+
+def test_four_spin_recompute_bitwise_equal_to_stored():
+    """Under a workspace budget too small for every slice's matrices, the
+    block-tiled adjoint runs in slice windows and re-runs each window's
+    forward instead of storing it: propagator, F and gradient are bitwise those
+    of the stored path (same chunk length), with squarings in some slices."""
+    cfg = synth.small_case(74, n_spins=4, n_slices=30, dt=2e-3)
+    amps = rounded(cfg["amps"], "f32")
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    b = np.asarray(cfg["B"])[None, :]
+    out = {}
+    for name, budget in (("stored", 0), ("recompute", 100 << 20)):
+        sysm = lib_system(cfg, "f32", 2, "foh", chunk=4, workspace_bytes_max=budget)
+        F, g = sysm.fidelity_and_grad(a, [30], cfg["dt"], cfg["U_target"], static_coef=b)
+        plan = sysm.last_plan()
+        hist = sysm.selection_histogram()
+        U = sysm.propagate(a, [30], cfg["dt"], static_coef=b)
+        out[name] = (F, g, U, plan, hist)
+    Fs, gs, Us, ps, hs = out["stored"]
+    Fr, gr, Ur, pr, hr = out["recompute"]
+    assert ps["recompute"] == 0 and ps["waves"] == 1
+    assert pr["recompute"] == 1 and pr["waves"] > 1 and pr["workspace_bytes"] <= 100 << 20
+    assert hs[1, 0] > 0 and hs[1, 1:].sum() > 0        # slices with and without squarings
+    assert torch.equal(Fs, Fr) and torch.equal(gs, gr) and torch.equal(Us, Ur)
+    osys = oracle_system(cfg)
+    F_ref, g_ref = oracle.grad_adjoint(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    assert abs(Fs.item() - F_ref) < 1e-6
+    assert rel(gs.cpu().numpy().astype(float), g_ref) < 1e-3
+
+
+def test_six_spin_full_pulse_under_64_GB():
+    """The 6-spin configuration (4096 x 4096 superoperator, 128 slices of
+    1 ns, five controls) without dissipation, forward and adjoint under a
+    64 GB workspace budget (storing every slice's matrices would need about
+    190 GB): the adjoint recomputes the forward window by window. Propagator,
+    F and all 640 gradient coordinates against the Hilbert-space reduction."""
+    cfg = synth.config3_six()
+    amps = rounded(cfg["amps"], "f32")
+    sysm = lib_system(cfg, "f32", 2, "foh", dissipative=False, workspace_bytes_max=64 << 30)
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    b = np.asarray(cfg["B"])[None, :]
+    F, g = sysm.fidelity_and_grad(a, [128], cfg["dt"], cfg["U_target"], static_coef=b)
+    plan = sysm.last_plan()
+    assert plan["recompute"] == 1 and plan["workspace_bytes"] <= 64 << 30
+    hs = hb.HilbertSystem.from_cfg(cfg)
+    F_ref, g_ref = hb.grad(hs, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    assert abs(F.item() - F_ref) <= 1e-6
+    assert rel(g.cpu().numpy().astype(float), g_ref) <= 1e-3
+    U = sysm.propagate(a, [128], cfg["dt"], static_coef=b).cpu().numpy()[0].astype(complex)
+    V = hb.unitary(hs, amps, cfg["dt"], 2, "foh")
+    assert rel(U, hb.superop(V)) <= 1e-4
