@@ -284,11 +284,15 @@ def large_system(args):
     cfg = synth.config3_four() if args.workload == "four_spin" else synth.config3_six()
     t0 = time.perf_counter()
     sysm = spin_chain_system(cfg["n_spins"], cfg["T1"], cfg["T2"], precision="f32",
-                             magnus_order=2, hold="foh", chunk_slices=args.chunk)
+                             magnus_order=2, hold="foh", chunk_slices=args.chunk,
+                             workspace_bytes_max=int(args.workspace_gb * (1 << 30)))
     t_setup = time.perf_counter() - t0
     N = cfg["n_slices"]
     a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
     b = np.asarray(cfg["B"])[None, :]
+    tuned = None
+    if args.autotune and args.chunk == 0:
+        tuned = sysm.autotune(a, [N], cfg["dt"], cfg["U_target"], static_coef=b, reps=1)
     F, g = sysm.fidelity_and_grad(a, [N], cfg["dt"], cfg["U_target"], static_coef=b)  # warm-up
     torch.cuda.synchronize()
     steps = max(1, min(args.steps, 3))
@@ -309,6 +313,9 @@ def large_system(args):
             "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded config-3 draws)",
             "config": {"workload": f"{cfg['n_spins']} spins, superoperator {n}x{n}, {N} slices of "
                                    f"{cfg['dt'] * 1e3:g} ns, FOH 2nd order, FP32 fwd+grad",
+                       "workspace_budget_gib": args.workspace_gb or None,
+                       "autotune": {"chunk": tuned[0], "product_kernel": tuned[1], "ms": tuned[2]}
+                       if tuned else None,
                        "plan": sysm.last_plan()},
             "seconds_per_eval": dt, "seconds_set_system": t_setup,
             "tflops_algorithmic": flops / dt / 1e12,
@@ -325,6 +332,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="pulses per step")
     ap.add_argument("--chunk", type=int, default=0, help="slices per work unit (0 = auto)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--workspace-gb", type=float, default=0.0,
+                    help="workspace budget of the large-system workloads in GiB (0 = 85 %% of free "
+                         "device memory); beyond it the adjoint recomputes the forward")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
     ap.add_argument("--autotune", action="store_true",
                     help="tune chunk length and inverse variant before the timed steps")

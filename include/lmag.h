@@ -211,9 +211,15 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
                                         const int32_t *target_of_item, double *score_out,
                                         void *grad_out, void *hip_stream);
 
-/* Autotuner of the persistent slice kernels: times lmag_fidelity_and_grad on
- * this batch (reps timed calls after one warm-up, HIP events on the stream) for
- * every candidate chunk length (slices per work unit) and the inverse variants
+/* Autotuner: times lmag_fidelity_and_grad on this batch (reps timed calls
+ * after one warm-up, HIP events on the stream) over a set of candidates.
+ * Block-tiled systems (n > 64): the product kernel -- 0: one 64 x 64 output
+ * tile per workgroup with the B tile in registers, 16x16x4 MFMA; 1: a 32 x 32
+ * quadrant per wave with both operand tiles in LDS and the next k-step's tiles
+ * loaded during the products, 16x16x4 MFMA; 2: as 1 with the 32x32x2 MFMA --
+ * at the automatic chunk length, half and twice it. 64 x 64 systems: the
+ * persistent slice kernels, for every candidate chunk length (slices per work
+ * unit) and the inverse variants
  * of the Pade step (0: per slice the cheapest whose error bound holds -- in
  * single precision r_2 itself by its power series truncated at degree 4
  * (Pade-2) or 1/q_3 by its truncated power series (Pade-3), else the MFMA
@@ -221,9 +227,11 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * where its bound allows, else Gauss-Jordan; 1 and 2 always form
  * r_m = q_m^{-1} p_m). The fastest pair is kept
  * for calls with chunk_slices = 0 whose precision, order, d and total slice
- * count (power-of-two bucket) match, and appended as one JSON line to the file
- * named by the environment variable LMAG_TUNE_CACHE if it is set.
- * best_out: HOST int32 [2] (chunk, inverse) or NULL; best_ms_out: HOST or NULL.
+ * count (power-of-two bucket) match, and appended as one JSON line
+ * {"key", "chunk", "variant", "ms"} to the file named by the environment
+ * variable LMAG_TUNE_CACHE if it is set.
+ * best_out: HOST int32 [2] (chunk, variant: inverse variant or product kernel)
+ * or NULL; best_ms_out: HOST or NULL.
  * Blocks. Outputs of the timed calls go to internal buffers. */
 lmag_status lmag_autotune(lmag_ctx *ctx, const lmag_batch *batch, const void *U_target,
                           int n_targets, const int32_t *target_of_item, int reps,

@@ -12,6 +12,7 @@
 #include "pade.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace lmag {
 
@@ -77,10 +78,160 @@ __global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
   rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
 }
 
+// Quadrant variants (single precision, no transposes): wave w of the
+// workgroup owns the 32 x 32 quadrant (w >> 1, w & 1) of the 64 x 64 output
+// tile. Both operand tiles of a k-step sit in LDS; every thread loads its share
+// of the next k-step's tiles into registers (coalesced 16-byte loads) before
+// the current products run, so the global loads drain under the MFMAs.
+// SHAPE 16: v_mfma_f32_16x16x4f32 on 2 x 2 blocks of 16 x 16 per quadrant,
+//   A operand lane (g, c) = (l / 16, l % 16) holds A[c][k = g], output row of
+//   register r is 4 g + r, column c.
+// SHAPE 32: v_mfma_f32_32x32x2f32 on the whole quadrant, A operand lane l
+//   holds A[l % 32][k = l / 32], B operand B[k = l / 32][l % 32], output row of
+//   register r is 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+// Complex products use the 3M form of tile.hpp.
+struct QuadShared {
+  cpx<float> a[64 * PITCH];
+  cpx<float> b[64 * PITCH];
+};
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void quad_fetch(f4 (&r)[8], const cpx<float>* M, size_t ld, int tid) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = tid + 256 * i, row = idx >> 5, c2 = idx & 31;
+    r[i] = *reinterpret_cast<const f4*>(M + (size_t)row * ld + 2 * c2);
+  }
+}
+
+__device__ __forceinline__ void quad_stage(const f4 (&r)[8], cpx<float>* S, int tid) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = tid + 256 * i, row = idx >> 5, c2 = idx & 31;
+    S[row * PITCH + 2 * c2] = cpx<float>{r[i].x, r[i].y};
+    S[row * PITCH + 2 * c2 + 1] = cpx<float>{r[i].z, r[i].w};
+  }
+}
+
+template <int SHAPE>
+__global__ void __launch_bounds__(WG) k_bgemm_q(BigGemmArgs g) {
+  __shared__ QuadShared sh;
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  const int b = blockIdx.y;
+  const int ti = blockIdx.x / Tn, tj = blockIdx.x % Tn;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int qi = w >> 1, qj = w & 1;
+  cpx<float>* C = const_cast<cpx<float>*>(mat<float>(g.C, g.Ci, b, nn));
+  const cpx<float>* D = g.D ? mat<float>(g.D, g.Di, b, nn) : nullptr;
+  const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
+  if (!active) {
+    const cpx<float>* src = D ? D : mat<float>(g.A, g.Ai, b, nn);
+    RT<float> X;
+    rt_load<float, false>(X, src + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    rt_store<float, false>(X, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    return;
+  }
+  const cpx<float>* A = mat<float>(g.A, g.Ai, b, nn) + (size_t)ti * 64 * g.n;   // row block ti
+  const cpx<float>* B = mat<float>(g.B, g.Bi, b, nn) + tj * 64;                 // column block tj
+  constexpr int NB = SHAPE == 16 ? 2 : 1;      // MFMA blocks per quadrant side
+  constexpr int NACC = SHAPE == 16 ? 4 : 16;   // accumulator registers per block
+  typedef typename std::conditional<SHAPE == 16, f4, f16v>::type acc_t;
+  acc_t k1[NB][NB], cr[NB][NB], ci[NB][NB];
+#pragma unroll
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+#pragma unroll
+      for (int r = 0; r < NACC; ++r) { k1[x][y][r] = 0.f; cr[x][y][r] = 0.f; ci[x][y][r] = 0.f; }
+  f4 ra[8], rb[8];
+  quad_fetch(ra, A, g.n, tid);
+  quad_fetch(rb, B, g.n, tid);
+  for (int tk = 0; tk < Tn; ++tk) {
+    __syncthreads();
+    quad_stage(ra, sh.a, tid);
+    quad_stage(rb, sh.b, tid);
+    __syncthreads();
+    if (tk + 1 < Tn) {
+      quad_fetch(ra, A + (tk + 1) * 64, g.n, tid);
+      quad_fetch(rb, B + (size_t)(tk + 1) * 64 * g.n, g.n, tid);
+    }
+    if constexpr (SHAPE == 16) {
+      const int gg = l >> 4, c = l & 15;
+#pragma unroll 4
+      for (int kk = 0; kk < 16; ++kk) {
+        const int k = 4 * kk + gg;
+        cpx<float> av[NB], bv[NB];
+#pragma unroll
+        for (int x = 0; x < NB; ++x) av[x] = sh.a[(qi * 32 + x * 16 + c) * PITCH + k];
+#pragma unroll
+        for (int y = 0; y < NB; ++y) bv[y] = sh.b[k * PITCH + qj * 32 + y * 16 + c];
+#pragma unroll
+        for (int x = 0; x < NB; ++x) {
+          const float asum = av[x].re + av[x].im;
+#pragma unroll
+          for (int y = 0; y < NB; ++y) {
+            const float nsum = -(bv[y].re + bv[y].im), diff = bv[y].im - bv[y].re;
+            k1[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(asum, bv[y].re, k1[x][y], 0, 0, 0);
+            cr[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x].im, nsum, cr[x][y], 0, 0, 0);
+            ci[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[x].re, diff, ci[x][y], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      const int h = l >> 5, c = l & 31;
+#pragma unroll 4
+      for (int kk = 0; kk < 32; ++kk) {
+        const int k = 2 * kk + h;
+        const cpx<float> av = sh.a[(qi * 32 + c) * PITCH + k];
+        const cpx<float> bv = sh.b[k * PITCH + qj * 32 + c];
+        const float nsum = -(bv.re + bv.im), diff = bv.im - bv.re;
+        k1[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re + av.im, bv.re, k1[0][0], 0, 0, 0);
+        cr[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.im, nsum, cr[0][0], 0, 0, 0);
+        ci[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.re, diff, ci[0][0], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue: C = alpha (K1 + Cr, K1 + Ci) + beta D + beta2 D2 + gamma I
+  const cpx<float>* D2 = g.D2 ? mat<float>(g.D2, g.D2i, b, nn) : nullptr;
+  const float al = (float)g.alpha, be = (float)g.beta, be2 = (float)g.beta2, ga = (float)g.gamma;
+#pragma unroll
+  for (int x = 0; x < NB; ++x)
+#pragma unroll
+    for (int y = 0; y < NB; ++y)
+#pragma unroll
+      for (int r = 0; r < NACC; ++r) {
+        int row, col;
+        if constexpr (SHAPE == 16) {
+          row = qi * 32 + x * 16 + 4 * (l >> 4) + r;
+          col = qj * 32 + y * 16 + (l & 15);
+        } else {
+          row = qi * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+          col = qj * 32 + (l & 31);
+        }
+        const size_t e = (size_t)(ti * 64 + row) * g.n + tj * 64 + col;
+        cpx<float> v{al * (k1[x][y][r] + cr[x][y][r]), al * (k1[x][y][r] + ci[x][y][r])};
+        if (D && g.beta != 0.0) { const cpx<float> d = D[e]; v.re += be * d.re; v.im += be * d.im; }
+        if (D2 && g.beta2 != 0.0) { const cpx<float> d = D2[e]; v.re += be2 * d.re; v.im += be2 * d.im; }
+        if (g.gamma != 0.0 && ti == tj && row == col) v.re += ga;
+        C[e] = v;
+      }
+}
+
 hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s) {
   if (g.batch <= 0) return hipSuccess;
   const int Tn = g.n / 64;
   const dim3 grid(Tn * Tn, g.batch);
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 1) {
+    hipLaunchKernelGGL(k_bgemm_q<16>, grid, dim3(WG), 0, s, g);
+    return hipGetLastError();
+  }
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 2) {
+    hipLaunchKernelGGL(k_bgemm_q<32>, grid, dim3(WG), 0, s, g);
+    return hipGetLastError();
+  }
 #define LMAG_BG(T, a, b) hipLaunchKernelGGL((k_bgemm<T, a, b>), grid, dim3(WG), 0, s, g)
   if (prec == 32) {
     if (g.transA && g.transB) LMAG_BG(float, true, true);

@@ -98,8 +98,10 @@ struct lmag_ctx {
   int64_t plan_info[5] = {0, 0, 0, 0, 0};
   bool plan_recompute = false;
   int plan_waves = 0;
-  // tuning: chosen (chunk, inverse variant) per key; inv_variant 0 auto, 1 Gauss-Jordan
+  // tuning: chosen (chunk, variant) per key. 64 x 64 path: inverse variant (0 auto,
+  // 1 Gauss-Jordan, 2 Neumann); block-tiled path: product kernel (BigGemmArgs::variant)
   int inv_variant = 0;
+  int big_variant = -1;          // forced product kernel of the block-tiled path (-1: tuned or default)
   std::vector<std::pair<std::string, std::pair<int, int>>> tuned;
   bool clk_on = false;
   long long* clk_dev = nullptr;
@@ -716,6 +718,14 @@ bool build_sparse(lmag_ctx* c, const std::vector<double>& hb, int nb, int prec) 
   return true;
 }
 
+// Chunk length of the block-tiled path: enough independent chunks (about 2048
+// output tiles per chain step) to fill the device.
+int big_auto_chunk(const lmag_ctx* c, long long total) {
+  const long long Tn = c->n / 64;
+  const long long want_chunks = std::max<long long>(1, 2048 / (Tn * Tn));
+  return (int)std::max<long long>(1, (total + want_chunks - 1) / want_chunks);
+}
+
 // Layout of a block-tiled call: metadata and index lists, per-slice scalars,
 // then the matrices. `window` is the number of slices whose per-slice matrices
 // are held at once (all of them when the adjoint stores them).
@@ -769,12 +779,13 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   for (int i = 0; i < b->n_items; ++i) total += b->n_slices[i];
   const int nt = fidelity ? n_targets : 0;
   const size_t budget = device_budget(c);
-  // chunk length: enough independent chunks to fill the device in the chains
+  // chunk length: enough independent chunks to fill the device in the chains;
+  // product kernel: forced, else autotuned for this size, else the default
   int C_auto = c->chunk;
-  if (C_auto <= 0) {
-    const long long want_chunks = std::max<long long>(1, 2048 / ((long long)Tn * Tn));
-    C_auto = (int)std::max<long long>(1, (total + want_chunks - 1) / want_chunks);
-  }
+  int variant = c->big_variant >= 0 ? c->big_variant : kBigGemmDefault;
+  const std::pair<int, int>* tuned = c->chunk <= 0 && c->big_variant < 0 ? tuned_for(c, total) : nullptr;
+  if (tuned) { C_auto = tuned->first; variant = tuned->second; }
+  if (C_auto <= 0) C_auto = big_auto_chunk(c, total);
   // metadata estimate (items, chunks, per-slice maps, index lists): bounded by
   // a few words per slice and chunk; the exact size is taken after planning
   auto plan_for = [&](int C, Plan& p) {
@@ -942,7 +953,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     BigGemmArgs g{};
     g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
     g.D = Dp; g.Di = Di; g.alpha = alpha; g.beta = beta; g.gamma = gamma; g.transA = tA; g.transB = tB;
-    g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh;
+    g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh; g.variant = variant;
     return launch_bgemm(32, g, s);
   };
   // C = alpha A B + beta D + beta2 D2 with index maps (null: the batch index)
@@ -954,7 +965,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
     g.D = Dp; g.Di = Di; g.D2 = D2p; g.D2i = D2i;
     g.alpha = alpha; g.beta = beta; g.beta2 = beta2;
-    g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh;
+    g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh; g.variant = variant;
     return launch_bgemm(32, g, s);
   };
   auto gemm2 = [&](int batch, const void* Ap, const void* Bp, const void* Cp, double alpha,
@@ -1687,12 +1698,21 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
       if (Fd) (void)hipFree(Fd);
       return c->fail(LMAG_E_NOMEM, "autotune output buffers");
     }
-    const int saved_chunk = c->chunk, saved_inv = c->inv_variant;
+    const int saved_chunk = c->chunk, saved_inv = c->inv_variant, saved_big = c->big_variant;
+    const bool big = c->n > 64;
     const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
     std::vector<int> chunks;
-    for (int C : {2, 4, 8, 16, 32, 64, 128, 256})
-      if (C <= std::max<long long>(2, 4 * per) && C >= std::min<long long>(per / 4, 64)) chunks.push_back(C);
-    if (chunks.empty()) chunks.push_back(auto_chunk(c, total, false));
+    if (big) {
+      // block-tiled path: the product kernel (tile ownership and MFMA shape) at
+      // the automatic chunk length and at half and twice it
+      const int C0 = big_auto_chunk(c, total);
+      for (int C : {C0, std::max(1, C0 / 2), 2 * C0})
+        if (std::find(chunks.begin(), chunks.end(), C) == chunks.end()) chunks.push_back(C);
+    } else {
+      for (int C : {2, 4, 8, 16, 32, 64, 128, 256})
+        if (C <= std::max<long long>(2, 4 * per) && C >= std::min<long long>(per / 4, 64)) chunks.push_back(C);
+      if (chunks.empty()) chunks.push_back(auto_chunk(c, total, false));
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -1701,7 +1721,8 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     for (int inv : {0, 1, 2}) {
       for (int C : chunks) {
         c->chunk = C;
-        c->inv_variant = inv;
+        if (big) c->big_variant = inv;
+        else c->inv_variant = inv;
         st = run_waves(c, b, target_of_item, n_targets, true, true, U_target, (double*)Fd, Gd,
                        nullptr, s);   // warm-up (also sizes the workspace)
         if (st != LMAG_OK) break;
@@ -1728,6 +1749,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     (void)hipFree(Gd);
     c->chunk = saved_chunk;
     c->inv_variant = saved_inv;
+    c->big_variant = saved_big;
     if (st != LMAG_OK) return st;
     const std::string k = tune_key(c, total);
     bool found = false;
@@ -1736,7 +1758,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     if (!found) c->tuned.push_back({k, {bestC, bestInv}});
     if (const char* path = std::getenv("LMAG_TUNE_CACHE")) {
       if (FILE* f = std::fopen(path, "a")) {
-        std::fprintf(f, "{\"key\": \"%s\", \"chunk\": %d, \"inverse\": %d, \"ms\": %.4f}\n",
+        std::fprintf(f, "{\"key\": \"%s\", \"chunk\": %d, \"variant\": %d, \"ms\": %.4f}\n",
                      k.c_str(), bestC, bestInv, best);
         std::fclose(f);
       }
@@ -1761,7 +1783,8 @@ lmag_status lmag_load_tuning(lmag_ctx* c, const char* path) {
   while (std::fgets(line, sizeof(line), f)) {
     char key[128];
     int C = 0, inv = 0;
-    if (std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"inverse\": %d", key, &C, &inv) == 3 &&
+    if ((std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"variant\": %d", key, &C, &inv) == 3 ||
+         std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"inverse\": %d", key, &C, &inv) == 3) &&
         C > 0 && inv >= 0 && inv <= 2) {
       bool found = false;
       for (auto& t : c->tuned)

@@ -243,3 +243,50 @@ def test_six_spin_full_pulse_under_64_GB():
     U = sysm.propagate(a, [128], cfg["dt"], static_coef=b).cpu().numpy()[0].astype(complex)
     V = hb.unitary(hs, amps, cfg["dt"], 2, "foh")
     assert rel(U, hb.superop(V)) <= 1e-4
+
+
+def _tuning_line(path, d, total, chunk, variant):
+    b = int(np.floor(np.log2(total)))
+    with open(path, "w") as f:
+        f.write('{"key": "p32_o2_d%d_s%d", "chunk": %d, "variant": %d, "ms": 0.0}\n'
+                % (d, b, chunk, variant))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_four_spin_product_kernels_match_oracle(variant, tmp_path):
+    """Each product kernel of the block-tiled path (register-B tiles with the
+    16x16x4 MFMA; a quadrant per wave with 16x16x4; a quadrant per wave with
+    32x32x2), selected through a tuning line: propagator, F and gradient
+    against the oracle, with squarings in some slices."""
+    cfg = synth.small_case(75, n_spins=4, n_slices=14, dt=2e-3)
+    amps = rounded(cfg["amps"], "f32")
+    sysm = lib_system(cfg, "f32", 2, "foh")
+    path = tmp_path / "tune.jsonl"
+    _tuning_line(path, 16, 14, 4, variant)
+    sysm.load_tuning(str(path))
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    b = np.asarray(cfg["B"])[None, :]
+    U = sysm.propagate(a, [14], cfg["dt"], static_coef=b).cpu().numpy()[0].astype(complex)
+    F, g = sysm.fidelity_and_grad(a, [14], cfg["dt"], cfg["U_target"], static_coef=b)
+    assert sysm.last_plan()["chunk_slices"] == 4
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    assert rel(U, U_ref) < 2e-5
+    F_ref, g_ref = oracle.grad_adjoint(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    assert abs(F.item() - F_ref) < 1e-6
+    assert rel(g.cpu().numpy().astype(float), g_ref) < 1e-3
+
+
+def test_block_tiled_autotune_picks_a_kernel():
+    cfg = synth.small_case(76, n_spins=4, n_slices=256, dt=2.5e-4)
+    amps = rounded(cfg["amps"], "f32")
+    sysm = lib_system(cfg, "f32", 2, "foh")
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    b = np.asarray(cfg["B"])[None, :]
+    chunk, variant, ms = sysm.autotune(a, [256], cfg["dt"], cfg["U_target"], static_coef=b, reps=1)
+    assert variant in (0, 1, 2) and chunk >= 1 and ms > 0
+    F, g = sysm.fidelity_and_grad(a, [256], cfg["dt"], cfg["U_target"], static_coef=b)
+    assert sysm.last_plan()["chunk_slices"] == chunk
+    F_ref, _ = oracle.fidelity(oracle.propagate(oracle_system(cfg).omegas(amps, cfg["dt"], 2, "foh")),
+                               cfg["U_target"])
+    assert abs(F.item() - F_ref) < 1e-6
