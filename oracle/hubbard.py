@@ -86,7 +86,7 @@ def static_terms(n_dots):
     n, _ = number_ops(n_dots)
     eye = np.eye(4 ** n_dots, dtype=complex)
     onsite = sum(0.5 * ni @ (ni - eye) for ni in n)
-    coulomb = sum(n[i] @ n[j] for i, j in pairs(n_dots))
+    coulomb = sum((n[i] @ n[j] for i, j in pairs(n_dots)), np.zeros_like(eye))
     return [onsite] + list(n) + [coulomb]
 
 

@@ -7,6 +7,7 @@ this package is its Python binding. Build with
 from ._lib import LmagError, lib, LIB_PATH
 from .system import System, PulseFidelity, spin_chain_system
 from .spin import chain_operators
+from .hubbard import hubbard_operators, hubbard_system
 
 __all__ = ["LmagError", "lib", "LIB_PATH", "System", "PulseFidelity",
-           "spin_chain_system", "chain_operators"]
+           "spin_chain_system", "chain_operators", "hubbard_operators", "hubbard_system"]

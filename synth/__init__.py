@@ -8,8 +8,8 @@ itself from the scalars returned here.
 """
 from .configs import (A_MAX, B_RANGE, T1_US, T2_US, haar_unitary, config0, config1_batch,
                       config1, config2, config3_four, config3_six, config4_targets,
-                      small_case)
+                      small_case, hubbard3)
 
 __all__ = ["A_MAX", "B_RANGE", "T1_US", "T2_US", "haar_unitary", "config0", "config1_batch",
            "config1", "config2", "config3_four", "config3_six",
-           "config4_targets", "small_case"]
+           "config4_targets", "small_case", "hubbard3"]

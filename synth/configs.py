@@ -90,6 +90,25 @@ def config3_six(seed=3):
     return cfg
 
 
+def hubbard3(seed=5, n_slices=128, dt=5e-4):
+    """Hubbard model of three dots in a line (Eq. 1; 4 states per dot, Hilbert
+    dimension 64, superoperator 4096 x 4096). The paper gives no parameter
+    values; these are seeded synthetic draws in the units of the spin
+    workloads: U~ ~ U[2pi 40, 2pi 60], V_i ~ U[-2pi 5, 2pi 5], U_C ~ U[2pi 5,
+    2pi 10] (static coefficients, in the order U~, V_1, V_2, V_3, U_C) and
+    hopping amplitudes t_12, t_23 ~ U[0, 2pi 10] per slice (the controls), FOH
+    second order, slices of 0.5 ns, FP32, T1 = 1 ms and T2 = 2 us per dot."""
+    rng = np.random.default_rng(seed)
+    cfg = dict(n_dots=3, d=64, n_ctrl=2, n_slices=n_slices, dt=dt, order=2, hold="foh",
+               precision="f32", T1=T1_US, T2=T2_US)
+    cfg["coef"] = np.concatenate([rng.uniform(TWO_PI * 40, TWO_PI * 60, 1),
+                                  rng.uniform(-TWO_PI * 5, TWO_PI * 5, 3),
+                                  rng.uniform(TWO_PI * 5, TWO_PI * 10, 1)])
+    cfg["amps"] = rng.uniform(0.0, TWO_PI * 10, (n_slices, 2))
+    cfg["U_target"] = haar_unitary(rng, 64)
+    return cfg
+
+
 def config4_targets(seed=4, n=4096, n_slices=256, modes=4):
     """Learned-proposal workload: per target a nominal field vector, quasi-static
     noise scales (network inputs only) and a smooth reference pulse: for each
