@@ -20,7 +20,8 @@ import numpy as np
 
 from .model import exchange_terms, zeeman_terms, jump_ops, hamiltonian
 from .liouville import liouvillian, lift_hamiltonian
-from .magnus import node_controls, gl2_nodes, slice_omega, SQ3
+from .magnus import (node_controls, gl2_nodes, slice_omega, SQ3, node_controls3, gl3_nodes,
+                     order6_terms, comm, SQ15)
 from .expm import expm_taylor, frechet_block
 
 
@@ -61,6 +62,8 @@ class System:
 
     def domega(self, amps, n, dt, order, hold):
         """dOmega_n / d u_{m,c} as a dict {(m, c): matrix}."""
+        if order == 6:
+            return self._domega6(amps, n, dt, hold)
         N = amps.shape[0]
         ua, ub = node_controls(amps, n, hold)
         A1, A2 = self.liouv(ua), self.liouv(ub)
@@ -83,6 +86,39 @@ class System:
                     dom = dom + k * ((d2 @ A1 - A1 @ d2) + (A2 @ d1 - d1 @ A2))
                 out[(m, c)] = dom
         return out
+
+
+def _domega6(self, amps, n, dt, hold):
+    """dOmega_n / d u_{m,c} of the sixth-order scheme by the product rule on
+    its commutators, with dB_k / d u_{m,c} = w_k(m) eps_c G_c (G_c the control
+    generator, w_k(m) the weight of row m in the control value at node k)."""
+    N = amps.shape[0]
+    u1, u2, u3 = node_controls3(amps, n, hold)
+    Bs = [self.liouv(u) for u in (u1, u2, u3)]
+    a1, a2, a3, C1, W, C2, X, Y = order6_terms(*Bs, dt)
+    lam = gl3_nodes()
+    if hold == "zoh" or n + 1 >= N:
+        w = {n: (1.0, 1.0, 1.0)}
+    else:
+        w = {n: tuple(1.0 - l for l in lam), n + 1: lam}
+    out = {}
+    for m, wk in w.items():
+        for c in range(self.n_ctrl):
+            G = self.eps[c] * self.ctrl_generator(c)
+            dB1, dB2, dB3 = (wk[k] * G for k in range(3))
+            da1 = dt * dB2
+            da2 = (SQ15 * dt / 3.0) * (dB3 - dB1)
+            da3 = (10.0 * dt / 3.0) * (dB3 - 2.0 * dB2 + dB1)
+            dC1 = comm(da1, a2) + comm(a1, da2)
+            dW = 2.0 * da3 + dC1
+            dC2 = -(comm(da1, W) + comm(a1, dW)) / 60.0
+            dX = -20.0 * da1 - da3 + dC1
+            dY = da2 + dC2
+            out[(m, c)] = da1 + da3 / 12.0 + (comm(dX, Y) + comm(X, dY)) / 240.0
+    return out
+
+
+System._domega6 = _domega6
 
 
 def slice_products(omegas):
