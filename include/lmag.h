@@ -12,6 +12,10 @@
  *   H(t)   = sum_c eps_c u_c(t) H_ctrl[c] + sum_i b_i H_static[i]
  *   Omega_n = int_slice L dt                                     (Eq. 13)
  *             [+ (sqrt(3) h^2 / 12) [L(tau_2), L(tau_1)], second order]
+ *             [order 6: a1 + a3/12 + [-20 a1 - a3 + C1, a2 + C2] / 240 with
+ *              a1 = h B2, a2 = (sqrt(15) h/3)(B3 - B1), a3 = (10 h/3)(B3 - 2 B2 + B1),
+ *              C1 = [a1, a2], C2 = -[a1, 2 a3 + C1] / 60, B_k = L at the three
+ *              Gauss-Legendre nodes of the slice]
  *   S_n    = exp(Omega_n)                                        (Eq. 14)
  *   U      = S_N ... S_1                                         (Eq. 15)
  *   F      = Re Tr(S_T^dag U) / d^2,  S_T = conj(U_T) (x) U_T
@@ -102,7 +106,10 @@ typedef struct {
   int n_jump;                   /* number of jump operators                          */
   const double *L_jump;         /* [n_jump][d][d] complex, rates folded in (op/sqrt T) */
   int precision;                /* LMAG_F32 or LMAG_F64: compute type of the slices  */
-  int magnus_order;             /* 1 (Eq. 13) or 2 (adds the Gauss-Legendre term)    */
+  int magnus_order;             /* 1 (Eq. 13), 2 (adds the two-node Gauss-Legendre    */
+                                /* commutator) or 6 (three Gauss-Legendre nodes,     */
+                                /* nested commutators; FP32, d*d a multiple of 64,   */
+                                /* block-tiled path)                                 */
   int hold;                     /* LMAG_ZOH (u constant per slice) or LMAG_FOH        */
                                 /* (u linear from u_n to u_{n+1}; u_N := u_{N-1})   */
   size_t workspace_bytes_max;   /* 0 = 85 % of free device memory. Gradient calls    */

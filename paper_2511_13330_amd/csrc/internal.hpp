@@ -114,6 +114,8 @@ struct AlphaArgs {
   int n_slices_total;
 };
 hipError_t launch_alpha(const AlphaArgs& a, hipStream_t s);
+// sixth-order slices: coefficient planes [3][n_slices_total][nb] of a1, a2, a3
+hipError_t launch_alpha6(const AlphaArgs& a, hipStream_t s);
 
 struct TargetArgs {
   const double* U;          // [n_targets][d][d] complex128
@@ -194,6 +196,7 @@ struct GradArgs {
   const void* ctrl_scale;
   int n_ctrl, n_static, order, hold_foh, nb;
   double dt, inv_d2;
+  int n_slices_total;       // sixth order: stride of the three trace planes
   void* grad;               // out, like amps (per item) or per group
   const int32_t* group_first_item;  // [n_groups+1] items sorted by group (null = no groups)
   const int32_t* group_items;       // [n_items]
@@ -285,6 +288,7 @@ struct BigFidArgs {
 hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s);
 hipError_t launch_baxpby(int prec, const BigAxpbyArgs& g, hipStream_t s);
 hipError_t launch_bomega(int prec, const BigOmegaArgs& g, hipStream_t s);
+hipError_t launch_bnorm_dense(int prec, const BigOmegaArgs& g, hipStream_t s);
 hipError_t launch_btraces(int prec, const BigTraceArgs& g, hipStream_t s);
 hipError_t launch_bfidelity(int prec, const BigFidArgs& g, hipStream_t s);
 hipError_t launch_blift(const double* H, int d, double* out, hipStream_t s);

@@ -168,6 +168,67 @@ template <typename T> __global__ void k_alpha(AlphaArgs a) {
   }
 }
 
+// Sixth-order slices (three Gauss-Legendre nodes c_k = 1/2 - sqrt(15)/10,
+// 1/2, 1/2 + sqrt(15)/10): the coefficients, on the order-1 basis
+// {L_c, Z_i, D}, of a1 = h B_2, a2 = (sqrt(15) h / 3)(B_3 - B_1) and
+// a3 = (10 h / 3)(B_3 - 2 B_2 + B_1), B_k = L(t_n + c_k h). Output planes
+// alpha[p][slice][nb], p = 0, 1, 2 for a1, a2, a3.
+#define LMAG_SQ15 3.872983346207417
+__device__ __forceinline__ void gl3_fracs(double* lam) {
+  lam[0] = 0.5 - LMAG_SQ15 / 10.0; lam[1] = 0.5; lam[2] = 0.5 + LMAG_SQ15 / 10.0;
+}
+
+template <typename T>
+__device__ void node_values3(const AlphaArgs& a, int it, int k, int N, double (*v)[16]) {
+  const T* amps = (const T*)a.amps + (size_t)(a.item_amp_offset[it] + k) * a.n_ctrl;
+  const T* nxt = (a.hold_foh && k + 1 < N) ? amps + a.n_ctrl : amps;
+  double lam[3];
+  gl3_fracs(lam);
+  for (int c = 0; c < a.n_ctrl; ++c) {
+    const double u0 = (double)amps[c], u1 = (double)nxt[c];
+    const double eps = a.ctrl_scale ? ((const double*)a.ctrl_scale)[(size_t)a.items[it].src * a.n_ctrl + c] : 1.0;
+    for (int q = 0; q < 3; ++q) v[q][c] = eps * (u0 + lam[q] * (u1 - u0));
+  }
+}
+
+template <typename T> __global__ void k_alpha6(AlphaArgs a) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.n_slices_total) return;
+  const int it = a.slice_item[n];
+  const Item item = a.items[it];
+  const int k = n - item.first_slice;
+  double v[3][16];
+  node_values3<T>(a, it, k, item.n_slices, v);
+  const BasisIdx B{a.n_ctrl, a.n_static};
+  const size_t plane = (size_t)a.n_slices_total * a.nb;
+  double* p1 = a.alpha + (size_t)n * a.nb;
+  double* p2 = p1 + plane;
+  double* p3 = p2 + plane;
+  const double h = a.dt, w2 = LMAG_SQ15 * h / 3.0, w3 = 10.0 * h / 3.0;
+  const double* bc = a.static_coef ? (const double*)a.static_coef + (size_t)item.src * a.n_static : nullptr;
+  for (int c = 0; c < a.n_ctrl; ++c) {
+    p1[B.L(c)] = h * v[1][c];
+    p2[B.L(c)] = w2 * (v[2][c] - v[0][c]);
+    p3[B.L(c)] = w3 * (v[2][c] - 2.0 * v[1][c] + v[0][c]);
+  }
+  for (int i = 0; i < a.n_static; ++i) {
+    p1[B.Z(i)] = h * (bc ? bc[i] : 0.0);
+    p2[B.Z(i)] = 0.0;
+    p3[B.Z(i)] = 0.0;
+  }
+  p1[B.D()] = h;
+  p2[B.D()] = 0.0;
+  p3[B.D()] = 0.0;
+}
+
+hipError_t launch_alpha6(const AlphaArgs& a, hipStream_t s) {
+  if (a.n_slices_total <= 0) return hipSuccess;
+  const dim3 g((a.n_slices_total + 127) / 128);
+  if (a.prec == 32) hipLaunchKernelGGL(k_alpha6<float>, g, dim3(128), 0, s, a);
+  else hipLaunchKernelGGL(k_alpha6<double>, g, dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_alpha(const AlphaArgs& a, hipStream_t s) {
   if (a.n_slices_total <= 0) return hipSuccess;
   const dim3 g((a.n_slices_total + 127) / 128);
@@ -482,8 +543,53 @@ __device__ void slice_dA(const GradArgs& g, const AlphaArgs& aa, int it, int k, 
   }
 }
 
+// Sixth order: gtrace holds three planes [p][slice][nb] of Re Tr(G_p B_j) for
+// the cotangents G_p of a1, a2, a3; dF/d(node value k of control c) is
+// sum_p w_pk Re Tr(G_p L_c) with the weights of a1, a2, a3 in B_1, B_2, B_3.
+__device__ void slice_dnodes6(const GradArgs& g, int n, size_t plane, double (*dv)[16]) {
+  const BasisIdx B{g.n_ctrl, g.n_static};
+  const double h = g.dt, w2 = LMAG_SQ15 * h / 3.0, w3 = 10.0 * h / 3.0;
+  const double* G1 = g.gtrace + (size_t)n * g.nb;
+  const double* G2 = G1 + plane;
+  const double* G3 = G2 + plane;
+  for (int c = 0; c < g.n_ctrl; ++c) {
+    const double t1 = G1[B.L(c)], t2 = G2[B.L(c)], t3 = G3[B.L(c)];
+    dv[0][c] = -w2 * t2 + w3 * t3;
+    dv[1][c] = h * t1 - 2.0 * w3 * t3;
+    dv[2][c] = w2 * t2 + w3 * t3;
+  }
+}
+
+template <typename T>
+__device__ void item_grad6(const GradArgs& g, int it, int k, double* out) {
+  const Item item = g.items[it];
+  const int N = item.n_slices;
+  const size_t plane = (size_t)g.n_slices_total * g.nb;
+  double lam[3], dv[3][16];
+  gl3_fracs(lam);
+  slice_dnodes6(g, item.first_slice + k, plane, dv);
+  for (int c = 0; c < g.n_ctrl; ++c) {
+    out[c] = 0.0;
+    for (int q = 0; q < 3; ++q)
+      out[c] += (!g.hold_foh || k + 1 == N) ? dv[q][c] : (1.0 - lam[q]) * dv[q][c];
+  }
+  if (g.hold_foh && k > 0) {
+    slice_dnodes6(g, item.first_slice + k - 1, plane, dv);
+    for (int c = 0; c < g.n_ctrl; ++c)
+      for (int q = 0; q < 3; ++q) out[c] += lam[q] * dv[q][c];
+  }
+  for (int c = 0; c < g.n_ctrl; ++c) {
+    const double eps = g.ctrl_scale ? ((const double*)g.ctrl_scale)[(size_t)item.src * g.n_ctrl + c] : 1.0;
+    out[c] *= eps * g.inv_d2;
+  }
+}
+
 template <typename T>
 __device__ void item_grad(const GradArgs& g, int it, int k, double* out) {
+  if (g.order == 6) {
+    item_grad6<T>(g, it, k, out);
+    return;
+  }
   AlphaArgs aa{};
   aa.amps = g.amps; aa.item_amp_offset = g.item_amp_offset; aa.ctrl_scale = g.ctrl_scale;
   aa.items = g.items;

@@ -359,14 +359,55 @@ __global__ void __launch_bounds__(256) k_bnorm(BigOmegaArgs g) {
   for (size_t e = threadIdx.x; e < nn; e += 256) { X[e].re *= f; X[e].im *= f; }
 }
 
+// Partial FP64 column 1-norms of dense matrices (as k_bomega's second half):
+// part[slice][tile_row][col].
+template <typename T>
+__global__ void __launch_bounds__(WG) k_bcolsum(BigOmegaArgs g) {
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  const int slice = blockIdx.y;
+  const int ti = blockIdx.x / Tn, tj = blockIdx.x % Tn;
+  RT<T> X;
+  rt_load<T, false>(X, (const cpx<T>*)g.omega + (size_t)slice * nn + (size_t)ti * 64 * g.n + tj * 64, g.n);
+  const Lane L;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double a = (double)X.re[q][r], b = (double)X.im[q][r];
+      s += sqrt(a * a + b * b);
+    }
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  if (L.g == 0) g.part[((size_t)slice * Tn + ti) * g.n + tj * 64 + L.col] = s;
+}
+
+// Omega = sum_j alpha_j B_j with its partial column norms; with ms set, also
+// the per-slice (m, s), Neumann levels and the scaling Omega / 2^s.
 hipError_t launch_bomega(int prec, const BigOmegaArgs& g, hipStream_t s) {
   if (g.n_slices <= 0) return hipSuccess;
   const int Tn = g.n / 64;
   if (prec == 32) {
     hipLaunchKernelGGL(k_bomega<float>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
-    hipLaunchKernelGGL(k_bnorm<float>, dim3(g.n_slices), dim3(256), 0, s, g);
+    if (g.ms) hipLaunchKernelGGL(k_bnorm<float>, dim3(g.n_slices), dim3(256), 0, s, g);
   } else {
     hipLaunchKernelGGL(k_bomega<double>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+    if (g.ms) hipLaunchKernelGGL(k_bnorm<double>, dim3(g.n_slices), dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+// (m, s), Neumann levels and the scaling Omega / 2^s of dense exponents held
+// in g.omega (the sixth-order slices, assembled by products).
+hipError_t launch_bnorm_dense(int prec, const BigOmegaArgs& g, hipStream_t s) {
+  if (g.n_slices <= 0) return hipSuccess;
+  const int Tn = g.n / 64;
+  if (prec == 32) {
+    hipLaunchKernelGGL(k_bcolsum<float>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+    hipLaunchKernelGGL(k_bnorm<float>, dim3(g.n_slices), dim3(256), 0, s, g);
+  } else {
+    hipLaunchKernelGGL(k_bcolsum<double>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
     hipLaunchKernelGGL(k_bnorm<double>, dim3(g.n_slices), dim3(256), 0, s, g);
   }
   return hipGetLastError();

@@ -64,6 +64,7 @@ struct lmag_ctx {
   // system
   bool has_sys = false;
   int d = 0, n = 0, ns = 0, nc = 0, nj = 0, prec = 32, order = 1, hold = 0, nb = 0, chunk = 0;
+  bool tiled = false;   // block-tiled path: superoperators above 64 x 64, or Magnus order 6
   size_t ws_max = 0;
   double* basis64 = nullptr;
   void* basis32 = nullptr;
@@ -742,8 +743,9 @@ BigLayout big_layout(const lmag_ctx* c, size_t meta_bytes, int Ns, int Lc, int n
   size_t o = align_up(meta_bytes);
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
   L.meta_end = o;
-  L.alpha = take((size_t)Ns * c->nb * 8);
-  L.gtrace = take((size_t)Ns * c->nb * 8);
+  const size_t planes = c->order == 6 ? 3 : 1;   // sixth order: a1, a2, a3 coefficients and traces
+  L.alpha = take(planes * Ns * c->nb * 8);
+  L.gtrace = take(planes * Ns * c->nb * 8);
   L.ms = take((size_t)Ns * 2);
   L.nlev = take((size_t)Ns);
   L.F_items = take((size_t)n_items * 8);
@@ -992,7 +994,32 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   aa.hold_foh = c->hold == LMAG_FOH; aa.nb = c->nb; aa.dt = b->dt;
   aa.slice_item = (const int32_t*)at(L.slice_item); aa.alpha = (double*)at(BL.alpha);
   aa.n_slices_total = Ns;
-  { StageTimer t(c, 0, s); HIPCHK(launch_alpha(aa, s), "alpha"); }
+  { StageTimer t(c, 0, s); HIPCHK(c->order == 6 ? launch_alpha6(aa, s) : launch_alpha(aa, s), "alpha"); }
+  const size_t coef_plane = (size_t)Ns * c->nb;
+  // sixth order: a1, a2, a3 of the window's slices on the order-1 basis (in
+  // A2, R0, S), then C1 = [a1, a2] (in Qi), W = 2 a3 + C1 (in T2),
+  // C2 = -(1/60) [a1, W] and Y = a2 + C2 (in T1), X = C1 - 20 a1 - a3 (in Qi);
+  // `tmp` is a free array
+  auto order6_levels = [&](const BigWindow& w, void* tmp) -> lmag_status {
+    const int Wn = w.ns;
+    const double* coef = (const double*)at(BL.alpha) + (size_t)w.s0 * c->nb;
+    void* al[3] = {A2, R0, S};
+    for (int pl = 0; pl < 3; ++pl) {
+      BigOmegaArgs oa{};
+      oa.n = n; oa.n_slices = Wn; oa.nb = c->nb; oa.basis = c->basis32;
+      oa.alpha = coef + pl * coef_plane; oa.omega = al[pl]; oa.part = (double*)at(BL.part);
+      HIPCHK(launch_bomega(32, oa, s), "a_p");
+    }
+    HIPCHK(gemm(Wn, A2, nullptr, R0, nullptr, T1, nullptr, 1.0), "a1 a2");
+    HIPCHK(gemm(Wn, R0, nullptr, A2, nullptr, Qi, nullptr, -1.0, T1, nullptr, 1.0), "C1");
+    HIPCHK(axpby(Wn, S, nullptr, T2, nullptr, 2.0, Qi, nullptr, 1.0), "W");
+    HIPCHK(gemm(Wn, A2, nullptr, T2, nullptr, tmp, nullptr, 1.0), "a1 W");
+    HIPCHK(gemm(Wn, T2, nullptr, A2, nullptr, T1, nullptr, 1.0 / 60.0, tmp, nullptr, -1.0 / 60.0), "C2");
+    HIPCHK(axpby(Wn, A2, nullptr, Qi, nullptr, -20.0, Qi, nullptr, 1.0), "X");
+    HIPCHK(axpby(Wn, S, nullptr, Qi, nullptr, -1.0, Qi, nullptr, 1.0), "X");
+    HIPCHK(axpby(Wn, R0, nullptr, T1, nullptr, 1.0, T1, nullptr, 1.0), "Y");
+    return LMAG_OK;
+  };
   c->last_ms = ms_all;
   c->last_total_slices = Ns;
 
@@ -1012,7 +1039,20 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     om.alpha = (const double*)at(BL.alpha) + (size_t)w.s0 * c->nb;
     om.omega = A; om.part = (double*)at(BL.part); om.ms = ms_w; om.nlev = nlev_w;
     for (int i = 0; i < 4; ++i) om.b3[i] = b3[i];
-    { StageTimer t(c, 1, s); HIPCHK(launch_bomega(32, om, s), "omega"); }
+    if (c->order == 6) {
+      // Omega = a1 + a3 / 12 + (1/240) [X, Y]
+      StageTimer t(c, 1, s);
+      lmag_status st6 = order6_levels(w, A);
+      if (st6 != LMAG_OK) return st6;
+      HIPCHK(gemm(Wn, Qi, nullptr, T1, nullptr, T2, nullptr, 1.0), "X Y");
+      HIPCHK(gemm(Wn, T1, nullptr, Qi, nullptr, A, nullptr, -1.0 / 240.0, T2, nullptr, 1.0 / 240.0), "[X, Y]");
+      HIPCHK(axpby(Wn, A2, nullptr, A, nullptr, 1.0, A, nullptr, 1.0), "+ a1");
+      HIPCHK(axpby(Wn, S, nullptr, A, nullptr, 1.0 / 12.0, A, nullptr, 1.0), "+ a3 / 12");
+      HIPCHK(launch_bnorm_dense(32, om, s), "omega norm");
+    } else {
+      StageTimer t(c, 1, s);
+      HIPCHK(launch_bomega(32, om, s), "omega");
+    }
     if (first_pass) {
       std::vector<int8_t> msh((size_t)Wn * 2);
       HIPCHK(hipMemcpyAsync(msh.data(), ms_w, msh.size(), hipMemcpyDeviceToHost, s), "ms");
@@ -1211,12 +1251,50 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           HIPCHK(axpby(cnt, T1, li, R0, li, 1.0), "R");
         }
       }
+      if (c->order == 6) {
+        // cotangents of a1, a2, a3 from K = dF/dOmega through
+        // Omega = a1 + a3/12 + [X, Y]/240, X = C1 - 20 a1 - a3, Y = a2 + C2,
+        // C2 = -(1/60)[a1, W], W = 2 a3 + C1, C1 = [a1, a2]; for C = [P, Q]
+        // with cotangent G the cotangents are [Q, G] for P and [G, P] for Q
+        StageTimer t(c, 5, s);
+        lmag_status st6 = order6_levels(w, A);
+        if (st6 != LMAG_OK) return st6;
+        // G_X = [Y, K] / 240 (S), G_Y = [K, X] / 240 (Pl)
+        HIPCHK(gemm(Wn, T1, nullptr, T3, nullptr, Em, nullptr, 1.0), "Y K");
+        HIPCHK(gemm(Wn, T3, nullptr, T1, nullptr, S, nullptr, -1.0 / 240.0, Em, nullptr, 1.0 / 240.0), "G_X");
+        HIPCHK(gemm(Wn, T3, nullptr, Qi, nullptr, Em, nullptr, 1.0), "K X");
+        HIPCHK(gemm(Wn, Qi, nullptr, T3, nullptr, Pl, nullptr, -1.0 / 240.0, Em, nullptr, 1.0 / 240.0), "G_Y");
+        // G_a1 = K - 20 G_X (Qi), G_a3 = K / 12 - G_X (T1)
+        HIPCHK(axpby(Wn, T3, nullptr, Qi, nullptr, 1.0, S, nullptr, -20.0), "G_a1");
+        HIPCHK(axpby(Wn, T3, nullptr, T1, nullptr, 1.0 / 12.0, S, nullptr, -1.0), "G_a3");
+        // G_W = -(1/60)[G_Y, a1] (T4); G_a1 += -(1/60)[W, G_Y]
+        HIPCHK(gemm(Wn, A2, nullptr, Pl, nullptr, Em, nullptr, 1.0), "a1 G_Y");
+        HIPCHK(gemm(Wn, Pl, nullptr, A2, nullptr, T4, nullptr, -1.0 / 60.0, Em, nullptr, 1.0 / 60.0), "G_W");
+        HIPCHK(gemm(Wn, T2, nullptr, Pl, nullptr, Em, nullptr, 1.0), "W G_Y");
+        HIPCHK(gemm(Wn, Pl, nullptr, T2, nullptr, A, nullptr, 1.0 / 60.0, Em, nullptr, -1.0 / 60.0), "[W, G_Y]");
+        HIPCHK(axpby(Wn, A, nullptr, Qi, nullptr, 1.0, Qi, nullptr, 1.0), "G_a1 +");
+        // G_a3 += 2 G_W; G_C1 = G_X + G_W (S)
+        HIPCHK(axpby(Wn, T4, nullptr, T1, nullptr, 2.0, T1, nullptr, 1.0), "G_a3 +");
+        HIPCHK(axpby(Wn, T4, nullptr, S, nullptr, 1.0, S, nullptr, 1.0), "G_C1");
+        // G_a1 += [a2, G_C1]; G_a2 = G_Y + [G_C1, a1] (Pl)
+        HIPCHK(gemm(Wn, R0, nullptr, S, nullptr, Em, nullptr, 1.0), "a2 G_C1");
+        HIPCHK(gemm(Wn, S, nullptr, R0, nullptr, A, nullptr, -1.0, Em, nullptr, 1.0), "[a2, G_C1]");
+        HIPCHK(axpby(Wn, A, nullptr, Qi, nullptr, 1.0, Qi, nullptr, 1.0), "G_a1 +");
+        HIPCHK(gemm(Wn, S, nullptr, A2, nullptr, Em, nullptr, 1.0), "G_C1 a1");
+        HIPCHK(gemm(Wn, A2, nullptr, S, nullptr, A, nullptr, -1.0, Em, nullptr, 1.0), "[G_C1, a1]");
+        HIPCHK(axpby(Wn, A, nullptr, Pl, nullptr, 1.0, Pl, nullptr, 1.0), "G_a2");
+      }
       {
         StageTimer t(c, 6, s);
-        BigTraceArgs ta{};
-        ta.n = n; ta.n_slices = Wn; ta.nb = c->nb; ta.first_slice = w.s0; ta.trans_basis = 1;
-        ta.K = T3; ta.basis = c->basis32; ta.part = (double*)at(BL.part); ta.gtrace = (double*)at(BL.gtrace);
-        HIPCHK(launch_btraces(32, ta, s), "traces");
+        void* Ks[3] = {T3, nullptr, nullptr};
+        if (c->order == 6) { Ks[0] = Qi; Ks[1] = Pl; Ks[2] = T1; }
+        for (int pl = 0; pl < (c->order == 6 ? 3 : 1); ++pl) {
+          BigTraceArgs ta{};
+          ta.n = n; ta.n_slices = Wn; ta.nb = c->nb; ta.first_slice = w.s0; ta.trans_basis = 1;
+          ta.K = Ks[pl]; ta.basis = c->basis32; ta.part = (double*)at(BL.part);
+          ta.gtrace = (double*)at(BL.gtrace) + pl * coef_plane;
+          HIPCHK(launch_btraces(32, ta, s), "traces");
+        }
       }
     }
   }
@@ -1227,6 +1305,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     ga.n_items = (int)p.items.size(); ga.static_coef = b->static_coef; ga.ctrl_scale = b->ctrl_scale;
     ga.n_ctrl = c->nc; ga.n_static = c->ns; ga.order = c->order; ga.hold_foh = c->hold == LMAG_FOH;
     ga.nb = c->nb; ga.dt = b->dt; ga.inv_d2 = 1.0 / ((double)c->d * c->d);
+    ga.n_slices_total = Ns;
     ga.grad = grad ? grad_out : nullptr;
     ga.group_first_item = grouped ? (const int32_t*)at(L.group_first) : nullptr;
     ga.group_items = grouped ? (const int32_t*)at(L.group_items) : nullptr;
@@ -1271,7 +1350,7 @@ lmag_status run_waves_body(lmag_ctx* c, const lmag_batch* b, const int32_t* targ
                            int n_targets, bool grad, bool fidelity, const void* U_target,
                            double* F_out, void* grad_out, void* S_out, hipStream_t s) {
   lmag_status st = LMAG_OK;
-  if (c->n > 64)
+  if (c->tiled)
     return run_big(c, b, target_of_item, n_targets, grad, fidelity, U_target, F_out, grad_out, S_out, s);
   // units: whole groups (grouped calls) or single items, in order
   std::vector<std::vector<int>> units;
@@ -1442,11 +1521,12 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     if (!s) return c->fail(LMAG_E_INVALID, "system descriptor is NULL");
     const int d = s->d;
     if (d < 1 || d > 64) return c->fail(LMAG_E_INVALID, "d must satisfy 1 <= d <= 64");
-    const bool big = d * d > 64;
+    const bool big = d * d > 64 || s->magnus_order == 6;
     if (big && (d * d) % 64 != 0)
-      return c->fail(LMAG_E_UNSUPPORTED, "d*d must be <= 64 or a multiple of 64");
+      return c->fail(LMAG_E_UNSUPPORTED, d * d > 64 ? "d*d must be <= 64 or a multiple of 64"
+                                                    : "Magnus order 6 needs d*d a multiple of 64");
     if (big && s->precision != LMAG_F32)
-      return c->fail(LMAG_E_UNSUPPORTED, "superoperators larger than 64 x 64 run in FP32 only");
+      return c->fail(LMAG_E_UNSUPPORTED, "superoperators larger than 64 x 64 and Magnus order 6 run in FP32 only");
     if (s->n_static < 0 || s->n_ctrl < 0 || s->n_jump < 0)
       return c->fail(LMAG_E_INVALID, "negative operator count");
     if (s->n_ctrl > 8 || s->n_static > 8) return c->fail(LMAG_E_UNSUPPORTED, "at most 8 controls and 8 static terms");
@@ -1454,8 +1534,8 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       return c->fail(LMAG_E_INVALID, "operator array is NULL");
     if (s->precision != LMAG_F32 && s->precision != LMAG_F64)
       return c->fail(LMAG_E_INVALID, "precision must be LMAG_F32 or LMAG_F64");
-    if (s->magnus_order != 1 && s->magnus_order != 2)
-      return c->fail(LMAG_E_INVALID, "magnus_order must be 1 or 2");
+    if (s->magnus_order != 1 && s->magnus_order != 2 && s->magnus_order != 6)
+      return c->fail(LMAG_E_INVALID, "magnus_order must be 1, 2 or 6");
     if (s->hold != LMAG_ZOH && s->hold != LMAG_FOH) return c->fail(LMAG_E_INVALID, "hold must be ZOH or FOH");
     if (s->chunk_slices < 0) return c->fail(LMAG_E_INVALID, "chunk_slices < 0");
     const size_t dd2 = (size_t)d * d * 2;
@@ -1550,6 +1630,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     c->d = d; c->n = d * d; c->ns = ns; c->nc = nc; c->nj = s->n_jump;
     c->prec = s->precision; c->order = s->magnus_order; c->hold = s->hold; c->nb = nb;
     c->chunk = s->chunk_slices; c->ws_max = s->workspace_bytes_max;
+    c->tiled = big;
     c->has_sys = true;
     return LMAG_OK;
   } catch (const std::bad_alloc&) {
@@ -1604,8 +1685,9 @@ lmag_status lmag_fidelity_and_grad_noalloc(lmag_ctx* c, const lmag_batch* b, con
     if (!c->has_sys) return c->fail(LMAG_E_NOSYSTEM, "lmag_set_system has not been called");
     if (!U_target || n_targets < 1) return c->fail(LMAG_E_INVALID, "U_target NULL or n_targets < 1");
     if (!F_out) return c->fail(LMAG_E_INVALID, "F_out is NULL");
-    if (c->n > 64)
-      return c->fail(LMAG_E_UNSUPPORTED, "the no-allocation entry point covers superoperators up to 64 x 64");
+    if (c->tiled)
+      return c->fail(LMAG_E_UNSUPPORTED, "the no-allocation entry point covers the 64 x 64 slice kernels "
+                                         "(superoperators up to 64 x 64, Magnus order 1 or 2)");
     if (!c->scratch) return c->fail(LMAG_E_DEVICE, "no address for the scratch array on this device");
     const bool grad = grad_out != nullptr;
     lmag_status st = validate_batch(c, b, target_of_item, n_targets, grad);
@@ -1699,7 +1781,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
       return c->fail(LMAG_E_NOMEM, "autotune output buffers");
     }
     const int saved_chunk = c->chunk, saved_inv = c->inv_variant, saved_big = c->big_variant;
-    const bool big = c->n > 64;
+    const bool big = c->tiled;
     const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
     std::vector<int> chunks;
     if (big) {
@@ -1882,7 +1964,7 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx* c, const lmag_batch* b, int ki
     if (L < 1 || L > MAX_LOGICAL) return c->fail(LMAG_E_INVALID, "L must be 1..4");
     if (!P || !T || n_targets < 1) return c->fail(LMAG_E_INVALID, "P or T NULL, or n_targets < 1");
     if (!score_out) return c->fail(LMAG_E_INVALID, "score_out is NULL");
-    if (c->n > 64) return c->fail(LMAG_E_UNSUPPORTED, "logical scores need d * d <= 64");
+    if (c->tiled) return c->fail(LMAG_E_UNSUPPORTED, "logical scores need d * d <= 64 and Magnus order 1 or 2");
     if (!finite_array(P, (size_t)c->n * L * 2)) return c->fail(LMAG_E_INVALID, "non-finite P");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)hip_stream;
