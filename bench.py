@@ -384,6 +384,10 @@ def main():
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
     ap.add_argument("--autotune", action="store_true",
                     help="tune chunk length and inverse variant before the timed steps")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2511_13330_amd", "tuning",
+                                                     "gfx950.jsonl"),
+                    help="tuning lines written by lmag_autotune (LMAG_TUNE_CACHE) to load first; "
+                         "'' for none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES (counter calibration)")
     ap.add_argument("--workload", default="pulse",
@@ -461,6 +465,16 @@ def main():
         return sysm.fidelity_and_grad(a, ns, cfg["dt"], UT, static_coef=st)
 
     tuned = None
+    if args.tuning and os.path.exists(args.tuning) and args.chunk == 0 and not args.autotune:
+        # the autotuner's stored choice for this size (same key as the library's)
+        sysm.load_tuning(args.tuning)
+        key = f"p32_o2_d8_s{int(np.floor(np.log2(B * 4096)))}"
+        with open(args.tuning) as f:
+            for line in f:
+                rec = json.loads(line)
+                if rec.get("key") == key:
+                    tuned = (rec["chunk"], rec.get("variant", rec.get("inverse")), rec["ms"],
+                             os.path.relpath(args.tuning, ROOT))
     if args.autotune and args.chunk == 0:
         tuned = sysm.autotune(amps, n_slices, cfg["dt"], UT, static_coef=static, reps=1)
     for _ in range(args.warmup):
@@ -513,8 +527,12 @@ def main():
                                f"batch of {B} pulses per step",
                    "batch_pulses": B, "n_slices": 4096, "superop_dim": 64,
                    "chunk_slices": plan["chunk_slices"], "grid": plan["grid"],
-                   "inverse": "autotuned" if tuned else "auto (power series, MFMA Neumann or Gauss-Jordan per slice bound)",
-                   "autotune": list(tuned) if tuned else None},
+                   "inverse": "auto (power series, MFMA Neumann or Gauss-Jordan per slice bound)"
+                   if not tuned or tuned[1] == 0 else ("Gauss-Jordan" if tuned[1] == 1 else "Neumann"),
+                   "autotune": ({"chunk": tuned[0], "inverse_variant": tuned[1],
+                                 "ms_per_call_when_tuned": tuned[2],
+                                 "source": tuned[3] if len(tuned) > 3 else "tuned in this run"}
+                                if tuned else None)},
         "roofline": roofline,
         "whole_step_tflops": total_flops / (elapsed / args.steps) / 1e12,
         "other_kernel": {"kernel": other, "achieved_tflops": fl2 / (ms2 * 1e-3) / 1e12,

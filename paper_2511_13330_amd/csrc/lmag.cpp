@@ -732,7 +732,7 @@ int big_auto_chunk(const lmag_ctx* c, long long total) {
 // are held at once (all of them when the adjoint stores them).
 struct BigLayout {
   size_t meta_end = 0, alpha = 0, gtrace = 0, ms = 0, nlev = 0, F_items = 0, part = 0, st64 = 0,
-         st = 0, sq = 0, mats = 0, cmats = 0, total = 0;
+         st = 0, sq = 0, mlist = 0, mats = 0, cmats = 0, total = 0;
 };
 
 BigLayout big_layout(const lmag_ctx* c, size_t meta_bytes, int Ns, int Lc, int n_items, int window,
@@ -753,6 +753,7 @@ BigLayout big_layout(const lmag_ctx* c, size_t meta_bytes, int Ns, int Lc, int n
   L.st64 = take((size_t)std::max(1, n_targets) * n * n * 16);
   L.st = take((size_t)std::max(1, n_targets) * mb);
   L.sq = take((size_t)Ns * kBigMaxSquarings * 4 + 4);   // squaring lists of every window
+  L.mlist = take((size_t)Ns * 4 + 4);                    // slices by Pade degree, per window
   L.mats = take((size_t)(grad ? 11 : 7) * window * mb);
   L.cmats = take((size_t)8 * Lc * mb);
   L.total = o;
@@ -768,6 +769,8 @@ struct BigWindow {
   int smax = 0;
   size_t sq_base = 0;                   // first entry of its squaring lists
   std::vector<int32_t> sq_list, sq_off;
+  int n2 = 0, n3 = 0;                   // slices at Pade degree 2 and 3 (lists at s0 of mlist)
+  std::vector<int32_t> mlist_host;
 };
 
 lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_item,
@@ -1078,29 +1081,54 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       if (!w.sq_list.empty())
         HIPCHK(hipMemcpyAsync((int32_t*)at(BL.sq) + w.sq_base, w.sq_list.data(), w.sq_list.size() * 4,
                               hipMemcpyHostToDevice, s), "squaring lists");
+      // the window's slices at Pade degree 2 (by the degree-4 series of r_2),
+      // then those at degree 3
+      std::vector<int32_t> ml;
+      for (int i = 0; i < Wn; ++i)
+        if (msh[2 * i] == 2) ml.push_back(i);
+      w.n2 = (int)ml.size();
+      for (int i = 0; i < Wn; ++i)
+        if (msh[2 * i] != 2) ml.push_back(i);
+      w.n3 = Wn - w.n2;
+      w.mlist_host.swap(ml);
+      HIPCHK(hipMemcpyAsync((int32_t*)at(BL.mlist) + w.s0, w.mlist_host.data(), (size_t)Wn * 4,
+                            hipMemcpyHostToDevice, s), "degree lists");
     }
     const int32_t* sq = ip(BL.sq) + w.sq_base;
+    const int32_t* L2 = ip(BL.mlist) + w.s0;     // degree-2 slices (window-local)
+    const int32_t* L3 = L2 + w.n2;               // degree-3 slices
     {
       StageTimer t(c, 2, s);
-      HIPCHK(gemm(Wn, A, nullptr, A, nullptr, A2, nullptr, 1.0), "A2");
-      HIPCHK(axpby(Wn, A2, nullptr, T1, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");
-      HIPCHK(gemm(Wn, A, nullptr, T1, nullptr, T2, nullptr, 1.0), "U");                  // T2 = U
-      HIPCHK(axpby(Wn, A2, nullptr, T1, nullptr, b3[2], T2, nullptr, 1.0), "X_P");        // T1 = b2 A2 + U
-      HIPCHK(axpby(Wn, A2, nullptr, S, nullptr, -b3[2], T2, nullptr, 1.0), "E");         // S = E = U - b2 A2
-      HIPCHK(axpby(Wn, S, nullptr, T2, nullptr, 1.0), "X = E");                           // T2 = X
-      // (I + X)(I + F2) - I = X + F2 + F2 X; level k runs for the slices whose
-      // Neumann level count exceeds k (the others copy F and X through)
-      void *F = S, *X = T2, *F2 = R0, *Xn = Qi;
-      for (int k = 1; k < kBigNeumannLevels; ++k) {
-        HIPCHK(gemm(Wn, F, nullptr, F, nullptr, F2, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, 0, 0,
-                    nlev_w, k), "F2");
-        HIPCHK(gemm2(Wn, F2, X, Xn, 1.0, X, 1.0, F2, 1.0, nlev_w, k), "X + F2 + F2 X");
-        std::swap(F, F2);
-        std::swap(X, Xn);
+      if (w.n3) {
+        const int n3 = w.n3;
+        HIPCHK(gemm(n3, A, L3, A, L3, A2, L3, 1.0), "A2");
+        HIPCHK(axpby(n3, A2, L3, T1, L3, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");
+        HIPCHK(gemm(n3, A, L3, T1, L3, T2, L3, 1.0), "U");                                    // T2 = U
+        HIPCHK(axpby(n3, A2, L3, T1, L3, b3[2], T2, L3, 1.0), "X_P");                         // T1 = b2 A2 + U
+        HIPCHK(axpby(n3, A2, L3, S, L3, -b3[2], T2, L3, 1.0), "E");                          // S = E = U - b2 A2
+        HIPCHK(axpby(n3, S, L3, T2, L3, 1.0), "X = E");                                       // T2 = X
+        // (I + X)(I + F2) - I = X + F2 + F2 X; level k runs for the slices whose
+        // Neumann level count exceeds k (the others copy F and X through)
+        void *F = S, *X = T2, *F2 = R0, *Xn = Qi;
+        for (int k = 1; k < kBigNeumannLevels; ++k) {
+          HIPCHK(gemm(n3, F, L3, F, L3, F2, L3, 1.0, nullptr, nullptr, 0.0, 0.0, 0, 0, nlev_w, k), "F2");
+          HIPCHK(gemmx(n3, F2, L3, X, L3, Xn, L3, 1.0, X, L3, 1.0, F2, L3, 1.0, nlev_w, k), "X + F2 + F2 X");
+          std::swap(F, F2);
+          std::swap(X, Xn);
+        }
+        if (X != Qi) HIPCHK(axpby(n3, X, L3, Qi, L3, 1.0), "X_Q");
+        HIPCHK(gemmx(n3, Qi, L3, T1, L3, R0, L3, 1.0, Qi, L3, 1.0, T1, L3, 1.0), "D");   // R0 = X_Q + X_P + X_Q X_P
+        HIPCHK(axpby(n3, R0, L3, S, L3, 1.0), "S");
       }
-      if (X != Qi) HIPCHK(axpby(Wn, X, nullptr, Qi, nullptr, 1.0), "X_Q");
-      HIPCHK(gemm2(Wn, Qi, T1, R0, 1.0, Qi, 1.0, T1, 1.0), "D");   // R0 = X_Q + X_P + X_Q X_P
-      HIPCHK(axpby(Wn, R0, nullptr, S, nullptr, 1.0), "S");
+      if (w.n2) {
+        // Pade 2 by its power series cut at degree 4 (the degree-4 Taylor
+        // polynomial): D = A + A^2 (I/2 + A/6 + A^2/24); s = 0 at this degree
+        const int n2 = w.n2;
+        HIPCHK(gemm(n2, A, L2, A, L2, A2, L2, 1.0), "A2");
+        HIPCHK(axpby(n2, A, L2, T1, L2, 1.0 / 6.0, A2, L2, 1.0 / 24.0, 0.5), "I/2 + A/6 + A2/24");
+        HIPCHK(gemm(n2, A2, L2, T1, L2, R0, L2, 1.0, A, L2, 1.0), "D");
+        HIPCHK(axpby(n2, R0, L2, S, L2, 1.0), "S");
+      }
       // (I + D)^2 = I + 2 D + D^2
       for (int k = 0; k < w.smax; ++k) {
         const int cnt = w.sq_off[k + 1] - w.sq_off[k];
@@ -1227,17 +1255,33 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
         HIPCHK(axpby(Wn, Em, nullptr, Em, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, ms_all + 2 * (size_t)w.s0),
                "E scale");
-        HIPCHK(gemm(Wn, A, nullptr, Em, nullptr, T1, nullptr, 1.0), "AE");
-        HIPCHK(gemm(Wn, Em, nullptr, A, nullptr, T1, nullptr, 1.0, T1, nullptr, 1.0), "L2");       // T1 = L2
-        HIPCHK(axpby(Wn, A2, nullptr, T2, nullptr, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");      // T2 = W
-        HIPCHK(axpby(Wn, T1, nullptr, T3, nullptr, b3[3]), "LW");                                    // T3 = L_W
-        HIPCHK(gemm(Wn, A, nullptr, T3, nullptr, T4, nullptr, 1.0), "A LW");
-        HIPCHK(gemm(Wn, Em, nullptr, T2, nullptr, T4, nullptr, 1.0, T4, nullptr, 1.0), "LU");       // T4 = L_U
-        HIPCHK(axpby(Wn, T1, nullptr, T3, nullptr, b3[2], T4, nullptr, -1.0), "LQ");                 // T3 = L_Q
-        HIPCHK(axpby(Wn, T1, nullptr, T2, nullptr, b3[2], T4, nullptr, 1.0), "LP");                  // T2 = L_P
-        // r = I + D (R0 = D), Q^{-1} = I + X_Q (Qi = X_Q)
-        HIPCHK(gemm2(Wn, T3, R0, T1, -1.0, T2, 1.0, T3, -1.0), "X");   // T1 = L_P - L_Q - L_Q D
-        HIPCHK(gemm(Wn, Qi, nullptr, T1, nullptr, T3, nullptr, 1.0, T1, nullptr, 1.0), "K");   // T3 = K
+        const int32_t* L2 = ip(BL.mlist) + w.s0;
+        const int32_t* L3 = L2 + w.n2;
+        if (w.n3) {
+          const int n3 = w.n3;
+          HIPCHK(gemm(n3, A, L3, Em, L3, T1, L3, 1.0), "AE");
+          HIPCHK(gemm(n3, Em, L3, A, L3, T1, L3, 1.0, T1, L3, 1.0), "L2");                    // T1 = L2
+          HIPCHK(axpby(n3, A2, L3, T2, L3, b3[3], nullptr, nullptr, 0.0, b3[1]), "W");         // T2 = W
+          HIPCHK(axpby(n3, T1, L3, T3, L3, b3[3]), "LW");                                       // T3 = L_W
+          HIPCHK(gemm(n3, A, L3, T3, L3, T4, L3, 1.0), "A LW");
+          HIPCHK(gemm(n3, Em, L3, T2, L3, T4, L3, 1.0, T4, L3, 1.0), "LU");                    // T4 = L_U
+          HIPCHK(axpby(n3, T1, L3, T3, L3, b3[2], T4, L3, -1.0), "LQ");                        // T3 = L_Q
+          HIPCHK(axpby(n3, T1, L3, T2, L3, b3[2], T4, L3, 1.0), "LP");                         // T2 = L_P
+          // r = I + D (R0 = D), Q^{-1} = I + X_Q (Qi = X_Q)
+          HIPCHK(gemmx(n3, T3, L3, R0, L3, T1, L3, -1.0, T2, L3, 1.0, T3, L3, -1.0), "X");   // T1 = L_P - L_Q - L_Q D
+          HIPCHK(gemm(n3, Qi, L3, T1, L3, T3, L3, 1.0, T1, L3, 1.0), "K");                    // T3 = K
+        }
+        if (w.n2) {
+          // derivative of the degree-4 polynomial A + A^2/2 + A^3/6 + A^4/24:
+          // K = E + L2/2 + L2 (A/6 + A^2/24) + A^2 (E/6 + L2/24), L2 = A E + E A
+          const int n2 = w.n2;
+          HIPCHK(gemm(n2, A, L2, Em, L2, T1, L2, 1.0), "AE");
+          HIPCHK(gemm(n2, Em, L2, A, L2, T1, L2, 1.0, T1, L2, 1.0), "L2");                    // T1 = L2
+          HIPCHK(axpby(n2, A, L2, T2, L2, 1.0 / 6.0, A2, L2, 1.0 / 24.0), "A/6 + A2/24");
+          HIPCHK(gemmx(n2, T1, L2, T2, L2, T4, L2, 1.0, Em, L2, 1.0, T1, L2, 0.5), "E + L2/2 + L2 (.)");
+          HIPCHK(axpby(n2, Em, L2, T2, L2, 1.0 / 6.0, T1, L2, 1.0 / 24.0), "E/6 + L2/24");
+          HIPCHK(gemm(n2, A2, L2, T2, L2, T3, L2, 1.0, T4, L2, 1.0), "K");                    // T3 = K
+        }
         // squaring recurrence K <- R K + K R = 2 K + D K + K D, D <- 2 D + D D for the
         // slices with s > k
         for (int k = 0; k < w.smax; ++k) {

@@ -147,11 +147,11 @@ __device__ __forceinline__ int inverse_code(double nA, const double* b, int m, i
   return neumann_levels<T>(nA, b, m);
 }
 
-// Block-tiled path: single precision, Pade-3 only.
+// Block-tiled path: single precision; Pade 2 (evaluated by its degree-4
+// series, no scaling) or Pade 3 with scaling, as in the 64 x 64 kernels.
 template <typename T>
 __device__ __forceinline__ void big_choose_ms(double nrm, int& m, int& s) {
   choose_ms<T>(nrm, m, s);
-  m = 3;
 }
 
 template <typename T>
