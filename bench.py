@@ -249,6 +249,17 @@ def robust_sweep(args):
     scale = torch.as_tensor(np.tile(cfg["eps"], (n_cand, 1)), dtype=torch.float64, device="cuda")
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     kw = dict(slice_offset=off, static_coef=static, ctrl_scale=scale, groups=groups)
+    tuned = None
+    if args.autotune and args.chunk == 0:
+        tuned = sysm.autotune(a, ns, cfg["dt"], cfg["U_target"], reps=1, **kw)
+    elif args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
+        sysm.load_tuning(args.tuning)
+        key = f"p32_o2_d8_s{int(np.floor(np.log2(int(ns.sum()))))}"
+        with open(args.tuning) as f:
+            for line in f:
+                rec = json.loads(line)
+                if rec.get("key") == key:
+                    tuned = (rec["chunk"], rec.get("variant", rec.get("inverse")), rec["ms"])
     F, g = sysm.fidelity_and_grad(a, ns, cfg["dt"], cfg["U_target"], **kw)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -269,7 +280,10 @@ def robust_sweep(args):
                     "eps ~ N(1, 0.01))",
             "config": {"workload": f"{n_cand} candidates x {S} noise samples, uneven N, "
                                    "3-spin FOH 2nd order", "items": int(len(ns)),
-                       "slice_evaluations": slices, "waves": plan["waves"]},
+                       "slice_evaluations": slices, "waves": plan["waves"],
+                       "chunk_slices": plan["chunk_slices"],
+                       "autotune": {"chunk": tuned[0], "inverse_variant": tuned[1],
+                                    "ms_per_call_when_tuned": tuned[2]} if tuned else None},
             "slice_evals_per_s": slices / dt, "tflops_algorithmic": flops / dt / 1e12,
             "F_mean_first_candidates": [float(x) for x in F[:4].cpu().numpy()]}
 

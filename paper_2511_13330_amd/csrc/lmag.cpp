@@ -65,6 +65,7 @@ struct lmag_ctx {
   bool has_sys = false;
   int d = 0, n = 0, ns = 0, nc = 0, nj = 0, prec = 32, order = 1, hold = 0, nb = 0, chunk = 0;
   bool tiled = false;   // block-tiled path: superoperators above 64 x 64, or Magnus order 6
+  long long call_total = 0;   // slices of the current compute call (tuning key)
   size_t ws_max = 0;
   double* basis64 = nullptr;
   void* basis32 = nullptr;
@@ -223,7 +224,9 @@ const std::pair<int, int>* tuned_for(const lmag_ctx* c, long long total) {
 // 64: its per-workgroup scratch grows with the chunk.
 int auto_chunk(const lmag_ctx* c, long long total, bool recompute) {
   if (c->chunk > 0) return c->chunk;
-  if (const auto* t = tuned_for(c, total)) return t->first;
+  // tuned choices are keyed by the whole call's size (a call split into
+  // budget waves looks up the key of the call, as the autotuner stored it)
+  if (const auto* t = tuned_for(c, c->call_total > 0 ? c->call_total : total)) return t->first;
   const long long per = (total + c->n_cu - 1) / std::max(1, c->n_cu);
   if (per <= 64) return (int)std::max<long long>(1, per);
   return (int)std::min<long long>(recompute ? 64 : 256, std::max<long long>(64, per / 4));
@@ -464,7 +467,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   {
     int inv = c->inv_variant;
     if (inv == 0 && c->chunk <= 0)
-      if (const auto* t = tuned_for(c, p.total_slices)) inv = t->second;
+      if (const auto* t = tuned_for(c, c->call_total > 0 ? c->call_total : p.total_slices)) inv = t->second;
     if (inv == 1) sa.nlev = nullptr;   // Gauss-Jordan for every slice
     sa.inv_mode = inv;
   }
@@ -1382,8 +1385,11 @@ lmag_status run_waves(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of
   if (c->call_pending && s != c->last_stream)
     HIPCHK(hipStreamWaitEvent(s, c->call_done, 0), "hipStreamWaitEvent");
   c->last_stream = s;
+  c->call_total = 0;
+  for (int i = 0; i < b->n_items; ++i) c->call_total += b->n_slices[i];
   st = run_waves_body(c, b, target_of_item, n_targets, grad, fidelity, U_target, F_out, grad_out,
                       S_out, s);
+  c->call_total = 0;
   hipError_t e = hipEventRecord(c->call_done, s);
   if (e != hipSuccess && st == LMAG_OK) return c->hip_fail(e, "hipEventRecord");
   c->call_pending = true;
