@@ -307,6 +307,14 @@ def large_system(args):
     tuned = None
     if args.autotune and args.chunk == 0:
         tuned = sysm.autotune(a, [N], cfg["dt"], cfg["U_target"], static_coef=b, reps=1)
+    elif args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
+        sysm.load_tuning(args.tuning)
+        key = f"p32_o2_d{cfg['d']}_s{int(np.floor(np.log2(N)))}"
+        with open(args.tuning) as f:
+            for line in f:
+                rec = json.loads(line)
+                if rec.get("key") == key:
+                    tuned = (rec["chunk"], rec.get("variant", rec.get("inverse")), rec["ms"])
     F, g = sysm.fidelity_and_grad(a, [N], cfg["dt"], cfg["U_target"], static_coef=b)  # warm-up
     torch.cuda.synchronize()
     steps = max(1, min(args.steps, 3))

@@ -267,18 +267,25 @@ struct BigAxpbyArgs {
   double a, c, d;
   const int8_t* ms;         // if set: a *= 2^-s of entry Yi[b] (ms[2 i + 1])
 };
+// Tile lists of the basis (block-tiled path): the basis elements whose 64 x 64
+// tile at position t = ti * Tn + tj is not all zero are tile_j[tile_ptr[t] ..
+// tile_ptr[t + 1]), ascending; null pointers mean every element.
 struct BigOmegaArgs {
   int n, n_slices, nb;
   const void* basis; const double* alpha;
   void* omega; double* part;
   int8_t* ms; int8_t* nlev;
   double b3[4];
+  const int32_t* tile_ptr; const int32_t* tile_j;
 };
 struct BigTraceArgs {
   int n, n_slices, nb, first_slice, trans_basis;
   const void* K; const void* basis;
   double* part; double* gtrace;
+  const int32_t* tile_ptr; const int32_t* tile_j;
 };
+// flags[j][t] = 1 if tile t of basis element j has a nonzero entry (FP64 basis)
+hipError_t launch_tile_flags(const double* basis, int nb, int n, uint8_t* flags, hipStream_t s);
 struct BigFidArgs {
   int n, n_items, d;
   const void* U; const int32_t* U_index;

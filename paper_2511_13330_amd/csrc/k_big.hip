@@ -290,7 +290,10 @@ __global__ void __launch_bounds__(WG) k_bomega(BigOmegaArgs g) {
   const double* al = g.alpha + (size_t)slice * g.nb;
   RT<T> X;
   rt_zero(X);
-  for (int j = 0; j < g.nb; ++j) {
+  const int t = blockIdx.x;
+  const int j0 = g.tile_ptr ? g.tile_ptr[t] : 0, j1 = g.tile_ptr ? g.tile_ptr[t + 1] : g.nb;
+  for (int e = j0; e < j1; ++e) {
+    const int j = g.tile_ptr ? g.tile_j[e] : e;
     const double aj = al[j];
     if (aj == 0.0) continue;
     RT<T> Bt;
@@ -425,9 +428,17 @@ __global__ void __launch_bounds__(WG) k_btraces_part(BigTraceArgs g) {
   const cpx<T>* K = (const cpx<T>*)g.K + (size_t)slice * nn;
   const cpx<T>* basis = (const cpx<T>*)g.basis;
   const Lane L;
+  // the basis tile read here sits at (tj, ti) when the basis is read transposed
+  const int bt = g.trans_basis ? tj * Tn + ti : tile;
+  for (int j = threadIdx.x; j < g.nb; j += WG) {
+    red[0][j] = 0.0; red[1][j] = 0.0; red[2][j] = 0.0; red[3][j] = 0.0;
+  }
+  __syncthreads();
+  const int j0 = g.tile_ptr ? g.tile_ptr[bt] : 0, j1 = g.tile_ptr ? g.tile_ptr[bt + 1] : g.nb;
   RT<T> Kt;
-  rt_load<T, false>(Kt, K + (size_t)ti * 64 * g.n + tj * 64, g.n);
-  for (int j = 0; j < g.nb; ++j) {
+  if (j1 > j0) rt_load<T, false>(Kt, K + (size_t)ti * 64 * g.n + tj * 64, g.n);
+  for (int e = j0; e < j1; ++e) {
+    const int j = g.tile_ptr ? g.tile_j[e] : e;
     RT<T> Bt;
     // same positions as K^T; with trans_basis the basis is read transposed
     // (Re Tr(K B_j) = Re sum_{a,b} K[a][b] B_j[b][a] for a K stored untransposed)
@@ -456,6 +467,31 @@ __global__ void k_btraces_sum(BigTraceArgs g) {
     for (int t = 0; t < Tn * Tn; ++t) s += g.part[((size_t)slice * Tn * Tn + t) * g.nb + j];
     g.gtrace[(size_t)(g.first_slice + slice) * g.nb + j] = s;
   }
+}
+
+__global__ void k_tile_flags(const cpx<double>* basis, int nb, int n, uint8_t* flags) {
+  __shared__ int any;
+  const int Tn = n / 64;
+  const int t = blockIdx.x, j = blockIdx.y;
+  const int ti = t / Tn, tj = t % Tn;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const cpx<double>* B = basis + (size_t)j * n * n + (size_t)ti * 64 * n + tj * 64;
+  int nz = 0;
+  for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+    const cpx<double> v = B[(size_t)(e / 64) * n + e % 64];
+    nz |= (v.re != 0.0 || v.im != 0.0);
+  }
+  if (nz) any = 1;   // benign race: every writer stores 1
+  __syncthreads();
+  if (threadIdx.x == 0) flags[(size_t)j * Tn * Tn + t] = (uint8_t)any;
+}
+
+hipError_t launch_tile_flags(const double* basis, int nb, int n, uint8_t* flags, hipStream_t s) {
+  const int Tn = n / 64;
+  hipLaunchKernelGGL(k_tile_flags, dim3(Tn * Tn, nb), dim3(256), 0, s, (const cpx<double>*)basis, nb, n,
+                     flags);
+  return hipGetLastError();
 }
 
 hipError_t launch_btraces(int prec, const BigTraceArgs& g, hipStream_t s) {

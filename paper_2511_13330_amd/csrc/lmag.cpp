@@ -70,6 +70,9 @@ struct lmag_ctx {
   double* basis64 = nullptr;
   void* basis32 = nullptr;
   void* sp_dev = nullptr;     // sparse basis tables (64 x 64 path), see build_sparse
+  int32_t* tile_lists = nullptr;   // block-tiled path: nonzero basis tiles per position
+  const int32_t* tile_ptr = nullptr;
+  const int32_t* tile_j = nullptr;
   SparseBasis sp{};
   // logical-subspace score of the current call (0: process fidelity)
   int score_kind = 0, score_L = 0;
@@ -606,6 +609,8 @@ size_t device_budget(lmag_ctx* c) {
 // over all slices (or over the active chunks of an ordered product step).
 struct BigPlan {
   std::vector<int32_t> chain_slice, chain_chunk, chain_off;      // forward step k: [off[k], off[k+1])
+  std::vector<int32_t> chain_zsrc, chain_zdst;                   // backward ping-pong indices (see run_big)
+  std::vector<int32_t> odd_chunks, odd_off;                      // chunks of odd length, per window
   std::vector<int32_t> scan_a, scan_b, scan_c, scan_off;         // per level, prefix then suffix
   std::vector<int32_t> copy_c, copy_off;                         // inactive entries per level
   std::vector<int32_t> env_suf_c, env_suf_next, env_nosuf_c;     // S_T^dag Suf_excl / S_T^dag
@@ -850,6 +855,15 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   q.C = C;
   // chain steps per window: step k advances the window's chunks longer than k
   // (window-local slice index, global chunk index)
+  // The chain products ping-pong between two per-chunk buffers instead of
+  // copying back after every step. Forward: step k reads buffer k & 1 and
+  // writes the other, so a chunk of length L ends in buffer L & 1 (chunks of
+  // odd length are copied to buffer 0 once, at the end). Backward: the chunk's
+  // suffix state starts in the environment array at its own last step; its
+  // buffer at step k alternates with the steps it has taken, (L - 1 - k) & 1,
+  // addressed through index lists into the adjacent environment (Lc + c) and
+  // spare (c) arrays.
+  q.odd_off.push_back(0);
   for (BigWindow& w : win) {
     w.koff = q.chain_off.size();
     q.chain_off.push_back((int32_t)q.chain_slice.size());
@@ -858,9 +872,15 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         if (chs[ci].count > k) {
           q.chain_slice.push_back(chs[ci].first + k - w.s0);
           q.chain_chunk.push_back(ci);
+          const bool in_env = ((chs[ci].count - 1 - k) & 1) == 0;
+          q.chain_zsrc.push_back(in_env ? Lc + ci : ci);
+          q.chain_zdst.push_back(in_env ? ci : Lc + ci);
         }
       q.chain_off.push_back((int32_t)q.chain_slice.size());
     }
+    for (int ci = w.c0; ci < w.c1; ++ci)
+      if (chs[ci].count & 1) q.odd_chunks.push_back(ci);
+    q.odd_off.push_back((int32_t)q.odd_chunks.size());
   }
   // scan levels: inclusive prefix P[c] = P[c] P[c - st]; suffix S[c] = S[c + st] S[c]
   q.scan_off.push_back(0);
@@ -916,7 +936,8 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
                o_ep = list(q.env_pre_c), o_epp = list(q.env_pre_prev), o_enp = list(q.env_nopre_c),
                o_est = list(q.env_suf_t), o_ent = list(q.env_nosuf_t),
                o_il = list(q.item_last_chunk), o_it = list(q.item_target),
-               o_is = list(q.item_src), o_id = list(q.ident);
+               o_is = list(q.item_src), o_id = list(q.ident), o_zs = list(q.chain_zsrc),
+               o_zd = list(q.chain_zdst), o_od = list(q.odd_chunks);
   BL = big_layout(c, o, Ns, Lc, (int)p.items.size(), W, nt, grad);
   L.meta_end = BL.meta_end;
   if (BL.total > budget)
@@ -1013,6 +1034,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     for (int pl = 0; pl < 3; ++pl) {
       BigOmegaArgs oa{};
       oa.n = n; oa.n_slices = Wn; oa.nb = c->nb; oa.basis = c->basis32;
+      oa.tile_ptr = c->tile_ptr; oa.tile_j = c->tile_j;
       oa.alpha = coef + pl * coef_plane; oa.omega = al[pl]; oa.part = (double*)at(BL.part);
       HIPCHK(launch_bomega(32, oa, s), "a_p");
     }
@@ -1042,6 +1064,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     int8_t* nlev_w = nlev_all + w.s0;
     BigOmegaArgs om{};
     om.n = n; om.n_slices = Wn; om.nb = c->nb; om.basis = c->basis32;
+    om.tile_ptr = c->tile_ptr; om.tile_j = c->tile_j;
     om.alpha = (const double*)at(BL.alpha) + (size_t)w.s0 * c->nb;
     om.omega = A; om.part = (double*)at(BL.part); om.ms = ms_w; om.nlev = nlev_w;
     for (int i = 0; i < 4; ++i) om.b3[i] = b3[i];
@@ -1151,11 +1174,15 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         if (cnt == 0) continue;
         const int32_t* sl = ip(o_cs) + a0;
         const int32_t* chn = ip(o_cc) + a0;
+        void* cur = Pc[k & 1];
+        void* nxt = Pc[(k + 1) & 1];
         if (store_ploc)
-          HIPCHK(axpby(cnt, Pc[0], chn, Pl, sl, 1.0, nullptr, nullptr, 0.0, 1.0), "store P_loc");
-        HIPCHK(gemmx(cnt, S, sl, Pc[0], chn, Pc[1], chn, 1.0, Pc[0], chn, 1.0, S, sl, 1.0), "chain");
-        HIPCHK(axpby(cnt, Pc[1], chn, Pc[0], chn, 1.0), "chain sync");
+          HIPCHK(axpby(cnt, cur, chn, Pl, sl, 1.0, nullptr, nullptr, 0.0, 1.0), "store P_loc");
+        HIPCHK(gemmx(cnt, S, sl, cur, chn, nxt, chn, 1.0, cur, chn, 1.0, S, sl, 1.0), "chain");
       }
+      const size_t wi = &w - win.data();
+      const int od0 = q.odd_off[wi], nod = q.odd_off[wi + 1] - od0;
+      if (nod) HIPCHK(axpby(nod, Pc[1], ip(o_od) + od0, Pc[0], ip(o_od) + od0, 1.0), "odd chunks");
     }
     return LMAG_OK;
   };
@@ -1245,15 +1272,15 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       {
         StageTimer t(c, 5, s);
         // backward chain: M_n = P_loc,n Z, Z <- Z S_n = Z + Z D_n (normal orientation)
-        void* Z[2] = {env, X};
+        void* Zb = X;   // X (index c) and env (index Lc + c) are adjacent arrays
         for (int k = C - 1; k >= 0; --k) {
           const int a0 = q.chain_off[w.koff + k], cnt = q.chain_off[w.koff + k + 1] - a0;
           if (cnt == 0) continue;
           const int32_t* sl = ip(o_cs) + a0;
-          const int32_t* chn = ip(o_cc) + a0;
-          HIPCHK(gemm(cnt, Pl, sl, Z[0], chn, Em, sl, 1.0), "M");
-          HIPCHK(gemm(cnt, Z[0], chn, S, sl, Z[1], chn, 1.0, Z[0], chn, 1.0), "Z");
-          HIPCHK(axpby(cnt, Z[1], chn, Z[0], chn, 1.0), "Z sync");
+          const int32_t* zs = ip(o_zs) + a0;
+          const int32_t* zd = ip(o_zd) + a0;
+          HIPCHK(gemm(cnt, Pl, sl, Zb, zs, Em, sl, 1.0), "M");
+          if (k > 0) HIPCHK(gemm(cnt, Zb, zs, S, sl, Zb, zd, 1.0, Zb, zs, 1.0), "Z");
         }
         // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
         HIPCHK(axpby(Wn, Em, nullptr, Em, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, ms_all + 2 * (size_t)w.s0),
@@ -1339,6 +1366,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           BigTraceArgs ta{};
           ta.n = n; ta.n_slices = Wn; ta.nb = c->nb; ta.first_slice = w.s0; ta.trans_basis = 1;
           ta.K = Ks[pl]; ta.basis = c->basis32; ta.part = (double*)at(BL.part);
+          ta.tile_ptr = c->tile_ptr; ta.tile_j = c->tile_j;
           ta.gtrace = (double*)at(BL.gtrace) + pl * coef_plane;
           HIPCHK(launch_btraces(32, ta, s), "traces");
         }
@@ -1542,6 +1570,7 @@ void lmag_destroy(lmag_ctx* c) {
   if (c->basis64) (void)hipFree(c->basis64);
   if (c->basis32) (void)hipFree(c->basis32);
   if (c->sp_dev) (void)hipFree(c->sp_dev);
+  if (c->tile_lists) (void)hipFree(c->tile_lists);
   if (c->logP_dev) (void)hipFree(c->logP_dev);
   if (c->dbg_scratch) (void)hipFree(c->dbg_scratch);
   if (c->clk_dev) (void)hipFree(c->clk_dev);
@@ -1604,9 +1633,13 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     if (c->basis64) (void)hipFree(c->basis64);
     if (c->basis32) (void)hipFree(c->basis32);
     if (c->sp_dev) (void)hipFree(c->sp_dev);
+    if (c->tile_lists) (void)hipFree(c->tile_lists);
     c->basis64 = nullptr;
     c->basis32 = nullptr;
     c->sp_dev = nullptr;
+    c->tile_lists = nullptr;
+    c->tile_ptr = nullptr;
+    c->tile_j = nullptr;
     c->sp = SparseBasis{};
     c->has_sys = false;
     const size_t nn = big ? (size_t)d * d * d * d : (size_t)TILE;   // elements per basis matrix
@@ -1665,7 +1698,39 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     }
     HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
     HIPCHK(hipDeviceSynchronize(), "set_system sync");
-    if (big) {   // the block-tiled path (FP32) reads only the FP32 copy
+    if (big) {
+      // the basis elements with a nonzero 64 x 64 tile, per tile position:
+      // the exponent assembly and the traces skip the all-zero tiles
+      const int Tn = d * d / 64;
+      const size_t nt = (size_t)Tn * Tn;
+      uint8_t* fl = nullptr;
+      std::vector<uint8_t> flh((size_t)nb * nt);
+      if (hipMalloc((void**)&fl, flh.size()) == hipSuccess) {
+        if (launch_tile_flags(c->basis64, nb, d * d, fl, st) == hipSuccess &&
+            hipMemcpy(flh.data(), fl, flh.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+          std::vector<int32_t> lists(nt + 1, 0);
+          for (size_t t = 0; t < nt; ++t)
+            for (int j = 0; j < nb; ++j)
+              if (flh[(size_t)j * nt + t]) lists.push_back(j);
+          int32_t pos = (int32_t)(nt + 1);
+          for (size_t t = 0; t < nt; ++t) {
+            lists[t] = pos - (int32_t)(nt + 1);
+            for (int j = 0; j < nb; ++j) pos += flh[(size_t)j * nt + t] ? 1 : 0;
+          }
+          lists[nt] = pos - (int32_t)(nt + 1);
+          if (hipMalloc((void**)&c->tile_lists, lists.size() * 4) == hipSuccess &&
+              hipMemcpy(c->tile_lists, lists.data(), lists.size() * 4, hipMemcpyHostToDevice) == hipSuccess) {
+            c->tile_ptr = c->tile_lists;
+            c->tile_j = c->tile_lists + nt + 1;
+          } else {
+            if (c->tile_lists) (void)hipFree(c->tile_lists);
+            c->tile_lists = nullptr;
+          }
+        }
+        (void)hipFree(fl);
+      }
+      (void)hipGetLastError();   // without the lists every tile is visited
+      // the block-tiled path (FP32) reads only the FP32 copy
       (void)hipFree(c->basis64);
       c->basis64 = nullptr;
     }
