@@ -290,3 +290,33 @@ def test_block_tiled_autotune_picks_a_kernel():
     F_ref, _ = oracle.fidelity(oracle.propagate(oracle_system(cfg).omegas(amps, cfg["dt"], 2, "foh")),
                                cfg["U_target"])
     assert abs(F.item() - F_ref) < 1e-6
+
+
+def test_four_spin_noise_groups_match_oracle_means():
+    """Block-tiled path with quasi-static noise: two candidates x two noise
+    samples (field offsets, control scales), grouped per candidate."""
+    cfg = synth.small_case(77, n_spins=4, n_slices=10, dt=2.5e-4)
+    rng = np.random.default_rng(5)
+    amps = [rounded(cfg["amps"], "f32"), rounded(rng.uniform(0, synth.A_MAX, (7, 3)), "f32")]
+    dB = rng.normal(0, 2 * np.pi, (2, 4))
+    eps = rng.normal(1, 0.01, (2, 3))
+    flat = np.concatenate(amps)
+    ns, off, static, scale, groups = [], [], [], [], []
+    for c, o in ((0, 0), (1, 10)):
+        for s in range(2):
+            ns.append(len(amps[c])); off.append(o); groups.append(c)
+            static.append(np.asarray(cfg["B"]) + dB[s]); scale.append(eps[s])
+    sysm = lib_system(cfg, "f32", 2, "foh", chunk=3)
+    F, g = sysm.fidelity_and_grad(torch.tensor(flat, dtype=torch.float32, device="cuda"), ns,
+                                  cfg["dt"], cfg["U_target"], slice_offset=off,
+                                  static_coef=np.array(static), ctrl_scale=np.array(scale),
+                                  groups=groups)
+    F = F.cpu().numpy(); g = g.cpu().numpy().astype(float)
+    for c, o in ((0, 0), (1, 10)):
+        Fs, gs = [], []
+        for s in range(2):
+            osys = oracle_system(cfg, eps=eps[s], dB=dB[s])
+            f, gk = oracle.grad_adjoint(osys, amps[c], cfg["dt"], 2, "foh", cfg["U_target"])
+            Fs.append(f); gs.append(gk)
+        assert abs(F[c] - np.mean(Fs)) < 1e-6
+        assert rel(g[o:o + len(amps[c])], np.mean(gs, axis=0)) < 1e-3

@@ -67,3 +67,35 @@ def test_order6_argument_checks():
         spin_chain_system(3, precision="f64", magnus_order=6, hold="foh")
     with pytest.raises(LmagError, match="INVALID"):
         spin_chain_system(3, precision="f32", magnus_order=4, hold="foh")
+
+
+def test_order6_noise_groups_and_recompute():
+    """Sixth order with quasi-static noise (field offsets and control scales),
+    two noise samples averaged as one group: the group mean of F and of the
+    gradient against the oracle; and the same call under a workspace budget
+    that forces slice windows (the adjoint re-runs the order-6 forward) is
+    bitwise equal to the stored call."""
+    cfg = synth.small_case(530, n_slices=12, dt=1e-3)
+    amps = rounded(cfg["amps"], "f32")
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    dB = np.array([[0.4, -1.3, 2.2], [-0.7, 0.9, 0.1]])
+    eps = np.array([[1.012, 0.994], [0.989, 1.007]])
+    static = np.asarray(cfg["B"])[None, :] + dB
+    out = []
+    for budget in (0, 5 << 20):
+        from paper_2511_13330_amd import spin_chain_system
+        sysm = spin_chain_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=6,
+                                 hold="foh", chunk_slices=3, workspace_bytes_max=budget)
+        F, g = sysm.fidelity_and_grad(a, [12, 12], cfg["dt"], cfg["U_target"], slice_offset=[0, 0],
+                                      static_coef=static, ctrl_scale=eps, groups=[0, 0])
+        out.append((F, g, sysm.last_plan()))
+    (Fs, gs, ps), (Fr, gr, pr) = out
+    assert ps["recompute"] == 0 and pr["recompute"] == 1 and pr["waves"] > 1
+    assert torch.equal(Fs, Fr) and torch.equal(gs, gr)
+    Fo, go = [], []
+    for k in range(2):
+        osys = oracle_system(cfg, eps=eps[k], dB=dB[k])
+        f, gk = oracle.grad_adjoint(osys, amps, cfg["dt"], 6, "foh", cfg["U_target"])
+        Fo.append(f); go.append(gk)
+    assert abs(Fs.item() - np.mean(Fo)) < 1e-6
+    assert rel(gs.cpu().numpy().astype(float), np.mean(go, axis=0)) < 1e-3
