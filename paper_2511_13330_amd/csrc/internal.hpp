@@ -255,9 +255,11 @@ struct BigGemmArgs {
   int transA, transB;
   const int8_t* pred; int pred_stride; int pred_thresh;   // active if pred[i*stride] > thresh
   int variant;   // FP32 product kernel (autotuned): 0 register-B tiles, 16x16x4 MFMA;
-                 // 1 quadrant per wave, 16x16x4; 2 quadrant per wave, 32x32x2
+                 // 1 quadrant per wave, 16x16x4; 2 quadrant per wave, 32x32x2;
+                 // 3 quadrant per wave, FP32 operands split into three bf16 pieces
+                 // on the 16x16x32 bf16 MFMA
 };
-constexpr int kBigGemmVariants = 3;
+constexpr int kBigGemmVariants = 4;
 constexpr int kBigGemmDefault = 0;   // product kernel of an untuned block-tiled call
 struct BigAxpbyArgs {
   int n, batch;

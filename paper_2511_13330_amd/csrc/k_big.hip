@@ -115,7 +115,25 @@ __device__ __forceinline__ void quad_stage(const f4 (&r)[8], cpx<float>* S, int 
   }
 }
 
-template <int SHAPE>
+// Split-bf16 products (variant 3): every FP32 operand value v is written as
+// three bfloat16 pieces v = v1 + v2 + v3 (v1 = bf16(v), v2 = bf16(v - v1),
+// v3 = bf16(v - v1 - v2); each difference is exact in FP32, so the pieces hold
+// all 24 significand bits), and a real product sum_k a_k b_k is formed from the
+// six cross terms a_i b_j with i + j <= 4 on v_mfma_f32_16x16x32_bf16
+// (products of bf16 pieces are exact, accumulation is FP32). The dropped terms
+// a_2 b_3, a_3 b_2, a_3 b_3 are below 2^-24 |a||b| relative: FP32-level error.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3(float v, bf16x8 (&p)[3], int i) {
+  const __bf16 h = (__bf16)v;
+  const float r1 = v - (float)h;
+  const __bf16 m = (__bf16)r1;
+  p[0][i] = h;
+  p[1][i] = m;
+  p[2][i] = (__bf16)(r1 - (float)m);
+}
+
+template <int SHAPE, bool SPLIT = false>
 __global__ void __launch_bounds__(WG) k_bgemm_q(BigGemmArgs g) {
   __shared__ QuadShared sh;
   const int Tn = g.n / 64;
@@ -158,7 +176,45 @@ __global__ void __launch_bounds__(WG) k_bgemm_q(BigGemmArgs g) {
       quad_fetch(ra, A + (tk + 1) * 64, g.n, tid);
       quad_fetch(rb, B + (size_t)(tk + 1) * 64 * g.n, g.n, tid);
     }
-    if constexpr (SHAPE == 16) {
+    if constexpr (SPLIT) {
+      // 16x16x32 bf16 MFMA: lane (gg, c) holds k = 32 kk + 8 gg + i, i = 0..7,
+      // of row c (A) and of column c (B); A and B agree on the k of each slot
+      const int gg = l >> 4, c = l & 15;
+      for (int kk = 0; kk < 2; ++kk) {
+        bf16x8 ap[NB][3][3], bp[NB][3][3];   // [block][operand][piece]
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = 32 * kk + 8 * gg + i;
+#pragma unroll
+          for (int x = 0; x < NB; ++x) {
+            const cpx<float> av = sh.a[(qi * 32 + x * 16 + c) * PITCH + k];
+            split3(av.re + av.im, ap[x][0], i);
+            split3(av.im, ap[x][1], i);
+            split3(av.re, ap[x][2], i);
+          }
+#pragma unroll
+          for (int y = 0; y < NB; ++y) {
+            const cpx<float> bv = sh.b[k * PITCH + qj * 32 + y * 16 + c];
+            split3(bv.re, bp[y][0], i);
+            split3(-(bv.re + bv.im), bp[y][1], i);
+            split3(bv.im - bv.re, bp[y][2], i);
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < NB; ++x)
+#pragma unroll
+          for (int y = 0; y < NB; ++y) {
+            // pieces (i, j) with i + j <= 4 (1-based): (1,1) (1,2) (2,1) (1,3) (3,1) (2,2)
+            constexpr int PI[6] = {0, 0, 1, 0, 2, 1}, PJ[6] = {0, 1, 0, 2, 0, 1};
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+              k1[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][0][PI[t]], bp[y][0][PJ[t]], k1[x][y], 0, 0, 0);
+              cr[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][1][PI[t]], bp[y][1][PJ[t]], cr[x][y], 0, 0, 0);
+              ci[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[x][2][PI[t]], bp[y][2][PJ[t]], ci[x][y], 0, 0, 0);
+            }
+          }
+      }
+    } else if constexpr (SHAPE == 16) {
       const int gg = l >> 4, c = l & 15;
 #pragma unroll 4
       for (int kk = 0; kk < 16; ++kk) {
@@ -230,6 +286,10 @@ hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s) {
   }
   if (prec == 32 && !g.transA && !g.transB && g.variant == 2) {
     hipLaunchKernelGGL(k_bgemm_q<32>, grid, dim3(WG), 0, s, g);
+    return hipGetLastError();
+  }
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 3) {
+    hipLaunchKernelGGL((k_bgemm_q<16, true>), grid, dim3(WG), 0, s, g);
     return hipGetLastError();
   }
 #define LMAG_BG(T, a, b) hipLaunchKernelGGL((k_bgemm<T, a, b>), grid, dim3(WG), 0, s, g)

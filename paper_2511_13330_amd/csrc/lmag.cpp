@@ -471,6 +471,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     int inv = c->inv_variant;
     if (inv == 0 && c->chunk <= 0)
       if (const auto* t = tuned_for(c, c->call_total > 0 ? c->call_total : p.total_slices)) inv = t->second;
+    if (inv < 0 || inv > 2) inv = 0;   // a line for a block-tiled key names a product kernel
     if (inv == 1) sa.nlev = nullptr;   // Gauss-Jordan for every slice
     sa.inv_mode = inv;
   }
@@ -1915,7 +1916,8 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     (void)hipEventCreate(&e1);
     double best = 1e300;
     int bestC = chunks[0], bestInv = 0;
-    for (int inv : {0, 1, 2}) {
+    const std::vector<int> variants = big ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0, 1, 2};
+    for (int inv : variants) {
       for (int C : chunks) {
         c->chunk = C;
         if (big) c->big_variant = inv;
@@ -1982,7 +1984,7 @@ lmag_status lmag_load_tuning(lmag_ctx* c, const char* path) {
     int C = 0, inv = 0;
     if ((std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"variant\": %d", key, &C, &inv) == 3 ||
          std::sscanf(line, " {\"key\": \"%127[^\"]\", \"chunk\": %d, \"inverse\": %d", key, &C, &inv) == 3) &&
-        C > 0 && inv >= 0 && inv <= 2) {
+        C > 0 && inv >= 0 && inv < kBigGemmVariants) {
       bool found = false;
       for (auto& t : c->tuned)
         if (t.first == key) { t.second = {C, inv}; found = true; }
