@@ -226,7 +226,9 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * loaded during the products, 16x16x4 MFMA; 2: as 1 with the 32x32x2 MFMA;
  * 3: as 1 with every FP32 operand split into three bfloat16 pieces and each
  * real product formed from the six leading cross terms on the 16x16x32 bf16
- * MFMA (FP32-level error) -- at the automatic chunk length, half and twice it. 64 x 64 systems: the
+ * MFMA (FP32-level error); 4: as 0 with two output tiles (eight waves) per
+ * workgroup sharing each staged A tile (n / 64 even) -- at the automatic chunk
+ * length, half and twice it. 64 x 64 systems: the
  * persistent slice kernels, for every candidate chunk length (slices per work
  * unit) and the inverse variants
  * of the Pade step (0: per slice the cheapest whose error bound holds -- in

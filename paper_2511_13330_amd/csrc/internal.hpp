@@ -257,9 +257,10 @@ struct BigGemmArgs {
   int variant;   // FP32 product kernel (autotuned): 0 register-B tiles, 16x16x4 MFMA;
                  // 1 quadrant per wave, 16x16x4; 2 quadrant per wave, 32x32x2;
                  // 3 quadrant per wave, FP32 operands split into three bf16 pieces
-                 // on the 16x16x32 bf16 MFMA
+                 // on the 16x16x32 bf16 MFMA; 4 as 0 with two output tiles (eight
+                 // waves) per workgroup sharing each staged A tile (n / 64 even)
 };
-constexpr int kBigGemmVariants = 4;
+constexpr int kBigGemmVariants = 5;
 constexpr int kBigGemmDefault = 0;   // product kernel of an untuned block-tiled call
 struct BigAxpbyArgs {
   int n, batch;

@@ -78,6 +78,64 @@ __global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
   rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
 }
 
+// Two output tiles per workgroup (variant 4; single precision, no transposes):
+// 512 threads, waves 0-3 compute tile (ti, 2p) and waves 4-7 tile (ti, 2p + 1).
+// The register-tile column of a lane is 16 w + c, so the second half's lanes
+// address columns 64..127 of the pair from the same base pointer. Each k-step's
+// A tile is loaded and staged in LDS once (by the first half) for both tiles.
+__global__ void __launch_bounds__(2 * WG) k_bgemm_pair(BigGemmArgs g) {
+  __shared__ BigShared<float> sh;
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  const int b = blockIdx.y, half = threadIdx.x >> 8;
+  const int ti = blockIdx.x / (Tn / 2), tj0 = 2 * (blockIdx.x % (Tn / 2));
+  const size_t base = (size_t)ti * 64 * g.n + tj0 * 64;
+  cpx<float>* C = const_cast<cpx<float>*>(mat<float>(g.C, g.Ci, b, nn));
+  const cpx<float>* D = g.D ? mat<float>(g.D, g.Di, b, nn) : nullptr;
+  const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
+  if (!active) {
+    const cpx<float>* src = D ? D : mat<float>(g.A, g.Ai, b, nn);
+    RT<float> X;
+    rt_load<float, false>(X, src + base, g.n);
+    rt_store<float, false>(X, C + base, g.n);
+    return;
+  }
+  const cpx<float>* A = mat<float>(g.A, g.Ai, b, nn);
+  const cpx<float>* B = mat<float>(g.B, g.Bi, b, nn);
+  RT<float> acc;
+  rt_zero(acc);
+  for (int tk = 0; tk < Tn; ++tk) {
+    RT<float> At, Bt;
+    if (half == 0) rt_load<float, false>(At, A + (size_t)ti * 64 * g.n + tk * 64, g.n);
+    rt_load<float, false>(Bt, B + (size_t)tk * 64 * g.n + tj0 * 64, g.n);
+    __syncthreads();
+    if (half == 0) rt_store<float, false>(At, sh.slot, PITCH);
+    __syncthreads();
+    gemm_acc<float, false, PITCH>(acc, sh.slot, Bt);
+  }
+  rt_scale(acc, (float)g.alpha);
+  if (D && g.beta != 0.0) {
+    RT<float> Dt;
+    rt_load<float, false>(Dt, D + base, g.n);
+    rt_axpy(acc, (float)g.beta, Dt);
+  }
+  if (g.D2 && g.beta2 != 0.0) {
+    RT<float> Dt;
+    rt_load<float, false>(Dt, mat<float>(g.D2, g.D2i, b, nn) + base, g.n);
+    rt_axpy(acc, (float)g.beta2, Dt);
+  }
+  if (g.gamma != 0.0 && ti == tj0 + half) {
+    // the diagonal of this half's own tile: row == column - 64 half
+    const Lane L;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (L.row<float>(q, r) == L.col - 64 * half) acc.re[q][r] += (float)g.gamma;
+  }
+  rt_store<float, false>(acc, C + base, g.n);
+}
+
 // Quadrant variants (single precision, no transposes): wave w of the
 // workgroup owns the 32 x 32 quadrant (w >> 1, w & 1) of the 64 x 64 output
 // tile. Both operand tiles of a k-step sit in LDS; every thread loads its share
@@ -280,6 +338,10 @@ hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s) {
   if (g.batch <= 0) return hipSuccess;
   const int Tn = g.n / 64;
   const dim3 grid(Tn * Tn, g.batch);
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 4 && Tn % 2 == 0) {
+    hipLaunchKernelGGL(k_bgemm_pair, dim3(Tn * Tn / 2, g.batch), dim3(2 * WG), 0, s, g);
+    return hipGetLastError();
+  }
   if (prec == 32 && !g.transA && !g.transB && g.variant == 1) {
     hipLaunchKernelGGL(k_bgemm_q<16>, grid, dim3(WG), 0, s, g);
     return hipGetLastError();

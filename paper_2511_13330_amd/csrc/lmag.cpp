@@ -1284,8 +1284,11 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           if (k > 0) HIPCHK(gemm(cnt, Zb, zs, S, sl, Zb, zd, 1.0, Zb, zs, 1.0), "Z");
         }
         // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
-        HIPCHK(axpby(Wn, Em, nullptr, Em, nullptr, 1.0, nullptr, nullptr, 0.0, 0.0, ms_all + 2 * (size_t)w.s0),
-               "E scale");
+        if (w.smax > 0) {   // E / 2^s on the slices with s > 0 (the first squaring list)
+          const int32_t* l0 = ip(BL.sq) + w.sq_base;
+          HIPCHK(axpby(w.sq_off[1], Em, l0, Em, l0, 1.0, nullptr, nullptr, 0.0, 0.0,
+                       ms_all + 2 * (size_t)w.s0), "E scale");
+        }
         const int32_t* L2 = ip(BL.mlist) + w.s0;
         const int32_t* L3 = L2 + w.n2;
         if (w.n3) {
@@ -1916,7 +1919,11 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     (void)hipEventCreate(&e1);
     double best = 1e300;
     int bestC = chunks[0], bestInv = 0;
-    const std::vector<int> variants = big ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0, 1, 2};
+    std::vector<int> variants{0, 1, 2};
+    if (big) {
+      variants.push_back(3);
+      if ((c->n / 64) % 2 == 0) variants.push_back(4);
+    }
     for (int inv : variants) {
       for (int C : chunks) {
         c->chunk = C;
