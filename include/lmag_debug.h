@@ -4,7 +4,8 @@
  * Not part of the propagator's interface (include/lmag.h): unit-test kernels
  * on single 64 x 64 tiles, used by the library's own tests to check the tile
  * product, the unpivoted inverse and the scaled Pade exponential in isolation,
- * and a per-phase cycle counter of the slice kernels used to place memory
+ * the block-tiled product kernels at any supported size, and a per-phase cycle
+ * counter of the slice kernels used to place memory
  * traffic inside the products. Same conventions and status codes as lmag.h.
  */
 #ifndef LMAG_DEBUG_H
@@ -32,6 +33,14 @@ lmag_status lmag_debug_tile_inverse(lmag_ctx *ctx, int precision, const void *A,
                                     void *hip_stream);
 lmag_status lmag_debug_tile_expm(lmag_ctx *ctx, int precision, const void *A, void *C,
                                  int8_t *ms_out, void *hip_stream);
+
+/* The block-tiled product kernels on their own: C_b = A_b B_b for b < batch,
+ * complex FP32 n x n matrices (n a multiple of 64, 64 <= n <= 4096), DEVICE
+ * pointers to batch contiguous row-major matrices each, C distinct from A and
+ * B. variant selects the product kernel as the autotuner does (0..6; a kernel
+ * whose shape condition fails runs kernel 0). Asynchronous on hip_stream. */
+lmag_status lmag_debug_block_gemm(lmag_ctx *ctx, int n, int batch, const void *A, const void *B,
+                                  void *C, int variant, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,8 @@ SIGNATURES = {
     "lmag_debug_tile_gemm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int,
                                      c_void_p]),
     "lmag_debug_tile_inverse": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "lmag_debug_block_gemm": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_int,
+                                      c_void_p]),
     "lmag_debug_tile_expm": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 

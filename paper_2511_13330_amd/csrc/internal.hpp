@@ -258,9 +258,12 @@ struct BigGemmArgs {
                  // 1 quadrant per wave, 16x16x4; 2 quadrant per wave, 32x32x2;
                  // 3 quadrant per wave, FP32 operands split into three bf16 pieces
                  // on the 16x16x32 bf16 MFMA; 4 as 0 with two output tiles (eight
-                 // waves) per workgroup sharing each staged A tile (n / 64 even)
+                 // waves) per workgroup sharing each staged A tile (n / 64 even);
+                 // 5 as 0 with every product's tiles on one XCD (n <= 1024);
+                 // 6 as 0 without the operand pipeline, three workgroups per CU;
+                 // 7 as 6 with every product's tiles on one XCD (n <= 1024)
 };
-constexpr int kBigGemmVariants = 5;
+constexpr int kBigGemmVariants = 8;
 constexpr int kBigGemmDefault = 0;   // product kernel of an untuned block-tiled call
 struct BigAxpbyArgs {
   int n, batch;

@@ -29,13 +29,28 @@ __device__ __forceinline__ const cpx<T>* mat(const void* base, const int32_t* id
 // C_b = alpha * op(A_b) op(B_b) + beta * D_b + beta2 * D2_b + gamma * I, for every batch entry
 // b with (pred == null or pred[b] != 0); other entries copy D_b (or A_b when
 // D is null) into C_b. op = transpose when the flag is set.
-template <typename T, bool TA, bool TB>
-__global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
-  __shared__ BigShared<T> sh;
+// XCD = true takes a one-dimensional grid of Tn^2 * batch workgroups (a
+// multiple of 8) and gives every product whole to one XCD: workgroups are
+// dispatched round-robin over the eight XCDs, so hardware slot L runs on XCD
+// L mod 8 and is given product tile (L mod 8) * (grid / 8) + L / 8. An XCD then
+// works through consecutive products, each one's operand tiles fetched into its
+// own L2 once and re-read there by the product's other output tiles.
+template <typename T, bool TA, bool TB, bool XCD, bool PIPE>
+__device__ __forceinline__ void bgemm_body(const BigGemmArgs& g, BigShared<T>& sh) {
   const int Tn = g.n / 64;
   const size_t nn = (size_t)g.n * g.n;
-  const int b = blockIdx.y;
-  const int ti = blockIdx.x / Tn, tj = blockIdx.x % Tn;
+  int b, ti, tj;
+  if constexpr (XCD) {
+    const int L = blockIdx.x, per = gridDim.x / 8;
+    const int logical = (L % 8) * per + L / 8;
+    b = logical / (Tn * Tn);
+    ti = (logical % (Tn * Tn)) / Tn;
+    tj = logical % Tn;
+  } else {
+    b = blockIdx.y;
+    ti = blockIdx.x / Tn;
+    tj = blockIdx.x % Tn;
+  }
   cpx<T>* C = const_cast<cpx<T>*>(mat<T>(g.C, g.Ci, b, nn));
   const cpx<T>* D = g.D ? mat<T>(g.D, g.Di, b, nn) : nullptr;
   const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
@@ -55,12 +70,20 @@ __global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
     RT<T> At, Bt;
     if (TA) rt_load<T, true>(At, A + (size_t)tk * 64 * g.n + ti * 64, g.n);
     else rt_load<T, false>(At, A + (size_t)ti * 64 * g.n + tk * 64, g.n);
-    if (TB) rt_load<T, true>(Bt, B + (size_t)tj * 64 * g.n + tk * 64, g.n);
-    else rt_load<T, false>(Bt, B + (size_t)tk * 64 * g.n + tj * 64, g.n);
+    // without the pipeline (fewer registers) the B tile is fetched after the
+    // A tile has gone to LDS, so that the two are never live together
+    if (PIPE) {
+      if (TB) rt_load<T, true>(Bt, B + (size_t)tj * 64 * g.n + tk * 64, g.n);
+      else rt_load<T, false>(Bt, B + (size_t)tk * 64 * g.n + tj * 64, g.n);
+    }
     __syncthreads();
     rt_store<T, false>(At, sh.slot, PITCH);
+    if (!PIPE) {
+      if (TB) rt_load<T, true>(Bt, B + (size_t)tj * 64 * g.n + tk * 64, g.n);
+      else rt_load<T, false>(Bt, B + (size_t)tk * 64 * g.n + tj * 64, g.n);
+    }
     __syncthreads();
-    gemm_acc<T, false, PITCH>(acc, sh.slot, Bt);
+    gemm_acc<T, false, PITCH, PIPE>(acc, sh.slot, Bt);
   }
   const T al = (T)g.alpha;
   rt_scale(acc, al);
@@ -76,6 +99,23 @@ __global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
   }
   if (g.gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.gamma);
   rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
+}
+
+template <typename T, bool TA, bool TB, bool XCD = false>
+__global__ void __launch_bounds__(WG) k_bgemm(BigGemmArgs g) {
+  __shared__ BigShared<T> sh;
+  bgemm_body<T, TA, TB, XCD, true>(g, sh);
+}
+
+// Three resident workgroups per CU (three waves per SIMD, at most 168
+// registers): the k-step loads of one workgroup hide behind the products of
+// two others; the A operands are read from LDS without the software pipeline
+// of the two-workgroup kernel, which needs more registers.
+template <bool XCD>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3)))
+k_bgemm_occ3(BigGemmArgs g) {
+  __shared__ BigShared<float> sh;
+  bgemm_body<float, false, false, XCD, false>(g, sh);
 }
 
 // Two output tiles per workgroup (variant 4; single precision, no transposes):
@@ -340,6 +380,20 @@ hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s) {
   const dim3 grid(Tn * Tn, g.batch);
   if (prec == 32 && !g.transA && !g.transB && g.variant == 4 && Tn % 2 == 0) {
     hipLaunchKernelGGL(k_bgemm_pair, dim3(Tn * Tn / 2, g.batch), dim3(2 * WG), 0, s, g);
+    return hipGetLastError();
+  }
+  const bool xcd_ok = Tn <= 16 && ((size_t)Tn * Tn * g.batch) % 8 == 0 &&
+                      (size_t)Tn * Tn * g.batch <= 0x7fffffff;
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 7 && xcd_ok) {
+    hipLaunchKernelGGL(k_bgemm_occ3<true>, dim3(Tn * Tn * g.batch), dim3(WG), 0, s, g);
+    return hipGetLastError();
+  }
+  if (prec == 32 && !g.transA && !g.transB && (g.variant == 6 || g.variant == 7)) {
+    hipLaunchKernelGGL(k_bgemm_occ3<false>, grid, dim3(WG), 0, s, g);
+    return hipGetLastError();
+  }
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 5 && xcd_ok) {
+    hipLaunchKernelGGL((k_bgemm<float, false, false, true>), dim3(Tn * Tn * g.batch), dim3(WG), 0, s, g);
     return hipGetLastError();
   }
   if (prec == 32 && !g.transA && !g.transB && g.variant == 1) {

@@ -1923,6 +1923,11 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     if (big) {
       variants.push_back(3);
       if ((c->n / 64) % 2 == 0) variants.push_back(4);
+      variants.push_back(6);
+      if (c->n / 64 <= 16) {
+        variants.push_back(5);
+        variants.push_back(7);
+      }
     }
     for (int inv : variants) {
       for (int C : chunks) {
@@ -2244,6 +2249,21 @@ lmag_status lmag_debug_tile_gemm(lmag_ctx* c, int precision, const void* A, cons
   if (precision != LMAG_F32 && precision != LMAG_F64) return c->fail(LMAG_E_INVALID, "precision");
   DeviceGuard g(c->device);
   HIPCHK(launch_debug_gemm(precision, A, B, C, transA, (hipStream_t)hip_stream), "debug_gemm");
+  return LMAG_OK;
+}
+
+lmag_status lmag_debug_block_gemm(lmag_ctx* c, int n, int batch, const void* A, const void* B, void* C,
+                                  int variant, void* hip_stream) {
+  if (!c) return LMAG_E_INVALID;
+  if (!A || !B || !C) return c->fail(LMAG_E_INVALID, "NULL matrix");
+  if (n < 64 || n > 4096 || n % 64 != 0) return c->fail(LMAG_E_INVALID, "n must be a multiple of 64 in [64, 4096]");
+  if (batch < 0) return c->fail(LMAG_E_INVALID, "batch < 0");
+  if (variant < 0 || variant >= kBigGemmVariants) return c->fail(LMAG_E_INVALID, "product kernel variant");
+  if (C == A || C == B) return c->fail(LMAG_E_INVALID, "C must not alias A or B");
+  DeviceGuard g(c->device);
+  BigGemmArgs a{};
+  a.n = n; a.batch = batch; a.A = A; a.B = B; a.C = C; a.alpha = 1.0; a.variant = variant;
+  HIPCHK(launch_bgemm(32, a, (hipStream_t)hip_stream), "debug block gemm");
   return LMAG_OK;
 }
 

@@ -279,6 +279,21 @@ class System:
                                          int(transA), _stream(None)), self._ctx)
         return C
 
+    def debug_block_gemm(self, A, B, variant=0):
+        """C[b] = A[b] @ B[b] for complex64 tensors of shape (batch, n, n) by the
+        block-tiled product kernel `variant`."""
+        if A.dtype != torch.complex64 or B.dtype != torch.complex64:
+            raise TypeError("complex64 operands expected")
+        if A.dim() != 3 or A.shape != B.shape or A.shape[1] != A.shape[2]:
+            raise ValueError("operands of shape (batch, n, n) expected")
+        A, B = A.contiguous(), B.contiguous()
+        C = torch.empty_like(A)
+        check(lib().lmag_debug_block_gemm(self._ctx, int(A.shape[1]), int(A.shape[0]),
+                                          ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                          ctypes.c_void_p(C.data_ptr()), int(variant), _stream(None)),
+              self._ctx)
+        return C
+
     def debug_tile_inverse(self, A, precision=None):
         precision = precision or self.precision
         C = torch.empty_like(A)

@@ -60,3 +60,18 @@ def test_tile_expm(ctx_system, prec, norm, m, s):
     err = np.linalg.norm(C.cpu().numpy() - ref) / np.linalg.norm(ref)
     assert tuple(ms.cpu().numpy().tolist()) == (m, s)
     assert err < (20 * TOL[prec] * (1 + s)), err
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("n,batch", [(128, 3), (256, 5), (1024, 2), (4096, 1)])
+def test_block_product_kernels(ctx_system, variant, n, batch):
+    """Every block-tiled product kernel against an FP64 product of the same
+    FP32 inputs (a kernel whose shape condition fails runs kernel 0)."""
+    g = torch.Generator(device="cuda").manual_seed(1000 + n + variant)
+    A = torch.randn(batch, n, n, dtype=torch.complex64, device="cuda", generator=g)
+    B = torch.randn(batch, n, n, dtype=torch.complex64, device="cuda", generator=g)
+    C = ctx_system.debug_block_gemm(A, B, variant=variant)
+    ref = torch.matmul(A.to(torch.complex128), B.to(torch.complex128))
+    err = (torch.linalg.matrix_norm(C.to(torch.complex128) - ref) / torch.linalg.matrix_norm(ref)).max().item()
+    # FP32 accumulation over n terms: about sqrt(n) u relative (u = 6e-8)
+    assert err < 4e-8 * np.sqrt(n) * 4, err
