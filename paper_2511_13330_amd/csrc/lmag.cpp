@@ -612,6 +612,8 @@ struct BigPlan {
   std::vector<int32_t> chain_slice, chain_chunk, chain_off;      // forward step k: [off[k], off[k+1])
   std::vector<int32_t> chain_zsrc, chain_zdst;                   // backward ping-pong indices (see run_big)
   std::vector<int32_t> odd_chunks, odd_off;                      // chunks of odd length, per window
+  std::vector<int32_t> pl_cont_slice, pl_cont_next, pl_cont_off;  // forward step k, P_loc kept per
+  std::vector<int32_t> pl_end_slice, pl_end_chunk, pl_end_off;    // slice (see run_big)
   std::vector<int32_t> scan_a, scan_b, scan_c, scan_off;         // per level, prefix then suffix
   std::vector<int32_t> copy_c, copy_off;                         // inactive entries per level
   std::vector<int32_t> env_suf_c, env_suf_next, env_nosuf_c;     // S_T^dag Suf_excl / S_T^dag
@@ -864,20 +866,37 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
   // buffer at step k alternates with the steps it has taken, (L - 1 - k) & 1,
   // addressed through index lists into the adjacent environment (Lc + c) and
   // spare (c) arrays.
+  // Where every slice's P_loc is kept (the adjoint's forward), step k instead
+  // reads the P_loc - I of each chunk's k-th slice and writes that of its next
+  // slice in place, or the chunk total at the chunk's last slice: no buffers
+  // and no copies. pl_* hold those two lists per step (offsets parallel to
+  // chain_off).
   q.odd_off.push_back(0);
   for (BigWindow& w : win) {
     w.koff = q.chain_off.size();
     q.chain_off.push_back((int32_t)q.chain_slice.size());
+    q.pl_cont_off.push_back((int32_t)q.pl_cont_slice.size());
+    q.pl_end_off.push_back((int32_t)q.pl_end_slice.size());
     for (int k = 0; k < C; ++k) {
       for (int ci = w.c0; ci < w.c1; ++ci)
         if (chs[ci].count > k) {
-          q.chain_slice.push_back(chs[ci].first + k - w.s0);
+          const int sl = chs[ci].first + k - w.s0;
+          q.chain_slice.push_back(sl);
           q.chain_chunk.push_back(ci);
           const bool in_env = ((chs[ci].count - 1 - k) & 1) == 0;
           q.chain_zsrc.push_back(in_env ? Lc + ci : ci);
           q.chain_zdst.push_back(in_env ? ci : Lc + ci);
+          if (chs[ci].count > k + 1) {
+            q.pl_cont_slice.push_back(sl);
+            q.pl_cont_next.push_back(sl + 1);
+          } else {
+            q.pl_end_slice.push_back(sl);
+            q.pl_end_chunk.push_back(ci);
+          }
         }
       q.chain_off.push_back((int32_t)q.chain_slice.size());
+      q.pl_cont_off.push_back((int32_t)q.pl_cont_slice.size());
+      q.pl_end_off.push_back((int32_t)q.pl_end_slice.size());
     }
     for (int ci = w.c0; ci < w.c1; ++ci)
       if (chs[ci].count & 1) q.odd_chunks.push_back(ci);
@@ -938,7 +957,9 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
                o_est = list(q.env_suf_t), o_ent = list(q.env_nosuf_t),
                o_il = list(q.item_last_chunk), o_it = list(q.item_target),
                o_is = list(q.item_src), o_id = list(q.ident), o_zs = list(q.chain_zsrc),
-               o_zd = list(q.chain_zdst), o_od = list(q.odd_chunks);
+               o_zd = list(q.chain_zdst), o_od = list(q.odd_chunks),
+               o_pcs = list(q.pl_cont_slice), o_pcn = list(q.pl_cont_next),
+               o_pes = list(q.pl_end_slice), o_pec = list(q.pl_end_chunk);
   BL = big_layout(c, o, Ns, Lc, (int)p.items.size(), W, nt, grad);
   L.meta_end = BL.meta_end;
   if (BL.total > budget)
@@ -1151,10 +1172,12 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         // Pade 2 by its power series cut at degree 4 (the degree-4 Taylor
         // polynomial): D = A + A^2 (I/2 + A/6 + A^2/24); s = 0 at this degree
         const int n2 = w.n2;
+        // (no squarings at this degree and the adjoint reads neither R0 nor a
+        // second copy of D here: D goes straight to S; T1 = W stays for the
+        // adjoint)
         HIPCHK(gemm(n2, A, L2, A, L2, A2, L2, 1.0), "A2");
-        HIPCHK(axpby(n2, A, L2, T1, L2, 1.0 / 6.0, A2, L2, 1.0 / 24.0, 0.5), "I/2 + A/6 + A2/24");
-        HIPCHK(gemm(n2, A2, L2, T1, L2, R0, L2, 1.0, A, L2, 1.0), "D");
-        HIPCHK(axpby(n2, R0, L2, S, L2, 1.0), "S");
+        HIPCHK(axpby(n2, A, L2, T1, L2, 1.0 / 6.0, A2, L2, 1.0 / 24.0, 0.5), "W = I/2 + A/6 + A2/24");
+        HIPCHK(gemm(n2, A2, L2, T1, L2, S, L2, 1.0, A, L2, 1.0), "D");
       }
       // (I + D)^2 = I + 2 D + D^2
       for (int k = 0; k < w.smax; ++k) {
@@ -1167,6 +1190,25 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     }
     // ordered products inside the window's chunks, kept as M - I:
     // (I + D)(I + Q) - I = Q + D + D Q
+    if (store_ploc) {
+      // every slice's P_loc - I in place (Pl), the chunk totals into Pc[0]
+      StageTimer t(c, 2, s);
+      const int f0 = q.chain_off[w.koff], nf = q.chain_off[w.koff + 1] - f0;
+      HIPCHK(axpby(nf, Pl, ip(o_cs) + f0, Pl, ip(o_cs) + f0, 0.0), "P_loc - I = 0");
+      for (int k = 0; k < C; ++k) {
+        const int a0 = q.pl_cont_off[w.koff + k], na = q.pl_cont_off[w.koff + k + 1] - a0;
+        const int e0 = q.pl_end_off[w.koff + k], ne = q.pl_end_off[w.koff + k + 1] - e0;
+        if (na) {
+          const int32_t* sl = ip(o_pcs) + a0;
+          HIPCHK(gemmx(na, S, sl, Pl, sl, Pl, ip(o_pcn) + a0, 1.0, Pl, sl, 1.0, S, sl, 1.0), "chain");
+        }
+        if (ne) {
+          const int32_t* sl = ip(o_pes) + e0;
+          HIPCHK(gemmx(ne, S, sl, Pl, sl, Pc[0], ip(o_pec) + e0, 1.0, Pl, sl, 1.0, S, sl, 1.0), "chain end");
+        }
+      }
+      return LMAG_OK;
+    }
     {
       StageTimer t(c, 2, s);
       HIPCHK(axpby(w.c1 - w.c0, Pc[0], ip(o_id) + w.c0, Pc[0], ip(o_id) + w.c0, 0.0), "P - I = 0");
@@ -1177,8 +1219,6 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         const int32_t* chn = ip(o_cc) + a0;
         void* cur = Pc[k & 1];
         void* nxt = Pc[(k + 1) & 1];
-        if (store_ploc)
-          HIPCHK(axpby(cnt, cur, chn, Pl, sl, 1.0, nullptr, nullptr, 0.0, 1.0), "store P_loc");
         HIPCHK(gemmx(cnt, S, sl, cur, chn, nxt, chn, 1.0, cur, chn, 1.0, S, sl, 1.0), "chain");
       }
       const size_t wi = &w - win.data();
@@ -1280,7 +1320,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           const int32_t* sl = ip(o_cs) + a0;
           const int32_t* zs = ip(o_zs) + a0;
           const int32_t* zd = ip(o_zd) + a0;
-          HIPCHK(gemm(cnt, Pl, sl, Zb, zs, Em, sl, 1.0), "M");
+          HIPCHK(gemm(cnt, Pl, sl, Zb, zs, Em, sl, 1.0, Zb, zs, 1.0), "M");   // (I + Pl) Z
           if (k > 0) HIPCHK(gemm(cnt, Zb, zs, S, sl, Zb, zd, 1.0, Zb, zs, 1.0), "Z");
         }
         // Frechet derivative of the scaled Pade approximant at A in direction E = M / 2^s
@@ -1309,11 +1349,12 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           // derivative of the degree-4 polynomial A + A^2/2 + A^3/6 + A^4/24:
           // K = E + L2/2 + L2 (A/6 + A^2/24) + A^2 (E/6 + L2/24), L2 = A E + E A
           const int n2 = w.n2;
-          HIPCHK(gemm(n2, A, L2, Em, L2, T1, L2, 1.0), "AE");
-          HIPCHK(gemm(n2, Em, L2, A, L2, T1, L2, 1.0, T1, L2, 1.0), "L2");                    // T1 = L2
-          HIPCHK(axpby(n2, A, L2, T2, L2, 1.0 / 6.0, A2, L2, 1.0 / 24.0), "A/6 + A2/24");
-          HIPCHK(gemmx(n2, T1, L2, T2, L2, T4, L2, 1.0, Em, L2, 1.0, T1, L2, 0.5), "E + L2/2 + L2 (.)");
-          HIPCHK(axpby(n2, Em, L2, T2, L2, 1.0 / 6.0, T1, L2, 1.0 / 24.0), "E/6 + L2/24");
+          // with W = I/2 + A/6 + A^2/24 (T1, kept from the forward):
+          // K = E + L2 W + A^2 (E/6 + L2/24)
+          HIPCHK(gemm(n2, A, L2, Em, L2, T3, L2, 1.0), "AE");
+          HIPCHK(gemm(n2, Em, L2, A, L2, T3, L2, 1.0, T3, L2, 1.0), "L2");                    // T3 = L2
+          HIPCHK(gemm(n2, T3, L2, T1, L2, T4, L2, 1.0, Em, L2, 1.0), "E + L2 W");
+          HIPCHK(axpby(n2, Em, L2, T2, L2, 1.0 / 6.0, T3, L2, 1.0 / 24.0), "E/6 + L2/24");
           HIPCHK(gemm(n2, A2, L2, T2, L2, T3, L2, 1.0, T4, L2, 1.0), "K");                    // T3 = K
         }
         // squaring recurrence K <- R K + K R = 2 K + D K + K D, D <- 2 D + D D for the

@@ -323,3 +323,29 @@ def test_four_spin_noise_groups_match_oracle_means():
             Fs.append(f); gs.append(gk)
         assert abs(F[c] - np.mean(Fs)) < 1e-6
         assert rel(g[o:o + len(amps[c])], np.mean(gs, axis=0)) < 1e-3
+
+
+def test_block_tiled_output_at_unaligned_address():
+    """The propagator written to a caller's buffer that starts 8 bytes past a
+    16-byte boundary (the elementwise kernels then take their one-element
+    path) equals the one written to an aligned buffer, bit for bit."""
+    import ctypes
+    from paper_2511_13330_amd._lib import lib, check
+    cfg = synth.small_case(77, n_spins=4, n_slices=5, dt=2.5e-4)
+    amps = rounded(cfg["amps"], "f32")
+    sysm = lib_system(cfg, "f32", 2, "foh")
+    a = torch.tensor(amps, dtype=torch.float32, device="cuda")
+    st = np.asarray(cfg["B"])[None, :]
+    U = sysm.propagate(a, [5], cfg["dt"], static_coef=st)
+    b, keep, n_items, _ = sysm._batch(a, [5], None, cfg["dt"], st, None, None)
+    n = U.shape[-1]
+    buf = torch.zeros(n * n + 1, dtype=torch.complex64, device="cuda")
+    view = buf[1:]
+    assert view.data_ptr() % 16 == 8
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(lib().lmag_propagate(sysm._ctx, ctypes.byref(b), ctypes.c_void_p(view.data_ptr()), stream),
+          sysm._ctx)
+    del keep
+    torch.cuda.synchronize()
+    assert torch.equal(view.view(1, n, n), U)
+    assert buf[0].item() == 0
