@@ -238,6 +238,9 @@ hipError_t launch_cast_bf16(const float* in, uint16_t* out, int64_t n, hipStream
 
 // block-tiled path (n = 64 T)
 constexpr int MAX_BIG_NB = 64;
+// consecutive slices per workgroup in the basis assembly and trace kernels of
+// the block-tiled path (each basis tile is fetched once for all of them)
+constexpr int kBigSlicesPerGroup = 4;
 // Block-tiled path: Neumann levels of the Pade-3 denominator inverse (the
 // single-precision bound of neumann_levels; a slice whose bound does not hold
 // takes all of them) and the largest supported scaling exponent.

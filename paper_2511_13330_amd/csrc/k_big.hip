@@ -535,41 +535,55 @@ hipError_t launch_baxpby(int prec, const BigAxpbyArgs& g, hipStream_t s) {
 
 // Omega_n = sum_j alpha_{n,j} B_j tile by tile; partial FP64 column 1-norms of
 // every 64-row block: part[slice][tile_row][col].
-template <typename T>
+template <typename T, int S>
 __global__ void __launch_bounds__(WG) k_bomega(BigOmegaArgs g) {
   const int Tn = g.n / 64;
   const size_t nn = (size_t)g.n * g.n;
-  const int slice = blockIdx.y;
+  const int s0 = blockIdx.y * S;
   const int ti = blockIdx.x / Tn, tj = blockIdx.x % Tn;
   const cpx<T>* basis = (const cpx<T>*)g.basis;
-  const double* al = g.alpha + (size_t)slice * g.nb;
-  RT<T> X;
-  rt_zero(X);
+  // S consecutive slices per workgroup: each basis tile is fetched once for all S
+  RT<T> X[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) rt_zero(X[q]);
   const int t = blockIdx.x;
   const int j0 = g.tile_ptr ? g.tile_ptr[t] : 0, j1 = g.tile_ptr ? g.tile_ptr[t + 1] : g.nb;
   for (int e = j0; e < j1; ++e) {
     const int j = g.tile_ptr ? g.tile_j[e] : e;
-    const double aj = al[j];
-    if (aj == 0.0) continue;
+    double aj[S];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      aj[q] = s0 + q < g.n_slices ? g.alpha[(size_t)(s0 + q) * g.nb + j] : 0.0;
+      any |= aj[q] != 0.0;
+    }
+    if (!any) continue;
     RT<T> Bt;
     rt_load<T, false>(Bt, basis + (size_t)j * nn + (size_t)ti * 64 * g.n + tj * 64, g.n);
-    rt_axpy(X, (T)aj, Bt);
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (aj[q] != 0.0) rt_axpy(X[q], (T)aj[q], Bt);
   }
-  cpx<T>* out = (cpx<T>*)g.omega + (size_t)slice * nn;
-  rt_store<T, false>(X, out + (size_t)ti * 64 * g.n + tj * 64, g.n);
-  // column sums of |X| over this tile's 64 rows
   const Lane L;
-  double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < S; ++q) {
+    const int slice = s0 + q;
+    if (slice >= g.n_slices) break;
+    cpx<T>* out = (cpx<T>*)g.omega + (size_t)slice * nn;
+    rt_store<T, false>(X[q], out + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    // column sums of |X| over this tile's 64 rows
+    double sum = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double a = (double)X.re[q][r], b = (double)X.im[q][r];
-      s += sqrt(a * a + b * b);
-    }
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  if (L.g == 0) g.part[((size_t)slice * Tn + ti) * g.n + tj * 64 + L.col] = s;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double u = (double)X[q].re[a][r], v = (double)X[q].im[a][r];
+        sum += sqrt(u * u + v * v);
+      }
+    sum += __shfl_xor(sum, 16);
+    sum += __shfl_xor(sum, 32);
+    if (L.g == 0) g.part[((size_t)slice * Tn + ti) * g.n + tj * 64 + L.col] = sum;
+  }
 }
 
 // Per slice: ||Omega||_1 from the partial column sums, (m, s) and Neumann
@@ -646,11 +660,13 @@ __global__ void __launch_bounds__(WG) k_bcolsum(BigOmegaArgs g) {
 hipError_t launch_bomega(int prec, const BigOmegaArgs& g, hipStream_t s) {
   if (g.n_slices <= 0) return hipSuccess;
   const int Tn = g.n / 64;
+  constexpr int S = kBigSlicesPerGroup;
+  const dim3 grid(Tn * Tn, (g.n_slices + S - 1) / S);
   if (prec == 32) {
-    hipLaunchKernelGGL(k_bomega<float>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+    hipLaunchKernelGGL((k_bomega<float, S>), grid, dim3(WG), 0, s, g);
     if (g.ms) hipLaunchKernelGGL(k_bnorm<float>, dim3(g.n_slices), dim3(256), 0, s, g);
   } else {
-    hipLaunchKernelGGL(k_bomega<double>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+    hipLaunchKernelGGL((k_bomega<double, S>), grid, dim3(WG), 0, s, g);
     if (g.ms) hipLaunchKernelGGL(k_bnorm<double>, dim3(g.n_slices), dim3(256), 0, s, g);
   }
   return hipGetLastError();
@@ -673,45 +689,71 @@ hipError_t launch_bnorm_dense(int prec, const BigOmegaArgs& g, hipStream_t s) {
 
 // g[slice][j] = Re sum_x K^T[x] B_j[x]: partial sums per (slice, tile) in
 // part[slice][tile][j], then a fixed-order reduction over tiles.
-template <typename T>
+template <typename T, int S>
 __global__ void __launch_bounds__(WG) k_btraces_part(BigTraceArgs g) {
-  __shared__ double red[4][MAX_BIG_NB];
+  __shared__ BigShared<T> sh;
+  __shared__ double red[4][S][MAX_BIG_NB];
   const int Tn = g.n / 64;
   const size_t nn = (size_t)g.n * g.n;
-  const int slice = blockIdx.y, tile = blockIdx.x;
+  const int s0 = blockIdx.y * S, tile = blockIdx.x;
   const int ti = tile / Tn, tj = tile % Tn;
-  const cpx<T>* K = (const cpx<T>*)g.K + (size_t)slice * nn;
   const cpx<T>* basis = (const cpx<T>*)g.basis;
   const Lane L;
-  // the basis tile read here sits at (tj, ti) when the basis is read transposed
+  // Re Tr(K B_j) over this tile = Re sum_{a,b} K[a][b] B_j[b][a] (a in row block
+  // ti, b in column block tj): with trans_basis the K tile is transposed once
+  // through LDS and paired with the untransposed basis tile (tj, ti), whose
+  // rows the lanes then read contiguously; otherwise K and B_j pair as stored
   const int bt = g.trans_basis ? tj * Tn + ti : tile;
-  for (int j = threadIdx.x; j < g.nb; j += WG) {
-    red[0][j] = 0.0; red[1][j] = 0.0; red[2][j] = 0.0; red[3][j] = 0.0;
+  for (int e = threadIdx.x; e < 4 * S * g.nb; e += WG) (&red[0][0][0])[(e / g.nb) * MAX_BIG_NB + e % g.nb] = 0.0;
+  const int j0 = g.tile_ptr ? g.tile_ptr[bt] : 0, j1 = g.tile_ptr ? g.tile_ptr[bt + 1] : g.nb;
+  RT<T> Kt[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    if (j1 > j0 && s0 + q < g.n_slices) {
+      const cpx<T>* K = (const cpx<T>*)g.K + (size_t)(s0 + q) * nn + (size_t)ti * 64 * g.n + tj * 64;
+      if (g.trans_basis) {
+        RT<T> X;
+        rt_load<T, false>(X, K, g.n);
+        __syncthreads();
+        rt_store<T, false>(X, sh.slot, PITCH);
+        __syncthreads();
+        rt_load<T, true>(Kt[q], sh.slot, PITCH);
+      } else {
+        rt_load<T, false>(Kt[q], K, g.n);
+      }
+    } else {
+      rt_zero(Kt[q]);
+    }
   }
   __syncthreads();
-  const int j0 = g.tile_ptr ? g.tile_ptr[bt] : 0, j1 = g.tile_ptr ? g.tile_ptr[bt + 1] : g.nb;
-  RT<T> Kt;
-  if (j1 > j0) rt_load<T, false>(Kt, K + (size_t)ti * 64 * g.n + tj * 64, g.n);
   for (int e = j0; e < j1; ++e) {
     const int j = g.tile_ptr ? g.tile_j[e] : e;
     RT<T> Bt;
-    // same positions as K^T; with trans_basis the basis is read transposed
-    // (Re Tr(K B_j) = Re sum_{a,b} K[a][b] B_j[b][a] for a K stored untransposed)
-    if (g.trans_basis) rt_load<T, true>(Bt, basis + (size_t)j * nn + (size_t)tj * 64 * g.n + ti * 64, g.n);
-    else rt_load<T, false>(Bt, basis + (size_t)j * nn + (size_t)ti * 64 * g.n + tj * 64, g.n);
-    double acc = 0.0;
+    rt_load<T, false>(Bt, basis + (size_t)j * nn + (size_t)(bt / Tn) * 64 * g.n + (bt % Tn) * 64, g.n);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < S; ++q) {
+      // a lane's 16 terms in the compute precision, the sums over lanes and
+      // tiles in FP64
+      T part = T(0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        acc += (double)Kt.re[q][r] * (double)Bt.re[q][r] - (double)Kt.im[q][r] * (double)Bt.im[q][r];
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-    if (L.l == 0) red[L.w][j] = acc;
+        for (int r = 0; r < 4; ++r) {
+          part = fma(Kt[q].re[a][r], Bt.re[a][r], part);
+          part = fma(-Kt[q].im[a][r], Bt.im[a][r], part);
+        }
+      double acc = (double)part;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+      if (L.l == 0) red[L.w][q][j] = acc;
+    }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < g.nb; j += WG)
-    g.part[((size_t)slice * Tn * Tn + tile) * g.nb + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+  for (int e = threadIdx.x; e < S * g.nb; e += WG) {
+    const int q = e / g.nb, j = e % g.nb;
+    if (s0 + q < g.n_slices)
+      g.part[((size_t)(s0 + q) * Tn * Tn + tile) * g.nb + j] = (red[0][q][j] + red[1][q][j]) + (red[2][q][j] + red[3][q][j]);
+  }
 }
 
 __global__ void k_btraces_sum(BigTraceArgs g) {
@@ -752,8 +794,10 @@ hipError_t launch_tile_flags(const double* basis, int nb, int n, uint8_t* flags,
 hipError_t launch_btraces(int prec, const BigTraceArgs& g, hipStream_t s) {
   if (g.n_slices <= 0) return hipSuccess;
   const int Tn = g.n / 64;
-  if (prec == 32) hipLaunchKernelGGL(k_btraces_part<float>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
-  else hipLaunchKernelGGL(k_btraces_part<double>, dim3(Tn * Tn, g.n_slices), dim3(WG), 0, s, g);
+  constexpr int S = kBigSlicesPerGroup;
+  const dim3 grid(Tn * Tn, (g.n_slices + S - 1) / S);
+  if (prec == 32) hipLaunchKernelGGL((k_btraces_part<float, S>), grid, dim3(WG), 0, s, g);
+  else hipLaunchKernelGGL((k_btraces_part<double, S>), grid, dim3(WG), 0, s, g);
   hipLaunchKernelGGL(k_btraces_sum, dim3(g.n_slices), dim3(64), 0, s, g);
   return hipGetLastError();
 }
