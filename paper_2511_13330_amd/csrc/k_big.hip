@@ -9,6 +9,7 @@
 // in registers). Matrices are row-major n x n, interleaved complex.
 #include "tile.hpp"
 #include "internal.hpp"
+#include "big.hpp"
 #include "pade.hpp"
 
 #include <algorithm>

@@ -3,6 +3,7 @@
 #include "../../include/lmag.h"
 #include "../../include/lmag_debug.h"
 #include "internal.hpp"
+#include "big.hpp"
 #include "tile.hpp"
 #include "pade.hpp"
 
