@@ -449,6 +449,40 @@ __device__ __forceinline__ int slice_inverse_code(const SliceArgs& a, int n) {
   return a.nlev ? (int)(int8_t)(code_word(a.nlev + n) & 0xff) : 0;
 }
 
+// The codes of one slice, packed in a word: m | s << 8 | inverse code << 16.
+struct SliceCode {
+  int m, s, K;
+};
+__device__ __forceinline__ SliceCode unpack_code(uint32_t w) {
+  return {(int)(int8_t)(w & 0xff), (int)(int8_t)((w >> 8) & 0xff), (int)(int8_t)((w >> 16) & 0xff)};
+}
+__device__ __forceinline__ uint32_t slice_code(const SliceArgs& a, int n) {
+  const SliceMS ms = slice_ms(a, n);
+  return (uint32_t)(ms.m & 0xff) | (uint32_t)(ms.s & 0xff) << 8 |
+         (uint32_t)(slice_inverse_code(a, n) & 0xff) << 16;
+}
+
+// The codes of up to 64 consecutive slices of a chunk, one slice per lane of
+// every wave, fetched by one vector load per 64 slices; a slice takes its code
+// with v_readlane (a scalar, for the branches). A scalar load per slice left
+// its latency exposed at every slice start, where the code decides the path.
+constexpr int CODE_WINDOW = 64;
+struct CodeWindow {
+  uint32_t v = 0;
+  __device__ __forceinline__ void load(const SliceArgs& a, int n0, int cnt) {
+    const int l = threadIdx.x & 63;
+    v = 0;
+    if (l < cnt) {
+      const size_t n = (size_t)n0 + l;
+      v = (uint32_t)(uint8_t)a.ms[2 * n] | (uint32_t)(uint8_t)a.ms[2 * n + 1] << 8 |
+          (a.nlev ? (uint32_t)(uint8_t)a.nlev[n] << 16 : 0u);
+    }
+  }
+  __device__ __forceinline__ uint32_t at(int i) const {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, i);
+  }
+};
+
 // One slice forward; returns D_n = S_n - I in R. Every matrix near the identity
 // is carried as I + X with only X inside the MFMA accumulators: accumulating
 // small products onto O(1) diagonal entries in FP32 biases them by a fraction of
@@ -463,10 +497,10 @@ __device__ __forceinline__ int slice_inverse_code(const SliceArgs& a, int n) {
 // previous slice's chain product).
 template <typename T, bool ST>
 __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& sh, cpx<T>* gs,
-                          const SliceArgs& a, int n, cpx<T>* ws, Clock& ck) {
+                          const SliceArgs& a, uint32_t code, cpx<T>* ws, Clock& ck) {
   constexpr bool hk = sizeof(T) == 4;   // stores inside products
-  const SliceMS ms = slice_ms(a, n);
-  const int m = ms.m, s = ms.s;
+  const SliceCode sc = unpack_code(code);
+  const int m = sc.m, s = sc.s;
   const double* b = pade_b<T>(a.pade, m);   // b[0] = 1
   ck.mark(0);
   constexpr bool st = ST;   // compile-time, so that the stores are straight-line code
@@ -490,7 +524,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   ck.mark(1);
   // single precision stores A^2 during the next product
   if constexpr (st && !hk) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
-  const int K = slice_inverse_code(a, n);
+  const int K = sc.K;
   if (sizeof(T) == 4 && m == 2 && K >= 16) {
     // r_2(A) by its power series, truncated at degree 4 (the selection rule keeps
     // the tail below u/2): D = r_2(A) - I = rho_1 A + A^2 (rho_2 I + rho_3 A + rho_4 A^2),
@@ -739,18 +773,23 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     rp_identity(P);
     RT<T> A;
     rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
-    for (int k = 0; k < ch.count; ++k) {
-      const int n = ch.first + k;
-      cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
-      RT<T> D;
-      fwd_slice<T, ST>(D, A, P.hi, sh, gs, a, n, ws, ck);
-      put<T, false>(D, slot<T, 3>(sh, gs));   // slot 3's last reader is the previous chain
-      __syncthreads();
-      // the next slice's Omega tile, spread over the chain product (the chunk's
-      // last slice reloads its own, so that the loads are unconditional)
-      chain_step<T>(P, slot<T, 3>(sh, gs),
-                    TileLoad<T, false>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
-      ck.mark(6);
+    for (int k0 = 0; k0 < ch.count; k0 += CODE_WINDOW) {
+      const int k1 = min(ch.count, k0 + CODE_WINDOW);
+      CodeWindow cw;
+      cw.load(a, ch.first + k0, k1 - k0);
+      for (int k = k0; k < k1; ++k) {
+        const int n = ch.first + k;
+        cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
+        RT<T> D;
+        fwd_slice<T, ST>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
+        put<T, false>(D, slot<T, 3>(sh, gs));   // slot 3's last reader is the previous chain
+        __syncthreads();
+        // the next slice's Omega tile, spread over the chain product (the chunk's
+        // last slice reloads its own, so that the loads are unconditional)
+        chain_step<T>(P, slot<T, 3>(sh, gs),
+                      TileLoad<T, false>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
+        ck.mark(6);
+      }
     }
     rp_store_delta<T>(P, tile_at<T>(a.totals, (size_t)ch.chunk));
   }
@@ -770,15 +809,15 @@ template <typename T> constexpr bool bwd_carry = sizeof(T) == 4;
 // kpack: this thread's compact-K_n^T word (sparse basis), see SparseBasis.
 template <typename T>
 __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* gs,
-                          const SliceArgs& a, int n, const cpx<T>* ws, int nn, const cpx<T>* nx,
-                          Clock& ck, uint32_t kpack) {
-  const SliceMS ms = slice_ms(a, n);
-  const int m = ms.m, s = ms.s;
+                          const SliceArgs& a, int n, uint32_t code, const cpx<T>* ws, int nn,
+                          const cpx<T>* nx, Clock& ck, uint32_t kpack) {
+  const SliceCode code_n = unpack_code(code);
+  const int m = code_n.m, s = code_n.s;
   const double* b = pade_b<T>(a.pade, m);
   const T sc = (T)ldexp(1.0, -s);
   // r_2 by its degree-4 series in the forward: the adjoint differentiates that
   // polynomial and reads A^2 in place of Q^{-1}
-  const bool ser2 = sizeof(T) == 4 && m == 2 && slice_inverse_code(a, n) >= 16;
+  const bool ser2 = sizeof(T) == 4 && m == 2 && code_n.K >= 16;
   // D^T = (r_m(A) - I)^T and (Q^{-1} - I)^T (or A^2). Single precision requests each
   // stored tile one product ahead of its use, spread over that product's
   // k-steps: a wave that requests whole tiles at once stalls on issue (about 4K
@@ -999,16 +1038,21 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       rp_identity(P);
       RT<T> A;
       rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
-      for (int k = 0; k < ch.count; ++k) {
-        cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
-        RT<T> D;
-        fwd_slice<T, true>(D, A, P.hi, sh, gs, a, ch.first + k, ws, ck);
-        if (k + 1 < ch.count) {
-          rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
-          __syncthreads();
-          put<T, false>(D, slot<T, 3>(sh, gs));
-          __syncthreads();
-          chain_step<T>(P, slot<T, 3>(sh, gs));
+      for (int k0 = 0; k0 < ch.count; k0 += CODE_WINDOW) {
+        const int k1 = min(ch.count, k0 + CODE_WINDOW);
+        CodeWindow cw;
+        cw.load(a, ch.first + k0, k1 - k0);
+        for (int k = k0; k < k1; ++k) {
+          cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
+          RT<T> D;
+          fwd_slice<T, true>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
+          if (k + 1 < ch.count) {
+            rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
+            __syncthreads();
+            put<T, false>(D, slot<T, 3>(sh, gs));
+            __syncthreads();
+            chain_step<T>(P, slot<T, 3>(sh, gs));
+          }
         }
       }
     }
@@ -1030,9 +1074,15 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       __builtin_amdgcn_s_waitcnt(0);
     }
     ck.mark(0);
-    for (int k = ch.count - 1; k >= 0; --k)
-      bwd_slice<T>(Z, Pl, A, sh, gs, a, ch.first + k, ws_of(k), ch.first + (k > 0 ? k - 1 : 0),
-                   ws_of(k > 0 ? k - 1 : 0), ck, kpack);
+    // code windows from the chunk's end: [k0, k1) with k1 - k0 <= 64
+    for (int k1 = ch.count; k1 > 0; k1 -= CODE_WINDOW) {
+      const int k0 = max(0, k1 - CODE_WINDOW);
+      CodeWindow cw;
+      cw.load(a, ch.first + k0, k1 - k0);
+      for (int k = k1 - 1; k >= k0; --k)
+        bwd_slice<T>(Z, Pl, A, sh, gs, a, ch.first + k, cw.at(k - k0), ws_of(k),
+                     ch.first + (k > 0 ? k - 1 : 0), ws_of(k > 0 ? k - 1 : 0), ck, kpack);
+    }
   }
   ck.flush(a.clk ? a.clk + 16 : nullptr);
 }
@@ -1136,7 +1186,7 @@ __global__ void __launch_bounds__(WG, 1) k_debug_expm2(cpx<T>* C, cpx<T>* gs, Sl
   Clock ck(nullptr, sh.clk);
   RT<T> R, A;
   rt_load<T, false>(A, tile_at<T>(a.omega, 0), 64);
-  fwd_slice<T, false>(R, A, A, sh, gs + 2 * SLOT, a, 0, nullptr, ck);
+  fwd_slice<T, false>(R, A, A, sh, gs + 2 * SLOT, a, slice_code(a, 0), nullptr, ck);
   rt_add_diag(R, T(1));
   rt_store<T, false>(R, C, 64);
 }
