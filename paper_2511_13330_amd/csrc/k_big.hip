@@ -100,6 +100,18 @@ __device__ __forceinline__ void bgemm_body(const BigGemmArgs& g, BigShared<T>& s
   }
   if (g.gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.gamma);
   rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
+  if (g.C2) {
+    // second output from the same tile: C2 = c2_c C + c2_e E2 + c2_gamma I
+    rt_scale(acc, (T)g.c2_c);
+    if (g.E2) {
+      RT<T> Et;
+      rt_load<T, false>(Et, mat<T>(g.E2, g.E2i, b, nn) + (size_t)ti * 64 * g.n + tj * 64, g.n);
+      rt_axpy(acc, (T)g.c2_e, Et);
+    }
+    if (g.c2_gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.c2_gamma);
+    cpx<T>* C2 = const_cast<cpx<T>*>(mat<T>(g.C2, g.C2i, b, nn));
+    rt_store<T, false>(acc, C2 + (size_t)ti * 64 * g.n + tj * 64, g.n);
+  }
 }
 
 template <typename T, bool TA, bool TB, bool XCD = false>
@@ -375,8 +387,12 @@ __global__ void __launch_bounds__(WG) k_bgemm_q(BigGemmArgs g) {
       }
 }
 
-hipError_t launch_bgemm(int prec, const BigGemmArgs& g, hipStream_t s) {
-  if (g.batch <= 0) return hipSuccess;
+hipError_t launch_bgemm(int prec, const BigGemmArgs& g_in, hipStream_t s) {
+  if (g_in.batch <= 0) return hipSuccess;
+  if (g_in.C2 && g_in.pred) return hipErrorInvalidValue;   // the copy path writes no C2
+  BigGemmArgs g = g_in;
+  // a second output is written by the register-B kernels (0, 5, 6, 7) only
+  if (g.C2 && g.variant >= 1 && g.variant <= 4) g.variant = 0;
   const int Tn = g.n / 64;
   const dim3 grid(Tn * Tn, g.batch);
   if (prec == 32 && !g.transA && !g.transB && g.variant == 4 && Tn % 2 == 0) {

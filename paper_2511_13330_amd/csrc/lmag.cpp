@@ -1026,6 +1026,17 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     return gemmx(batch, Ap, nullptr, Bp, nullptr, Cp, nullptr, alpha, Dp, nullptr, beta, D2p, nullptr,
                  beta2, pred, thresh);
   };
+  // C = alpha A B + beta D and, from the same tiles, C2 = c2c C + c2e E2 + c2g I
+  auto gemm_dual = [&](int batch, const void* Ap, const int32_t* Ai, const void* Bp, const int32_t* Bi,
+                       const void* Cp, const int32_t* Ci, double alpha, const void* Dp, const int32_t* Di,
+                       double beta, const void* C2p, const int32_t* C2i, double c2c, const void* E2p,
+                       const int32_t* E2i, double c2e, double c2g) {
+    BigGemmArgs g{};
+    g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
+    g.D = Dp; g.Di = Di; g.alpha = alpha; g.beta = beta; g.variant = variant;
+    g.C2 = C2p; g.C2i = C2i; g.E2 = E2p; g.E2i = E2i; g.c2_c = c2c; g.c2_e = c2e; g.c2_gamma = c2g;
+    return launch_bgemm(32, g, s);
+  };
   auto axpby = [&](int batch, const void* X, const int32_t* Xi, void* Y, const int32_t* Yi, double a,
                    const void* Z = nullptr, const int32_t* Zi = nullptr, double cc = 0.0, double d = 0.0,
                    const int8_t* ms = nullptr) {
@@ -1176,8 +1187,8 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
         // (no squarings at this degree and the adjoint reads neither R0 nor a
         // second copy of D here: D goes straight to S; T1 = W stays for the
         // adjoint)
-        HIPCHK(gemm(n2, A, L2, A, L2, A2, L2, 1.0), "A2");
-        HIPCHK(axpby(n2, A, L2, T1, L2, 1.0 / 6.0, A2, L2, 1.0 / 24.0, 0.5), "W = I/2 + A/6 + A2/24");
+        HIPCHK(gemm_dual(n2, A, L2, A, L2, A2, L2, 1.0, nullptr, nullptr, 0.0, T1, L2, 1.0 / 24.0, A, L2,
+                         1.0 / 6.0, 0.5), "A2, W = I/2 + A/6 + A2/24");
         HIPCHK(gemm(n2, A2, L2, T1, L2, S, L2, 1.0, A, L2, 1.0), "D");
       }
       // (I + D)^2 = I + 2 D + D^2
@@ -1353,9 +1364,9 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           // with W = I/2 + A/6 + A^2/24 (T1, kept from the forward):
           // K = E + L2 W + A^2 (E/6 + L2/24)
           HIPCHK(gemm(n2, A, L2, Em, L2, T3, L2, 1.0), "AE");
-          HIPCHK(gemm(n2, Em, L2, A, L2, T3, L2, 1.0, T3, L2, 1.0), "L2");                    // T3 = L2
+          HIPCHK(gemm_dual(n2, Em, L2, A, L2, T3, L2, 1.0, T3, L2, 1.0, T2, L2, 1.0 / 24.0, Em, L2, 1.0 / 6.0,
+                           0.0), "L2, E/6 + L2/24");                                       // T3 = L2, T2
           HIPCHK(gemm(n2, T3, L2, T1, L2, T4, L2, 1.0, Em, L2, 1.0), "E + L2 W");
-          HIPCHK(axpby(n2, Em, L2, T2, L2, 1.0 / 6.0, T3, L2, 1.0 / 24.0), "E/6 + L2/24");
           HIPCHK(gemm(n2, A2, L2, T2, L2, T3, L2, 1.0, T4, L2, 1.0), "K");                    // T3 = K
         }
         // squaring recurrence K <- R K + K R = 2 K + D K + K D, D <- 2 D + D D for the
