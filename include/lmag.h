@@ -242,7 +242,8 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * for calls with chunk_slices = 0 whose precision, order, d and total slice
  * count (power-of-two bucket) match, and appended as one JSON line
  * {"key", "chunk", "variant", "ms"} to the file named by the environment
- * variable LMAG_TUNE_CACHE if it is set.
+ * variable LMAG_TUNE_CACHE if it is set. With LMAG_TUNE_VERBOSE set, each
+ * candidate's time is written to stderr as it is measured.
  * best_out: HOST int32 [2] (chunk, variant: inverse variant or product kernel)
  * or NULL; best_ms_out: HOST or NULL.
  * Blocks. Outputs of the timed calls go to internal buffers. */

@@ -2003,6 +2003,10 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
         }
         const double per_call = ms / reps;
         if (per_call < best) { best = per_call; bestC = C; bestInv = inv; }
+        if (std::getenv("LMAG_TUNE_VERBOSE")) {
+          std::fprintf(stderr, "lmag_autotune: variant %d chunk %d: %.4f ms per call\n", inv, C, per_call);
+          std::fflush(stderr);
+        }
       }
       if (st != LMAG_OK) break;
     }
