@@ -229,8 +229,9 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * MFMA (FP32-level error); 4: as 0 with two output tiles (eight waves) per
  * workgroup sharing each staged A tile (n / 64 even); 5: as 0 with every
  * product's tiles on one XCD (n <= 1024); 6: as 0 without the operand pipeline,
- * three workgroups per CU; 7: as 6 with the grouping of 5 -- at the automatic
- * chunk length, half and twice it. 64 x 64 systems: the
+ * three workgroups per CU; 7: as 6 with the grouping of 5; 8: as 0 with the A
+ * tiles double-buffered in LDS by direct global-to-LDS loads (grouped as 5
+ * where n <= 1024) -- at the automatic chunk length, half and twice it. 64 x 64 systems: the
  * persistent slice kernels, for every candidate chunk length (slices per work
  * unit) and the inverse variants
  * of the Pade step (0: per slice the cheapest whose error bound holds -- in

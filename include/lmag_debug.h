@@ -37,7 +37,7 @@ lmag_status lmag_debug_tile_expm(lmag_ctx *ctx, int precision, const void *A, vo
 /* The block-tiled product kernels on their own: C_b = A_b B_b for b < batch,
  * complex FP32 n x n matrices (n a multiple of 64, 64 <= n <= 4096), DEVICE
  * pointers to batch contiguous row-major matrices each, C distinct from A and
- * B. variant selects the product kernel as the autotuner does (0..6; a kernel
+ * B. variant selects the product kernel as the autotuner does (0..8; a kernel
  * whose shape condition fails runs kernel 0). Asynchronous on hip_stream. */
 lmag_status lmag_debug_block_gemm(lmag_ctx *ctx, int n, int batch, const void *A, const void *B,
                                   void *C, int variant, void *hip_stream);

@@ -33,14 +33,16 @@ struct BigGemmArgs {
                  // waves) per workgroup sharing each staged A tile (n / 64 even);
                  // 5 as 0 with every product's tiles on one XCD (n <= 1024);
                  // 6 as 0 without the operand pipeline, three workgroups per CU;
-                 // 7 as 6 with every product's tiles on one XCD (n <= 1024)
-  // optional second output of the same tile (kernels 0, 5, 6, 7; not with
+                 // 7 as 6 with every product's tiles on one XCD (n <= 1024);
+                 // 8 as 0 with the A tiles double-buffered in LDS by direct
+                 // global-to-LDS loads (with the XCD grouping where n <= 1024)
+  // optional second output of the same tile (kernels 0, 5, 6, 7, 8; not with
   // pred): C2 = c2_c C + c2_e E2 + c2_gamma I, E2 may be null
   const void* C2; const int32_t* C2i;
   const void* E2; const int32_t* E2i;
   double c2_c, c2_e, c2_gamma;
 };
-constexpr int kBigGemmVariants = 8;
+constexpr int kBigGemmVariants = 9;
 constexpr int kBigGemmDefault = 0;   // product kernel of an untuned block-tiled call
 struct BigAxpbyArgs {
   int n, batch;

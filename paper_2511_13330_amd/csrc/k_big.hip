@@ -36,11 +36,9 @@ __device__ __forceinline__ const cpx<T>* mat(const void* base, const int32_t* id
 // L mod 8 and is given product tile (L mod 8) * (grid / 8) + L / 8. An XCD then
 // works through consecutive products, each one's operand tiles fetched into its
 // own L2 once and re-read there by the product's other output tiles.
-template <typename T, bool TA, bool TB, bool XCD, bool PIPE>
-__device__ __forceinline__ void bgemm_body(const BigGemmArgs& g, BigShared<T>& sh) {
-  const int Tn = g.n / 64;
-  const size_t nn = (size_t)g.n * g.n;
-  int b, ti, tj;
+// (batch entry, tile row, tile column) of this workgroup.
+template <bool XCD>
+__device__ __forceinline__ void tile_of_block(int Tn, int& b, int& ti, int& tj) {
   if constexpr (XCD) {
     const int L = blockIdx.x, per = gridDim.x / 8;
     const int logical = (L % 8) * per + L / 8;
@@ -52,6 +50,48 @@ __device__ __forceinline__ void bgemm_body(const BigGemmArgs& g, BigShared<T>& s
     ti = blockIdx.x / Tn;
     tj = blockIdx.x % Tn;
   }
+}
+
+// Epilogue of the register-B kernels: C = alpha acc + beta D + beta2 D2 +
+// gamma I, then the optional second output C2 = c2_c C + c2_e E2 + c2_gamma I.
+template <typename T>
+__device__ __forceinline__ void bgemm_epilogue(const BigGemmArgs& g, RT<T>& acc, int b, int ti, int tj,
+                                               cpx<T>* C, const cpx<T>* D) {
+  const size_t nn = (size_t)g.n * g.n;
+  const size_t off = (size_t)ti * 64 * g.n + tj * 64;
+  rt_scale(acc, (T)g.alpha);
+  if (D && g.beta != 0.0) {
+    RT<T> Dt;
+    rt_load<T, false>(Dt, D + off, g.n);
+    rt_axpy(acc, (T)g.beta, Dt);
+  }
+  if (g.D2 && g.beta2 != 0.0) {
+    RT<T> Dt;
+    rt_load<T, false>(Dt, mat<T>(g.D2, g.D2i, b, nn) + off, g.n);
+    rt_axpy(acc, (T)g.beta2, Dt);
+  }
+  if (g.gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.gamma);
+  rt_store<T, false>(acc, C + off, g.n);
+  if (g.C2) {
+    // second output from the same tile: C2 = c2_c C + c2_e E2 + c2_gamma I
+    rt_scale(acc, (T)g.c2_c);
+    if (g.E2) {
+      RT<T> Et;
+      rt_load<T, false>(Et, mat<T>(g.E2, g.E2i, b, nn) + off, g.n);
+      rt_axpy(acc, (T)g.c2_e, Et);
+    }
+    if (g.c2_gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.c2_gamma);
+    cpx<T>* C2 = const_cast<cpx<T>*>(mat<T>(g.C2, g.C2i, b, nn));
+    rt_store<T, false>(acc, C2 + off, g.n);
+  }
+}
+
+template <typename T, bool TA, bool TB, bool XCD, bool PIPE>
+__device__ __forceinline__ void bgemm_body(const BigGemmArgs& g, BigShared<T>& sh) {
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  int b, ti, tj;
+  tile_of_block<XCD>(Tn, b, ti, tj);
   cpx<T>* C = const_cast<cpx<T>*>(mat<T>(g.C, g.Ci, b, nn));
   const cpx<T>* D = g.D ? mat<T>(g.D, g.Di, b, nn) : nullptr;
   const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
@@ -86,32 +126,7 @@ __device__ __forceinline__ void bgemm_body(const BigGemmArgs& g, BigShared<T>& s
     __syncthreads();
     gemm_acc<T, false, PITCH, PIPE>(acc, sh.slot, Bt);
   }
-  const T al = (T)g.alpha;
-  rt_scale(acc, al);
-  if (D && g.beta != 0.0) {
-    RT<T> Dt;
-    rt_load<T, false>(Dt, D + (size_t)ti * 64 * g.n + tj * 64, g.n);
-    rt_axpy(acc, (T)g.beta, Dt);
-  }
-  if (g.D2 && g.beta2 != 0.0) {
-    RT<T> Dt;
-    rt_load<T, false>(Dt, mat<T>(g.D2, g.D2i, b, nn) + (size_t)ti * 64 * g.n + tj * 64, g.n);
-    rt_axpy(acc, (T)g.beta2, Dt);
-  }
-  if (g.gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.gamma);
-  rt_store<T, false>(acc, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
-  if (g.C2) {
-    // second output from the same tile: C2 = c2_c C + c2_e E2 + c2_gamma I
-    rt_scale(acc, (T)g.c2_c);
-    if (g.E2) {
-      RT<T> Et;
-      rt_load<T, false>(Et, mat<T>(g.E2, g.E2i, b, nn) + (size_t)ti * 64 * g.n + tj * 64, g.n);
-      rt_axpy(acc, (T)g.c2_e, Et);
-    }
-    if (g.c2_gamma != 0.0 && ti == tj) rt_add_diag(acc, (T)g.c2_gamma);
-    cpx<T>* C2 = const_cast<cpx<T>*>(mat<T>(g.C2, g.C2i, b, nn));
-    rt_store<T, false>(acc, C2 + (size_t)ti * 64 * g.n + tj * 64, g.n);
-  }
+  bgemm_epilogue<T>(g, acc, b, ti, tj, C, D);
 }
 
 template <typename T, bool TA, bool TB, bool XCD = false>
@@ -129,6 +144,118 @@ __global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_bgemm_occ3(BigGemmArgs g) {
   __shared__ BigShared<float> sh;
   bgemm_body<float, false, false, XCD, false>(g, sh);
+}
+
+// Kernel 8 (single precision, no transposes): one 64 x 64 output tile per
+// workgroup like kernel 0, with each A tile brought into LDS by the direct
+// global-to-LDS loads (no registers, no LDS stores by the waves) into one of
+// two buffers, so that the next k-step's A tile and B tile are in flight while
+// the current step's products run; one barrier per k-step. The A tile is kept
+// unpadded and row-major with the 16-byte granules of each row permuted
+// (granule G of row R at position G ^ (R & 15)): a 16-byte read of one granule
+// position by the 16 lanes that hold rows 16 q .. 16 q + 15 then touches 16
+// different bank groups, and a load instruction, whose 64 lanes fill 1 KB of
+// LDS in lane order, reads a permutation of two contiguous 512-byte rows.
+constexpr int DMA_TILE = 64 * 64;   // complex elements of one LDS A buffer
+
+__device__ __forceinline__ void dma_a_tile(const cpx<float>* At, int ld, cpx<float>* buf) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int chunk = 8 * w + i;                 // 1 KB of LDS: rows 2 chunk, 2 chunk + 1
+    const int r = 2 * chunk + (l >> 5);
+    const int G = (l & 31) ^ (r & 15);           // the granule that lands at position l & 31
+    __builtin_amdgcn_global_load_lds((const void*)(At + (size_t)r * ld + 2 * G),
+                                     (__attribute__((address_space(3))) void*)(buf + chunk * 128), 16, 0, 0);
+  }
+}
+
+// acc += A B for the A tile in LDS (layout above) and B in registers (RT), in
+// the 3M form, k = 16 kb + 4 g + t as in the RT layout. mid() runs after the
+// first half of the k-steps, whose B registers are dead by then: the next
+// step's B tile is requested there, so that it never doubles the B registers.
+template <typename F>
+__device__ __forceinline__ void mma_dma(RT<float>& acc, const cpx<float>* buf, const RT<float>& B,
+                                        const F& mid) {
+  const Lane L;
+  const int g = L.g, c = L.c;
+  const char* base = reinterpret_cast<const char*>(buf) + c * 512;   // row 16 q + c, q = 0 below
+  vec4<float>::type k1[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) k1[q] = vec4<float>::type{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    if (kb == 2) {
+      __builtin_amdgcn_sched_barrier(0);
+      mid();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const int G0 = 8 * kb + 2 * g;
+    float4 a[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const char* row = base + q * 16 * 512;
+      a[q][0] = *reinterpret_cast<const float4*>(row + ((G0 ^ c) << 4));
+      a[q][1] = *reinterpret_cast<const float4*>(row + (((G0 + 1) ^ c) << 4));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float br = B.re[kb][t], bi = B.im[kb][t];
+      const float nsum = -(br + bi), diff = bi - br;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4& v = a[q][t >> 1];
+        const float are = (t & 1) ? v.z : v.x, aim = (t & 1) ? v.w : v.y;
+        k1[q] = mfma4<float>(are + aim, br, k1[q]);
+        acc.re[q] = mfma4<float>(aim, nsum, acc.re[q]);
+        acc.im[q] = mfma4<float>(are, diff, acc.im[q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) { acc.re[q] += k1[q]; acc.im[q] += k1[q]; }
+}
+
+template <bool XCD>
+__global__ void __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) k_bgemm_dma(BigGemmArgs g) {
+  __shared__ __attribute__((aligned(16))) cpx<float> abuf[2 * DMA_TILE];
+  const int Tn = g.n / 64;
+  const size_t nn = (size_t)g.n * g.n;
+  int b, ti, tj;
+  tile_of_block<XCD>(Tn, b, ti, tj);
+  cpx<float>* C = const_cast<cpx<float>*>(mat<float>(g.C, g.Ci, b, nn));
+  const cpx<float>* D = g.D ? mat<float>(g.D, g.Di, b, nn) : nullptr;
+  const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
+  if (!active) {
+    const cpx<float>* src = D ? D : mat<float>(g.A, g.Ai, b, nn);
+    RT<float> X;
+    rt_load<float, false>(X, src + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    rt_store<float, false>(X, C + (size_t)ti * 64 * g.n + tj * 64, g.n);
+    return;
+  }
+  const cpx<float>* Arow = mat<float>(g.A, g.Ai, b, nn) + (size_t)ti * 64 * g.n;
+  const cpx<float>* Bcol = mat<float>(g.B, g.Bi, b, nn) + tj * 64;
+  RT<float> acc, Bt, Bn;
+  rt_zero(acc);
+  dma_a_tile(Arow, g.n, abuf);
+  rt_load<float, false>(Bt, Bcol, g.n);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int tk = 0; tk < Tn; ++tk) {
+    const bool more = tk + 1 < Tn;
+    // buffer (tk + 1) & 1 was last read by step tk - 1, which every wave has
+    // left at the barrier that ended it
+    if (more) dma_a_tile(Arow + (tk + 1) * 64, g.n, abuf + ((tk + 1) & 1) * DMA_TILE);
+    mma_dma(acc, abuf + (tk & 1) * DMA_TILE, Bt, [&] {
+      if (more) rt_load<float, false>(Bn, Bcol + (size_t)(tk + 1) * 64 * g.n, g.n);
+    });
+    if (more) {
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's loads into LDS and registers
+      __syncthreads();                 // every wave's
+      rt_copy(Bt, Bn);
+    }
+  }
+  bgemm_epilogue<float>(g, acc, b, ti, tj, C, D);
 }
 
 // Two output tiles per workgroup (variant 4; single precision, no transposes):
@@ -391,7 +518,7 @@ hipError_t launch_bgemm(int prec, const BigGemmArgs& g_in, hipStream_t s) {
   if (g_in.batch <= 0) return hipSuccess;
   if (g_in.C2 && g_in.pred) return hipErrorInvalidValue;   // the copy path writes no C2
   BigGemmArgs g = g_in;
-  // a second output is written by the register-B kernels (0, 5, 6, 7) only
+  // a second output is written by the register-B kernels (0, 5, 6, 7, 8) only
   if (g.C2 && g.variant >= 1 && g.variant <= 4) g.variant = 0;
   const int Tn = g.n / 64;
   const dim3 grid(Tn * Tn, g.batch);
@@ -401,6 +528,11 @@ hipError_t launch_bgemm(int prec, const BigGemmArgs& g_in, hipStream_t s) {
   }
   const bool xcd_ok = Tn <= 16 && ((size_t)Tn * Tn * g.batch) % 8 == 0 &&
                       (size_t)Tn * Tn * g.batch <= 0x7fffffff;
+  if (prec == 32 && !g.transA && !g.transB && g.variant == 8) {
+    if (xcd_ok) hipLaunchKernelGGL(k_bgemm_dma<true>, dim3(Tn * Tn * g.batch), dim3(WG), 0, s, g);
+    else hipLaunchKernelGGL(k_bgemm_dma<false>, grid, dim3(WG), 0, s, g);
+    return hipGetLastError();
+  }
   if (prec == 32 && !g.transA && !g.transB && g.variant == 7 && xcd_ok) {
     hipLaunchKernelGGL(k_bgemm_occ3<true>, dim3(Tn * Tn * g.batch), dim3(WG), 0, s, g);
     return hipGetLastError();

@@ -1977,6 +1977,7 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
       variants.push_back(3);
       if ((c->n / 64) % 2 == 0) variants.push_back(4);
       variants.push_back(6);
+      variants.push_back(8);
       if (c->n / 64 <= 16) {
         variants.push_back(5);
         variants.push_back(7);

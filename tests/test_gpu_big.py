@@ -252,15 +252,17 @@ def _tuning_line(path, d, total, chunk, variant):
                 % (d, b, chunk, variant))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 def test_four_spin_product_kernels_match_oracle(variant, tmp_path):
     """Each product kernel of the block-tiled path (register-B tiles with the
     16x16x4 MFMA; a quadrant per wave with 16x16x4; a quadrant per wave with
     32x32x2; a quadrant per wave with split-bf16 operands on the 16x16x32 bf16
     MFMA; two output tiles per eight-wave workgroup; register-B tiles with each
     product on one XCD; register-B tiles at three workgroups per CU, without and
-    with the XCD grouping), selected through a tuning line: propagator, F and
-    gradient against the oracle, with squarings in some slices."""
+    with the XCD grouping; register-B tiles with the A tiles double-buffered in
+    LDS by direct global-to-LDS loads), selected through a tuning line:
+    propagator, F and gradient against the oracle, with squarings in some
+    slices."""
     cfg = synth.small_case(75, n_spins=4, n_slices=14, dt=2e-3)
     amps = rounded(cfg["amps"], "f32")
     sysm = lib_system(cfg, "f32", 2, "foh")
@@ -287,7 +289,7 @@ def test_block_tiled_autotune_picks_a_kernel():
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     b = np.asarray(cfg["B"])[None, :]
     chunk, variant, ms = sysm.autotune(a, [256], cfg["dt"], cfg["U_target"], static_coef=b, reps=1)
-    assert 0 <= variant < 8 and chunk >= 1 and ms > 0
+    assert 0 <= variant < 9 and chunk >= 1 and ms > 0
     F, g = sysm.fidelity_and_grad(a, [256], cfg["dt"], cfg["U_target"], static_coef=b)
     assert sysm.last_plan()["chunk_slices"] == chunk
     F_ref, _ = oracle.fidelity(oracle.propagate(oracle_system(cfg).omegas(amps, cfg["dt"], 2, "foh")),

@@ -62,7 +62,7 @@ def test_tile_expm(ctx_system, prec, norm, m, s):
     assert err < (20 * TOL[prec] * (1 + s)), err
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("n,batch", [(128, 3), (256, 5), (1024, 2), (4096, 1)])
 def test_block_product_kernels(ctx_system, variant, n, batch):
     """Every block-tiled product kernel against an FP64 product of the same
