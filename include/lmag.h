@@ -122,6 +122,11 @@ typedef struct {
                                 /* one chunk per compute unit up to 64 slices per unit,*/
                                 /* above that about four chunks per workgroup within  */
                                 /* 64..256 slices (64 when the adjoint recomputes)    */
+  int block_basis;              /* superoperators larger than 64 x 64 and order 6:  */
+                                /* 0 = the real basis of Hermitian operators (every */
+                                /* matrix of the path is real there: one real MFMA  */
+                                /* product per complex one), 1 = column stacking    */
+                                /* (complex); results agree up to rounding          */
 } lmag_system_desc;
 
 /* Install (or replace) the system. Builds the superoperator basis on the

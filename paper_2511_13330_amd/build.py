@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblmag.so")
-SOURCES = ["k_slice.hip", "k_aux.hip", "k_optim.hip", "k_mlp.hip", "k_big.hip", "lmag.cpp"]
+SOURCES = ["k_slice.hip", "k_aux.hip", "k_optim.hip", "k_mlp.hip", "k_big.hip", "k_real.hip", "lmag.cpp"]
 ARCH = os.environ.get("LMAG_OFFLOAD_ARCH", "gfx950")
 
 # packed FP32 instructions are disabled on purpose (build notes)

@@ -86,5 +86,22 @@ hipError_t launch_bfidelity(int prec, const BigFidArgs& g, hipStream_t s);
 hipError_t launch_blift(const double* H, int d, double* out, hipStream_t s);
 hipError_t launch_bdissipator(const double* Ls, int n_jump, int d, double* ldl, double* out, hipStream_t s);
 hipError_t launch_btargets(const double* U, int n_targets, int d, double* st64, float* st32, hipStream_t s);
+hipError_t launch_btraces_sum(const BigTraceArgs& g, hipStream_t s);
+
+// the same path in the real basis of Hermitian operators (k_real.hip): real FP32
+// matrices of n x n floats behind the same argument structures
+hipError_t launch_rgemm(const BigGemmArgs& g, hipStream_t s);
+hipError_t launch_raxpby(const BigAxpbyArgs& g, hipStream_t s);
+hipError_t launch_romega(const BigOmegaArgs& g, hipStream_t s);
+hipError_t launch_rnorm_dense(const BigOmegaArgs& g, hipStream_t s);
+hipError_t launch_rtraces(const BigTraceArgs& g, hipStream_t s);
+hipError_t launch_rfidelity(const BigFidArgs& g, hipStream_t s);
+// R = T S T^dag for nmat complex FP64 superoperators (column stacking) -> real FP64
+hipError_t launch_to_real(const double* S, int d, int nmat, double* R, hipStream_t s);
+// out[Yi[b]] = T^dag (I + R[Xi[b]]) T, complex FP32 (column stacking)
+hipError_t launch_from_real(const float* R, const int32_t* Xi, int d, int batch, void* out, const int32_t* Yi,
+                            hipStream_t s);
+hipError_t launch_rtile_flags(const double* basis, int nb, int n, uint8_t* flags, hipStream_t s);
+hipError_t launch_rcast(const double* in, float* out, size_t count, hipStream_t s);
 
 }  // namespace lmag

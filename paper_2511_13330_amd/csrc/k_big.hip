@@ -947,6 +947,10 @@ hipError_t launch_btraces(int prec, const BigTraceArgs& g, hipStream_t s) {
   const dim3 grid(Tn * Tn, (g.n_slices + S - 1) / S);
   if (prec == 32) hipLaunchKernelGGL((k_btraces_part<float, S>), grid, dim3(WG), 0, s, g);
   else hipLaunchKernelGGL((k_btraces_part<double, S>), grid, dim3(WG), 0, s, g);
+  return launch_btraces_sum(g, s);
+}
+
+hipError_t launch_btraces_sum(const BigTraceArgs& g, hipStream_t s) {
   hipLaunchKernelGGL(k_btraces_sum, dim3(g.n_slices), dim3(64), 0, s, g);
   return hipGetLastError();
 }

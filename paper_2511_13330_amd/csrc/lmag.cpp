@@ -108,6 +108,7 @@ struct lmag_ctx {
   // 1 Gauss-Jordan, 2 Neumann); block-tiled path: product kernel (BigGemmArgs::variant)
   int inv_variant = 0;
   int big_variant = -1;          // forced product kernel of the block-tiled path (-1: tuned or default)
+  bool real = false;             // block-tiled path in the real Hermitian-operator basis
   std::vector<std::pair<std::string, std::pair<int, int>>> tuned;
   bool clk_on = false;
   long long* clk_dev = nullptr;
@@ -750,7 +751,7 @@ struct BigLayout {
 BigLayout big_layout(const lmag_ctx* c, size_t meta_bytes, int Ns, int Lc, int n_items, int window,
                      int n_targets, bool grad) {
   const int n = c->n, Tn = n / 64;
-  const size_t mb = (size_t)n * n * 8;
+  const size_t mb = (size_t)n * n * (c->real ? 4 : 8);   // bytes per FP32 matrix
   BigLayout L;
   size_t o = align_up(meta_bytes);
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
@@ -762,7 +763,8 @@ BigLayout big_layout(const lmag_ctx* c, size_t meta_bytes, int Ns, int Lc, int n
   L.nlev = take((size_t)Ns);
   L.F_items = take((size_t)n_items * 8);
   L.part = take(std::max((size_t)window * Tn * n * 8, (size_t)window * Tn * Tn * c->nb * 8));
-  L.st64 = take((size_t)std::max(1, n_targets) * n * n * 16);
+  // FP64 targets S_T^dag (complex; in the real basis followed by their real form)
+  L.st64 = take((size_t)std::max(1, n_targets) * n * n * (c->real ? 24 : 16));
   L.st = take((size_t)std::max(1, n_targets) * mb);
   L.sq = take((size_t)Ns * kBigMaxSquarings * 4 + 4);   // squaring lists of every window
   L.mlist = take((size_t)Ns * 4 + 4);                    // slices by Pade degree, per window
@@ -789,7 +791,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
                     int n_targets, bool grad, bool fidelity, const void* U_target, double* F_out,
                     void* grad_out, void* S_out, hipStream_t s) {
   const int n = c->n, Tn = n / 64;
-  const size_t nn = (size_t)n * n, mb = nn * 8;   // FP32 complex matrices
+  const size_t nn = (size_t)n * n, mb = nn * (c->real ? 4 : 8);   // FP32 matrices (real or complex)
   std::vector<int> all(b->n_items);
   for (int i = 0; i < b->n_items; ++i) all[i] = i;
   long long total = 0;
@@ -1006,7 +1008,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
     g.D = Dp; g.Di = Di; g.alpha = alpha; g.beta = beta; g.gamma = gamma; g.transA = tA; g.transB = tB;
     g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh; g.variant = variant;
-    return launch_bgemm(32, g, s);
+    return c->real ? launch_rgemm(g, s) : launch_bgemm(32, g, s);
   };
   // C = alpha A B + beta D + beta2 D2 with index maps (null: the batch index)
   auto gemmx = [&](int batch, const void* Ap, const int32_t* Ai, const void* Bp, const int32_t* Bi,
@@ -1018,7 +1020,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     g.D = Dp; g.Di = Di; g.D2 = D2p; g.D2i = D2i;
     g.alpha = alpha; g.beta = beta; g.beta2 = beta2;
     g.pred = pred; g.pred_stride = 1; g.pred_thresh = thresh; g.variant = variant;
-    return launch_bgemm(32, g, s);
+    return c->real ? launch_rgemm(g, s) : launch_bgemm(32, g, s);
   };
   auto gemm2 = [&](int batch, const void* Ap, const void* Bp, const void* Cp, double alpha,
                    const void* Dp, double beta, const void* D2p, double beta2,
@@ -1035,7 +1037,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     g.n = n; g.batch = batch; g.A = Ap; g.Ai = Ai; g.B = Bp; g.Bi = Bi; g.C = Cp; g.Ci = Ci;
     g.D = Dp; g.Di = Di; g.alpha = alpha; g.beta = beta; g.variant = variant;
     g.C2 = C2p; g.C2i = C2i; g.E2 = E2p; g.E2i = E2i; g.c2_c = c2c; g.c2_e = c2e; g.c2_gamma = c2g;
-    return launch_bgemm(32, g, s);
+    return c->real ? launch_rgemm(g, s) : launch_bgemm(32, g, s);
   };
   auto axpby = [&](int batch, const void* X, const int32_t* Xi, void* Y, const int32_t* Yi, double a,
                    const void* Z = nullptr, const int32_t* Zi = nullptr, double cc = 0.0, double d = 0.0,
@@ -1043,7 +1045,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     BigAxpbyArgs g{};
     g.n = n; g.batch = batch; g.X = X; g.Xi = Xi; g.Z = Z; g.Zi = Zi; g.Y = Y; g.Yi = Yi;
     g.a = a; g.c = cc; g.d = d; g.ms = ms;
-    return launch_baxpby(32, g, s);
+    return c->real ? launch_raxpby(g, s) : launch_baxpby(32, g, s);
   };
   const double* b3 = c->pade.b3;
 
@@ -1070,7 +1072,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       oa.n = n; oa.n_slices = Wn; oa.nb = c->nb; oa.basis = c->basis32;
       oa.tile_ptr = c->tile_ptr; oa.tile_j = c->tile_j;
       oa.alpha = coef + pl * coef_plane; oa.omega = al[pl]; oa.part = (double*)at(BL.part);
-      HIPCHK(launch_bomega(32, oa, s), "a_p");
+      HIPCHK(c->real ? launch_romega(oa, s) : launch_bomega(32, oa, s), "a_p");
     }
     HIPCHK(gemm(Wn, A2, nullptr, R0, nullptr, T1, nullptr, 1.0), "a1 a2");
     HIPCHK(gemm(Wn, R0, nullptr, A2, nullptr, Qi, nullptr, -1.0, T1, nullptr, 1.0), "C1");
@@ -1111,10 +1113,10 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
       HIPCHK(gemm(Wn, T1, nullptr, Qi, nullptr, A, nullptr, -1.0 / 240.0, T2, nullptr, 1.0 / 240.0), "[X, Y]");
       HIPCHK(axpby(Wn, A2, nullptr, A, nullptr, 1.0, A, nullptr, 1.0), "+ a1");
       HIPCHK(axpby(Wn, S, nullptr, A, nullptr, 1.0 / 12.0, A, nullptr, 1.0), "+ a3 / 12");
-      HIPCHK(launch_bnorm_dense(32, om, s), "omega norm");
+      HIPCHK(c->real ? launch_rnorm_dense(om, s) : launch_bnorm_dense(32, om, s), "omega norm");
     } else {
       StageTimer t(c, 1, s);
-      HIPCHK(launch_bomega(32, om, s), "omega");
+      HIPCHK(c->real ? launch_romega(om, s) : launch_bomega(32, om, s), "omega");
     }
     if (first_pass) {
       std::vector<int8_t> msh((size_t)Wn * 2);
@@ -1276,22 +1278,36 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
     c->plan_recompute = grad && windowed;
     c->plan_waves = (int)win.size();
   };
-  if (S_out)   // U of every item = I + inclusive prefix at its last chunk
-    HIPCHK(axpby((int)p.items.size(), pre_cur, ip(o_il), S_out, ip(o_is), 1.0, nullptr, nullptr, 0.0, 1.0),
-           "extract");
+  if (S_out) {   // U of every item = I + inclusive prefix at its last chunk
+    if (c->real)   // back to column stacking: T^dag (I + R) T
+      HIPCHK(launch_from_real((const float*)pre_cur, ip(o_il), c->d, (int)p.items.size(), S_out, ip(o_is), s),
+             "extract");
+    else
+      HIPCHK(axpby((int)p.items.size(), pre_cur, ip(o_il), S_out, ip(o_is), 1.0, nullptr, nullptr, 0.0, 1.0),
+             "extract");
+  }
   if (!fidelity) { finish_plan(); return LMAG_OK; }
   // ---- targets, fidelity, environments
-  HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, (double*)at(BL.st64), (float*)at(BL.st), s),
-         "targets");
+  // S_T^dag of every target (FP64 and FP32); in the real basis R_T^T = T S_T^dag T^dag
+  double* st64 = (double*)at(BL.st64);
+  if (c->real) {
+    double* r64 = st64 + (size_t)std::max(1, n_targets) * nn * 2;
+    HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, st64, nullptr, s), "targets");
+    HIPCHK(launch_to_real(st64, c->d, n_targets, r64, s), "targets (real)");
+    HIPCHK(launch_rcast(r64, (float*)at(BL.st), (size_t)n_targets * nn, s), "targets (FP32)");
+    st64 = r64;
+  } else {
+    HIPCHK(launch_btargets((const double*)U_target, n_targets, c->d, st64, (float*)at(BL.st), s), "targets");
+  }
   const bool grouped = p.n_groups > 0;
   double* F_items = grouped ? (double*)at(BL.F_items) : F_out;
   {
     StageTimer t(c, 4, s);
     BigFidArgs fa{};
     fa.n = n; fa.n_items = (int)p.items.size(); fa.d = c->d; fa.U = pre_cur; fa.U_index = ip(o_il);
-    fa.st64 = (const double*)at(BL.st64); fa.target = ip(o_it); fa.F = F_items;
+    fa.st64 = st64; fa.target = ip(o_it); fa.F = F_items;
     fa.F_index = grouped ? nullptr : ip(o_is);
-    HIPCHK(launch_bfidelity(32, fa, s), "fidelity");
+    HIPCHK(c->real ? launch_rfidelity(fa, s) : launch_bfidelity(32, fa, s), "fidelity");
   }
   if (grad) {
     void* X = CM(6);
@@ -1425,7 +1441,7 @@ lmag_status run_big(lmag_ctx* c, const lmag_batch* b, const int32_t* target_of_i
           ta.K = Ks[pl]; ta.basis = c->basis32; ta.part = (double*)at(BL.part);
           ta.tile_ptr = c->tile_ptr; ta.tile_j = c->tile_j;
           ta.gtrace = (double*)at(BL.gtrace) + pl * coef_plane;
-          HIPCHK(launch_btraces(32, ta, s), "traces");
+          HIPCHK(c->real ? launch_rtraces(ta, s) : launch_btraces(32, ta, s), "traces");
         }
       }
     }
@@ -1674,6 +1690,9 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       return c->fail(LMAG_E_INVALID, "magnus_order must be 1, 2 or 6");
     if (s->hold != LMAG_ZOH && s->hold != LMAG_FOH) return c->fail(LMAG_E_INVALID, "hold must be ZOH or FOH");
     if (s->chunk_slices < 0) return c->fail(LMAG_E_INVALID, "chunk_slices < 0");
+    if (s->block_basis != 0 && s->block_basis != 1)
+      return c->fail(LMAG_E_INVALID, "block_basis must be 0 (Hermitian-operator basis) or 1 (column stacking)");
+    const bool real = big && s->block_basis == 0;
     const size_t dd2 = (size_t)d * d * 2;
     if ((s->n_static && !finite_array(s->H_static, s->n_static * dd2)) ||
         (s->n_ctrl && !finite_array(s->H_ctrl, s->n_ctrl * dd2)) ||
@@ -1706,7 +1725,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     double* tmp = nullptr;
     const size_t nops = (size_t)(ns + nc + s->n_jump) * dd2;
     if (hipMalloc((void**)&c->basis64, nb * tb) != hipSuccess ||
-        hipMalloc(&c->basis32, nb * nn * 8) != hipSuccess ||
+        hipMalloc(&c->basis32, nb * nn * (real ? 4 : 8)) != hipSuccess ||
         hipMalloc((void**)&ops, std::max<size_t>(8, nops * 8)) != hipSuccess ||
         hipMalloc((void**)&ldl, std::max<size_t>(8, (size_t)s->n_jump * dd2 * 8)) != hipSuccess ||
         (big && hipMalloc((void**)&tmp, tb) != hipSuccess)) {
@@ -1753,8 +1772,26 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       for (int p = 0; p < nc; ++p)
         for (int q = p + 1; q < nc; ++q) HIPCHK(comm(tile(p), tile(q), tile(j++)), "comm");
     }
-    HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
-    HIPCHK(hipDeviceSynchronize(), "set_system sync");
+    if (real) {
+      // the real form R_j = T B_j T^dag in the basis of Hermitian operators,
+      // kept in FP64 for the tile lists and cast to the FP32 copy
+      double* r64 = nullptr;
+      if (hipMalloc((void**)&r64, (size_t)nb * nn * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(ops);
+        (void)hipFree(ldl);
+        if (tmp) (void)hipFree(tmp);
+        return c->fail(LMAG_E_NOMEM, "basis allocation failed");
+      }
+      HIPCHK(launch_to_real(c->basis64, d, nb, r64, st), "basis (real)");
+      HIPCHK(launch_rcast(r64, (float*)c->basis32, (size_t)nb * nn, st), "cast");
+      HIPCHK(hipDeviceSynchronize(), "set_system sync");
+      (void)hipFree(c->basis64);
+      c->basis64 = r64;
+    } else {
+      HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
+      HIPCHK(hipDeviceSynchronize(), "set_system sync");
+    }
     if (big) {
       // the basis elements with a nonzero 64 x 64 tile, per tile position:
       // the exponent assembly and the traces skip the all-zero tiles
@@ -1763,7 +1800,8 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       uint8_t* fl = nullptr;
       std::vector<uint8_t> flh((size_t)nb * nt);
       if (hipMalloc((void**)&fl, flh.size()) == hipSuccess) {
-        if (launch_tile_flags(c->basis64, nb, d * d, fl, st) == hipSuccess &&
+        if ((real ? launch_rtile_flags(c->basis64, nb, d * d, fl, st)
+                  : launch_tile_flags(c->basis64, nb, d * d, fl, st)) == hipSuccess &&
             hipMemcpy(flh.data(), fl, flh.size(), hipMemcpyDeviceToHost) == hipSuccess) {
           std::vector<int32_t> lists(nt + 1, 0);
           for (size_t t = 0; t < nt; ++t)
@@ -1803,6 +1841,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     c->prec = s->precision; c->order = s->magnus_order; c->hold = s->hold; c->nb = nb;
     c->chunk = s->chunk_slices; c->ws_max = s->workspace_bytes_max;
     c->tiled = big;
+    c->real = real;
     c->has_sys = true;
     return LMAG_OK;
   } catch (const std::bad_alloc&) {
@@ -1973,7 +2012,11 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     double best = 1e300;
     int bestC = chunks[0], bestInv = 0;
     std::vector<int> variants{0, 1, 2};
-    if (big) {
+    if (big && c->real) {
+      // the real product kernel, without and with the XCD grouping
+      variants = {0};
+      if (c->n / 64 <= 16) variants.push_back(5);
+    } else if (big) {
       variants.push_back(3);
       if ((c->n / 64) % 2 == 0) variants.push_back(4);
       variants.push_back(6);

@@ -17,8 +17,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def run(cfg, amps, chunk=0, want_grad=True, dissipative=True):
-    sysm = lib_system(cfg, "f32", cfg["order"], cfg["hold"], chunk=chunk, dissipative=dissipative)
+def run(cfg, amps, chunk=0, want_grad=True, dissipative=True, block_basis="hermitian"):
+    sysm = lib_system(cfg, "f32", cfg["order"], cfg["hold"], chunk=chunk, dissipative=dissipative,
+                      block_basis=block_basis)
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     b = np.asarray(cfg["B"])[None, :]
     N = len(amps)
@@ -28,11 +29,12 @@ def run(cfg, amps, chunk=0, want_grad=True, dissipative=True):
     return sysm, U, F.cpu().numpy()[0], (g.cpu().numpy().astype(float) if g is not None else None)
 
 
+@pytest.mark.parametrize("basis", ["hermitian", "column"])
 @pytest.mark.parametrize("chunk", [0, 3])
-def test_four_spin_small_matches_oracle(chunk):
+def test_four_spin_small_matches_oracle(chunk, basis):
     cfg = synth.small_case(71, n_spins=4, n_slices=12, dt=2.5e-4)
     amps = rounded(cfg["amps"], "f32")
-    sysm, U, F, g = run(cfg, amps, chunk)
+    sysm, U, F, g = run(cfg, amps, chunk, block_basis=basis)
     osys = oracle_system(cfg)
     U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
     assert rel(U, U_ref) < 2e-5
@@ -41,11 +43,12 @@ def test_four_spin_small_matches_oracle(chunk):
     assert rel(g, g_ref) < 1e-3
 
 
-def test_four_spin_with_squarings():
+@pytest.mark.parametrize("basis", ["hermitian", "column"])
+def test_four_spin_with_squarings(basis):
     # 1 ns slices of large amplitudes push ||Omega||_1 above theta_3: s > 0
     cfg = synth.small_case(72, n_spins=4, n_slices=6, dt=4e-3)
     amps = rounded(cfg["amps"], "f32")
-    sysm, U, F, g = run(cfg, amps, 2)
+    sysm, U, F, g = run(cfg, amps, 2, block_basis=basis)
     hist = sysm.selection_histogram()
     assert hist[1, 1:].sum() > 0   # Pade-3 with squarings
     osys = oracle_system(cfg)
@@ -252,20 +255,22 @@ def _tuning_line(path, d, total, chunk, variant):
                 % (d, b, chunk, variant))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
-def test_four_spin_product_kernels_match_oracle(variant, tmp_path):
+@pytest.mark.parametrize("basis,variant", [("column", v) for v in range(9)] +
+                         [("hermitian", 0), ("hermitian", 5)])
+def test_four_spin_product_kernels_match_oracle(basis, variant, tmp_path):
     """Each product kernel of the block-tiled path (register-B tiles with the
     16x16x4 MFMA; a quadrant per wave with 16x16x4; a quadrant per wave with
     32x32x2; a quadrant per wave with split-bf16 operands on the 16x16x32 bf16
     MFMA; two output tiles per eight-wave workgroup; register-B tiles with each
     product on one XCD; register-B tiles at three workgroups per CU, without and
     with the XCD grouping; register-B tiles with the A tiles double-buffered in
-    LDS by direct global-to-LDS loads), selected through a tuning line:
-    propagator, F and gradient against the oracle, with squarings in some
+    LDS by direct global-to-LDS loads; in the real Hermitian-operator basis the
+    real kernel without and with the XCD grouping), selected through a tuning
+    line: propagator, F and gradient against the oracle, with squarings in some
     slices."""
     cfg = synth.small_case(75, n_spins=4, n_slices=14, dt=2e-3)
     amps = rounded(cfg["amps"], "f32")
-    sysm = lib_system(cfg, "f32", 2, "foh")
+    sysm = lib_system(cfg, "f32", 2, "foh", block_basis=basis)
     path = tmp_path / "tune.jsonl"
     _tuning_line(path, 16, 14, 4, variant)
     sysm.load_tuning(str(path))
@@ -351,3 +356,20 @@ def test_block_tiled_output_at_unaligned_address():
     torch.cuda.synchronize()
     assert torch.equal(view.view(1, n, n), U)
     assert buf[0].item() == 0
+
+
+def test_hermitian_and_column_bases_agree():
+    """The two representations of the block-tiled path on one 4-spin pulse of
+    64 slices: propagator, F and gradient agree to FP32 rounding, and the real
+    one uses half the workspace."""
+    cfg = synth.small_case(79, n_spins=4, n_slices=64, dt=1e-3)
+    amps = rounded(cfg["amps"], "f32")
+    out = {}
+    for basis in ("hermitian", "column"):
+        sysm, U, F, g = run(cfg, amps, 8, block_basis=basis)
+        out[basis] = (U, F, g, sysm.last_plan()["workspace_bytes"])
+    (Uh, Fh, gh, wh), (Uc, Fc, gc, wc) = out["hermitian"], out["column"]
+    assert rel(Uh, Uc) < 2e-5
+    assert abs(Fh - Fc) < 1e-6
+    assert rel(gh, gc) < 1e-4
+    assert wh < 0.6 * wc

@@ -2,7 +2,7 @@
 n = 576 = 9 x 64 (nine tile rows; the two-tile kernel and the XCD grouping
 fall back where their shape conditions fail), with random Hermitian static and
 control terms and two jump operators, through every block-tiled product
-kernel, element by element against the oracle (propagator, F and the whole
+kernel in both representations, element by element against the oracle (propagator, F and the whole
 gradient), with slices at Pade degree 2 and 3 and with squarings."""
 import numpy as np
 import pytest
@@ -71,11 +71,12 @@ def reference():
     return (Hs, Hc, Ls, coef, amps, dt, UT), U_ref, F_ref, g_ref
 
 
-@pytest.mark.parametrize("variant", [0, 4, 5, 6, 7, 8])
-def test_nine_tile_rows_every_product_kernel(reference, variant, tmp_path):
+@pytest.mark.parametrize("basis,variant", [("column", v) for v in (0, 4, 5, 6, 7, 8)] +
+                         [("hermitian", 0), ("hermitian", 5)])
+def test_nine_tile_rows_every_product_kernel(reference, basis, variant, tmp_path):
     from paper_2511_13330_amd.system import System
     (Hs, Hc, Ls, coef, amps, dt, UT), U_ref, F_ref, g_ref = reference
-    sysm = System(Hs, Hc, Ls, precision="f32", magnus_order=2, hold="foh")
+    sysm = System(Hs, Hc, Ls, precision="f32", magnus_order=2, hold="foh", block_basis=basis)
     N = len(amps)
     with open(tmp_path / "tune.jsonl", "w") as f:
         f.write('{"key": "p32_o2_d%d_s%d", "chunk": 3, "variant": %d, "ms": 0.0}\n'
@@ -85,7 +86,11 @@ def test_nine_tile_rows_every_product_kernel(reference, variant, tmp_path):
     st = np.asarray(coef)[None, :]
     U = sysm.propagate(a, [N], dt, static_coef=st).cpu().numpy()[0].astype(complex)
     hist = sysm.selection_histogram()
-    assert hist[0].sum() > 0 and hist[1].sum() > 0 and hist[1, 1:].sum() > 0   # m = 2, m = 3, s > 0
+    # m = 3 with s > 0 on the strong slices; in column stacking the weak ones sit
+    # at m = 2 (the 1-norm, and so the selection, depends on the representation)
+    assert hist[1, 1:].sum() > 0
+    if basis == "column":
+        assert hist[0].sum() > 0
     assert rel(U, U_ref) < 1e-4
     F, g = sysm.fidelity_and_grad(a, [N], dt, UT, static_coef=st)
     assert abs(F.item() - F_ref) < 1e-6
