@@ -299,7 +299,8 @@ def large_system(args):
     t0 = time.perf_counter()
     sysm = spin_chain_system(cfg["n_spins"], cfg["T1"], cfg["T2"], precision="f32",
                              magnus_order=2, hold="foh", chunk_slices=args.chunk,
-                             workspace_bytes_max=int(args.workspace_gb * (1 << 30)))
+                             workspace_bytes_max=int(args.workspace_gb * (1 << 30)),
+                             block_basis=args.block_basis)
     t_setup = time.perf_counter() - t0
     N = cfg["n_slices"]
     a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
@@ -328,14 +329,21 @@ def large_system(args):
     prof = sysm.read_profile()
     hist = sysm.selection_histogram()
     n = 4 ** cfg["n_spins"]
+    # the products' count in complex flops (8 n^3 each); in the real basis of
+    # Hermitian operators each is one real product (2 n^3)
     flops = (flops_from_hist(hist, forward_flops_per_slice)
              + flops_from_hist(hist, backward_flops_per_slice)) * (n / N_SUPER) ** 3
+    if args.block_basis == "hermitian":
+        flops /= 4.0
     return {"metric": f"fwd+grad evaluations/s ({cfg['n_spins']} spins, {N} slices)",
             "value": 1.0 / dt, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
             "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded config-3 draws)",
             "config": {"workload": f"{cfg['n_spins']} spins, superoperator {n}x{n}, {N} slices of "
                                    f"{cfg['dt'] * 1e3:g} ns, FOH 2nd order, FP32 fwd+grad",
                        "workspace_budget_gib": args.workspace_gb or None,
+                       "representation": ("real (basis of Hermitian operators)"
+                                          if args.block_basis == "hermitian"
+                                          else "complex (column stacking)"),
                        "autotune": {"chunk": tuned[0], "product_kernel": tuned[1], "ms": tuned[2]}
                        if tuned else None,
                        "plan": sysm.last_plan()},
@@ -357,7 +365,8 @@ def hubbard(args):
     t0 = time.perf_counter()
     sysm = hubbard_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2, hold="foh",
                           chunk_slices=args.chunk,
-                          workspace_bytes_max=int(args.workspace_gb * (1 << 30)))
+                          workspace_bytes_max=int(args.workspace_gb * (1 << 30)),
+                          block_basis=args.block_basis)
     t_setup = time.perf_counter() - t0
     N = cfg["n_slices"]
     a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
@@ -386,7 +395,10 @@ def hubbard(args):
             "data": "synthetic (seeded Hubbard parameters and hopping pulses; the paper gives none)",
             "config": {"workload": f"3 dots x 4 states, {N} slices of {cfg['dt'] * 1e3:g} ns, FOH "
                                    "2nd order, T1/T2 per dot", "plan_propagate": plan_prop,
-                       "plan_fwd_grad": sysm.last_plan()},
+                       "plan_fwd_grad": sysm.last_plan(),
+                       "representation": ("real (basis of Hermitian operators)"
+                                          if args.block_basis == "hermitian"
+                                          else "complex (column stacking)")},
             "seconds_fwd_grad": t_fg, "seconds_set_system": t_setup, "F": float(F.item()),
             "context": "paper (Sec. IV): 1 min 15 s per propagator on an AMD EPYC 9634 CPU for this "
                        "superoperator size, slice count not stated"}
@@ -404,6 +416,9 @@ def main():
                     help="workspace budget of the large-system workloads in GiB (0 = 85 %% of free "
                          "device memory); beyond it the adjoint recomputes the forward")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
+    ap.add_argument("--block-basis", default="hermitian", choices=["hermitian", "column"],
+                    help="representation of the large-system workloads: the real basis of "
+                         "Hermitian operators (default) or column stacking (complex)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune chunk length and inverse variant before the timed steps")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2511_13330_amd", "tuning",
