@@ -310,7 +310,8 @@ def large_system(args):
         tuned = sysm.autotune(a, [N], cfg["dt"], cfg["U_target"], static_coef=b, reps=1)
     elif args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
         sysm.load_tuning(args.tuning)
-        key = f"p32_o2_d{cfg['d']}_s{int(np.floor(np.log2(N)))}"
+        tag = "h" if args.block_basis == "hermitian" else ""
+        key = f"p32{tag}_o2_d{cfg['d']}_s{int(np.floor(np.log2(N)))}"
         with open(args.tuning) as f:
             for line in f:
                 rec = json.loads(line)

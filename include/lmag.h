@@ -236,7 +236,10 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * product's tiles on one XCD (n <= 1024); 6: as 0 without the operand pipeline,
  * three workgroups per CU; 7: as 6 with the grouping of 5; 8: as 0 with the A
  * tiles double-buffered in LDS by direct global-to-LDS loads (grouped as 5
- * where n <= 1024) -- at the automatic chunk length, half and twice it. 64 x 64 systems: the
+ * where n <= 1024) -- at the automatic chunk length, half and twice it. In the
+ * real basis of Hermitian operators (block_basis 0) the candidates are the real
+ * product kernel (0) and, where n <= 1024, the same with the grouping of 5 (5).
+ * 64 x 64 systems: the
  * persistent slice kernels, for every candidate chunk length (slices per work
  * unit) and the inverse variants
  * of the Pade step (0: per slice the cheapest whose error bound holds -- in
@@ -245,9 +248,11 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * binary-Neumann product, else Gauss-Jordan; 1: Gauss-Jordan always; 2: Neumann
  * where its bound allows, else Gauss-Jordan; 1 and 2 always form
  * r_m = q_m^{-1} p_m). The fastest pair is kept
- * for calls with chunk_slices = 0 whose precision, order, d and total slice
- * count (power-of-two bucket) match, and appended as one JSON line
- * {"key", "chunk", "variant", "ms"} to the file named by the environment
+ * for calls with chunk_slices = 0 whose precision, representation, order, d
+ * and total slice count (power-of-two bucket) match (key
+ * "p<precision>[h]_o<order>_d<d>_s<log2 slices>", h for the real basis), and
+ * appended as one JSON line {"key", "chunk", "variant", "ms"} to the file
+ * named by the environment
  * variable LMAG_TUNE_CACHE if it is set. With LMAG_TUNE_VERBOSE set, each
  * candidate's time is written to stderr as it is measured.
  * best_out: HOST int32 [2] (chunk, variant: inverse variant or product kernel)

@@ -209,7 +209,8 @@ lmag_status validate_batch(lmag_ctx* c, const lmag_batch* b, const int32_t* targ
 std::string tune_key(const lmag_ctx* c, long long total) {
   int b = 0;
   while ((1LL << (b + 1)) <= total) ++b;
-  return "p" + std::to_string(c->prec) + "_o" + std::to_string(c->order) + "_d" +
+  // "h": the block-tiled path in the real basis of Hermitian operators
+  return "p" + std::to_string(c->prec) + (c->real ? "h" : "") + "_o" + std::to_string(c->order) + "_d" +
          std::to_string(c->d) + "_s" + std::to_string(b);
 }
 

@@ -248,11 +248,12 @@ def test_six_spin_full_pulse_under_64_GB():
     assert rel(U, hb.superop(V)) <= 1e-4
 
 
-def _tuning_line(path, d, total, chunk, variant):
+def _tuning_line(path, d, total, chunk, variant, basis="column"):
     b = int(np.floor(np.log2(total)))
+    tag = "h" if basis == "hermitian" else ""
     with open(path, "w") as f:
-        f.write('{"key": "p32_o2_d%d_s%d", "chunk": %d, "variant": %d, "ms": 0.0}\n'
-                % (d, b, chunk, variant))
+        f.write('{"key": "p32%s_o2_d%d_s%d", "chunk": %d, "variant": %d, "ms": 0.0}\n'
+                % (tag, d, b, chunk, variant))
 
 
 @pytest.mark.parametrize("basis,variant", [("column", v) for v in range(9)] +
@@ -272,7 +273,7 @@ def test_four_spin_product_kernels_match_oracle(basis, variant, tmp_path):
     amps = rounded(cfg["amps"], "f32")
     sysm = lib_system(cfg, "f32", 2, "foh", block_basis=basis)
     path = tmp_path / "tune.jsonl"
-    _tuning_line(path, 16, 14, 4, variant)
+    _tuning_line(path, 16, 14, 4, variant, basis)
     sysm.load_tuning(str(path))
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     b = np.asarray(cfg["B"])[None, :]

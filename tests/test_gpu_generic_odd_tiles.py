@@ -79,8 +79,8 @@ def test_nine_tile_rows_every_product_kernel(reference, basis, variant, tmp_path
     sysm = System(Hs, Hc, Ls, precision="f32", magnus_order=2, hold="foh", block_basis=basis)
     N = len(amps)
     with open(tmp_path / "tune.jsonl", "w") as f:
-        f.write('{"key": "p32_o2_d%d_s%d", "chunk": 3, "variant": %d, "ms": 0.0}\n'
-                % (D, int(np.floor(np.log2(N))), variant))
+        f.write('{"key": "p32%s_o2_d%d_s%d", "chunk": 3, "variant": %d, "ms": 0.0}\n'
+                % ("h" if basis == "hermitian" else "", D, int(np.floor(np.log2(N))), variant))
     sysm.load_tuning(str(tmp_path / "tune.jsonl"))
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     st = np.asarray(coef)[None, :]
