@@ -184,13 +184,117 @@ __global__ void __launch_bounds__(WG) k_rgemm(BigGemmArgs g) {
   }
 }
 
+// Real product kernel 1: a 128 x 128 output tile per workgroup, four waves in
+// a 2 x 2 arrangement each owning 64 x 64 (16 accumulator blocks), k-steps of
+// 32 with the A tile (128 x 32) and the transposed B tile (128 x 32) staged in
+// LDS, so that every lane reads its four consecutive k values of an operand with
+// one 16-byte load (pitch 36 floats: 16 rows at one k offset hit 16 different
+// bank groups). Twice the products per staged byte of the 64 x 64 kernel.
+// n must be a multiple of 128.
+constexpr int R2P = 36;   // LDS pitch (floats) of the 32-wide staged tiles
+
+__global__ void __launch_bounds__(WG) k_rgemm128(BigGemmArgs g) {
+  __shared__ __attribute__((aligned(16))) float sa[128 * R2P];
+  __shared__ __attribute__((aligned(16))) float sb[128 * R2P];   // B^T: [column][k]
+  const int T2 = g.n / 128;
+  const size_t nn = (size_t)g.n * g.n;
+  const int b = blockIdx.y, ti = blockIdx.x / T2, tj = blockIdx.x % T2;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, gq = l >> 4, c = l & 15;
+  const int wr = w >> 1, wc = w & 1;   // this wave's 64 x 64 quadrant
+  const size_t off = (size_t)ti * 128 * g.n + tj * 128;
+  float* C = const_cast<float*>(rmat(g.C, g.Ci, b, nn));
+  const float* D = g.D ? rmat(g.D, g.Di, b, nn) : nullptr;
+  const bool active = !g.pred || g.pred[(size_t)(g.Ci ? g.Ci[b] : b) * g.pred_stride] > g.pred_thresh;
+  // element (rb, cb, r) of this lane: row 64 wr + 16 rb + 4 gq + r, column 64 wc + 16 cb + c
+  auto at = [&](int rb, int cb, int r) {
+    return (size_t)(64 * wr + 16 * rb + 4 * gq + r) * g.n + 64 * wc + 16 * cb + c;
+  };
+  if (!active) {
+    const float* src = (D ? D : rmat(g.A, g.Ai, b, nn)) + off;
+    for (int rb = 0; rb < 4; ++rb)
+      for (int cb = 0; cb < 4; ++cb)
+        for (int r = 0; r < 4; ++r) C[off + at(rb, cb, r)] = src[at(rb, cb, r)];
+    return;
+  }
+  const float* A = rmat(g.A, g.Ai, b, nn) + (size_t)ti * 128 * g.n;
+  const float* B = rmat(g.B, g.Bi, b, nn) + tj * 128;
+  f4v acc[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = f4v{0.f, 0.f, 0.f, 0.f};
+  // staging: A rows (128 x 32): thread -> row tid / 2, k 16 (tid & 1) .. +15 (four f4v);
+  // B rows k (32 x 128): thread -> k tid / 8, columns 16 (tid & 7) .. +15
+  const int ar = tid >> 1, ak = 16 * (tid & 1);
+  const int bk = tid >> 3, bc = 16 * (tid & 7);
+  for (int k0 = 0; k0 < g.n; k0 += 32) {
+    f4v va[4], vb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      va[i] = *reinterpret_cast<const f4v*>(A + (size_t)ar * g.n + k0 + ak + 4 * i);
+      vb[i] = *reinterpret_cast<const f4v*>(B + (size_t)(k0 + bk) * g.n + bc + 4 * i);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      *reinterpret_cast<f4v*>(sa + ar * R2P + ak + 4 * i) = va[i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sb[(bc + 4 * i + j) * R2P + bk] = vb[i][j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      f4v av[4], bv[4];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+        av[rb] = *reinterpret_cast<const f4v*>(sa + (64 * wr + 16 * rb + c) * R2P + 16 * kb + 4 * gq);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        bv[cb] = *reinterpret_cast<const f4v*>(sb + (64 * wc + 16 * cb + c) * R2P + 16 * kb + 4 * gq);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 4; ++cb)
+            acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][t], bv[cb][t], acc[rb][cb], 0, 0, 0);
+    }
+  }
+  const float al = (float)g.alpha, be = (float)g.beta, be2 = (float)g.beta2;
+  const float* D2 = g.D2 ? rmat(g.D2, g.D2i, b, nn) + off : nullptr;
+  const float* E2 = g.E2 ? rmat(g.E2, g.E2i, b, nn) + off : nullptr;
+  float* C2 = g.C2 ? const_cast<float*>(rmat(g.C2, g.C2i, b, nn)) + off : nullptr;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t e = at(rb, cb, r);
+        float v = al * acc[rb][cb][r];
+        if (D && g.beta != 0.0) v += be * D[off + e];
+        if (D2 && g.beta2 != 0.0) v += be2 * D2[e];
+        const bool diag = ti == tj && wr == wc && rb == cb && 4 * gq + r == c;
+        if (diag && g.gamma != 0.0) v += (float)g.gamma;
+        C[off + e] = v;
+        if (C2) {
+          float v2 = (float)g.c2_c * v;
+          if (E2) v2 += (float)g.c2_e * E2[e];
+          if (diag && g.c2_gamma != 0.0) v2 += (float)g.c2_gamma;
+          C2[e] = v2;
+        }
+      }
+}
+
 hipError_t launch_rgemm(const BigGemmArgs& g, hipStream_t s) {
   if (g.batch <= 0) return hipSuccess;
   if (g.C2 && g.pred) return hipErrorInvalidValue;
   if (g.transA || g.transB) return hipErrorInvalidValue;
   const int Tn = g.n / 64;
   const size_t total = (size_t)Tn * Tn * g.batch;
-  if (g.variant == 5 && Tn <= 16 && total % 8 == 0 && total <= 0x7fffffff)
+  if (g.variant == 1 && Tn % 2 == 0)
+    hipLaunchKernelGGL(k_rgemm128, dim3((Tn / 2) * (Tn / 2), g.batch), dim3(WG), 0, s, g);
+  else if (g.variant == 5 && Tn <= 16 && total % 8 == 0 && total <= 0x7fffffff)
     hipLaunchKernelGGL(k_rgemm<true>, dim3((unsigned)total), dim3(WG), 0, s, g);
   else
     hipLaunchKernelGGL(k_rgemm<false>, dim3(Tn * Tn, g.batch), dim3(WG), 0, s, g);

@@ -257,7 +257,7 @@ def _tuning_line(path, d, total, chunk, variant, basis="column"):
 
 
 @pytest.mark.parametrize("basis,variant", [("column", v) for v in range(9)] +
-                         [("hermitian", 0), ("hermitian", 5)])
+                         [("hermitian", 0), ("hermitian", 1), ("hermitian", 5)])
 def test_four_spin_product_kernels_match_oracle(basis, variant, tmp_path):
     """Each product kernel of the block-tiled path (register-B tiles with the
     16x16x4 MFMA; a quadrant per wave with 16x16x4; a quadrant per wave with
@@ -266,7 +266,8 @@ def test_four_spin_product_kernels_match_oracle(basis, variant, tmp_path):
     product on one XCD; register-B tiles at three workgroups per CU, without and
     with the XCD grouping; register-B tiles with the A tiles double-buffered in
     LDS by direct global-to-LDS loads; in the real Hermitian-operator basis the
-    real kernel without and with the XCD grouping), selected through a tuning
+    real 64 x 64 kernel without and with the XCD grouping and the real 128 x 128
+    kernel), selected through a tuning
     line: propagator, F and gradient against the oracle, with squarings in some
     slices."""
     cfg = synth.small_case(75, n_spins=4, n_slices=14, dt=2e-3)
