@@ -120,7 +120,7 @@ __device__ __forceinline__ void rr_stage(const RTR& X, float* S) {
 // per workgroup: the A tile staged in LDS, the B tile in registers. Entries
 // with pred <= thresh copy D_b (A_b when D is null) into C_b. XCD as the
 // complex kernels: a one-dimensional grid with every product on one XCD.
-template <bool XCD>
+template <bool XCD, bool PIPE>
 __global__ void __launch_bounds__(WG) k_rgemm(BigGemmArgs g) {
   __shared__ __attribute__((aligned(16))) float sa[64 * RPITCH];
   const int Tn = g.n / 64;
@@ -151,13 +151,30 @@ __global__ void __launch_bounds__(WG) k_rgemm(BigGemmArgs g) {
   const float* B = rmat(g.B, g.Bi, b, nn) + tj * 64;
   RTR acc, At, Bt;
   rr_zero(acc);
-  for (int tk = 0; tk < Tn; ++tk) {
-    rr_load(At, A + tk * 64, g.n);
-    rr_load(Bt, B + (size_t)tk * 64 * g.n, g.n);
-    __syncthreads();
-    rr_stage(At, sa);
-    __syncthreads();
-    rr_gemm(acc, sa, Bt);
+  if constexpr (PIPE) {
+    // the next k-step's tiles are requested before this step's products
+    rr_load(At, A, g.n);
+    rr_load(Bt, B, g.n);
+    for (int tk = 0; tk < Tn; ++tk) {
+      __syncthreads();
+      rr_stage(At, sa);
+      __syncthreads();
+      const RTR Bc = Bt;
+      if (tk + 1 < Tn) {
+        rr_load(At, A + (tk + 1) * 64, g.n);
+        rr_load(Bt, B + (size_t)(tk + 1) * 64 * g.n, g.n);
+      }
+      rr_gemm(acc, sa, Bc);
+    }
+  } else {
+    for (int tk = 0; tk < Tn; ++tk) {
+      rr_load(At, A + tk * 64, g.n);
+      rr_load(Bt, B + (size_t)tk * 64 * g.n, g.n);
+      __syncthreads();
+      rr_stage(At, sa);
+      __syncthreads();
+      rr_gemm(acc, sa, Bt);
+    }
   }
   rr_scale(acc, (float)g.alpha);
   if (D && g.beta != 0.0) {
@@ -292,12 +309,17 @@ hipError_t launch_rgemm(const BigGemmArgs& g, hipStream_t s) {
   if (g.transA || g.transB) return hipErrorInvalidValue;
   const int Tn = g.n / 64;
   const size_t total = (size_t)Tn * Tn * g.batch;
+  const bool xcd = Tn <= 16 && total % 8 == 0 && total <= 0x7fffffff;
   if (g.variant == 1 && Tn % 2 == 0)
     hipLaunchKernelGGL(k_rgemm128, dim3((Tn / 2) * (Tn / 2), g.batch), dim3(WG), 0, s, g);
-  else if (g.variant == 5 && Tn <= 16 && total % 8 == 0 && total <= 0x7fffffff)
-    hipLaunchKernelGGL(k_rgemm<true>, dim3((unsigned)total), dim3(WG), 0, s, g);
+  else if (g.variant == 5 && xcd)
+    hipLaunchKernelGGL((k_rgemm<true, false>), dim3((unsigned)total), dim3(WG), 0, s, g);
+  else if (g.variant == 7 && xcd)
+    hipLaunchKernelGGL((k_rgemm<true, true>), dim3((unsigned)total), dim3(WG), 0, s, g);
+  else if (g.variant == 2 || g.variant == 7)
+    hipLaunchKernelGGL((k_rgemm<false, true>), dim3(Tn * Tn, g.batch), dim3(WG), 0, s, g);
   else
-    hipLaunchKernelGGL(k_rgemm<false>, dim3(Tn * Tn, g.batch), dim3(WG), 0, s, g);
+    hipLaunchKernelGGL((k_rgemm<false, false>), dim3(Tn * Tn, g.batch), dim3(WG), 0, s, g);
   return hipGetLastError();
 }
 

@@ -2014,11 +2014,15 @@ lmag_status lmag_autotune(lmag_ctx* c, const lmag_batch* b, const void* U_target
     int bestC = chunks[0], bestInv = 0;
     std::vector<int> variants{0, 1, 2};
     if (big && c->real) {
-      // the real product kernels: 64 x 64 tiles without and with the XCD
-      // grouping, 128 x 128 tiles
-      variants = {0};
+      // the real product kernels: 64 x 64 tiles without and with the next
+      // k-step's tiles requested ahead, each without and with the XCD
+      // grouping; 128 x 128 tiles
+      variants = {0, 2};
       if ((c->n / 64) % 2 == 0) variants.push_back(1);
-      if (c->n / 64 <= 16) variants.push_back(5);
+      if (c->n / 64 <= 16) {
+        variants.push_back(5);
+        variants.push_back(7);
+      }
     } else if (big) {
       variants.push_back(3);
       if ((c->n / 64) % 2 == 0) variants.push_back(4);

@@ -257,7 +257,7 @@ def _tuning_line(path, d, total, chunk, variant, basis="column"):
 
 
 @pytest.mark.parametrize("basis,variant", [("column", v) for v in range(9)] +
-                         [("hermitian", 0), ("hermitian", 1), ("hermitian", 5)])
+                         [("hermitian", v) for v in (0, 1, 2, 5, 7)])
 def test_four_spin_product_kernels_match_oracle(basis, variant, tmp_path):
     """Each product kernel of the block-tiled path (register-B tiles with the
     16x16x4 MFMA; a quadrant per wave with 16x16x4; a quadrant per wave with
