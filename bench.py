@@ -373,6 +373,17 @@ def hubbard(args):
     a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
     b = torch.tensor(np.asarray(cfg["coef"])[None, :], dtype=torch.float64, device="cuda")
     UT = torch.as_tensor(cfg["U_target"], dtype=torch.complex128, device="cuda")
+    tuned = None
+    if args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
+        # the autotuner's stored choice for this size (same key as the library's)
+        sysm.load_tuning(args.tuning)
+        tag = "h" if args.block_basis == "hermitian" else ""
+        key = f"p32{tag}_o2_d{cfg['d']}_s{int(np.floor(np.log2(N)))}"
+        with open(args.tuning) as f:
+            for line in f:
+                rec = json.loads(line)
+                if rec.get("key") == key:
+                    tuned = {"chunk": rec["chunk"], "product_kernel": rec.get("variant"), "ms": rec["ms"]}
     U = sysm.propagate(a, [N], cfg["dt"], static_coef=b)            # warm-up
     torch.cuda.synchronize()
     steps = max(1, min(args.steps, 3))
@@ -396,7 +407,7 @@ def hubbard(args):
             "data": "synthetic (seeded Hubbard parameters and hopping pulses; the paper gives none)",
             "config": {"workload": f"3 dots x 4 states, {N} slices of {cfg['dt'] * 1e3:g} ns, FOH "
                                    "2nd order, T1/T2 per dot", "plan_propagate": plan_prop,
-                       "plan_fwd_grad": sysm.last_plan(),
+                       "plan_fwd_grad": sysm.last_plan(), "autotune": tuned,
                        "representation": ("real (basis of Hermitian operators)"
                                           if args.block_basis == "hermitian"
                                           else "complex (column stacking)")},

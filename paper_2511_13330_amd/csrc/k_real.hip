@@ -255,8 +255,14 @@ __global__ void __launch_bounds__(WG) k_rgemm128(BigGemmArgs g) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       *reinterpret_cast<f4v*>(sa + ar * R2P + ak + 4 * i) = va[i];
+      // B^T row (column of B) bc + 4 i + j, k-granule (bk / 4) permuted by the
+      // column's 16-block index, so that the eight threads of one k row, whose
+      // columns are 16 apart, write eight different banks
 #pragma unroll
-      for (int j = 0; j < 4; ++j) sb[(bc + 4 * i + j) * R2P + bk] = vb[i][j];
+      for (int j = 0; j < 4; ++j) {
+        const int col = bc + 4 * i + j;
+        sb[col * R2P + 4 * ((bk >> 2) ^ ((col >> 4) & 7)) + (bk & 3)] = vb[i][j];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -267,7 +273,8 @@ __global__ void __launch_bounds__(WG) k_rgemm128(BigGemmArgs g) {
         av[rb] = *reinterpret_cast<const f4v*>(sa + (64 * wr + 16 * rb + c) * R2P + 16 * kb + 4 * gq);
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb)
-        bv[cb] = *reinterpret_cast<const f4v*>(sb + (64 * wc + 16 * cb + c) * R2P + 16 * kb + 4 * gq);
+        bv[cb] = *reinterpret_cast<const f4v*>(sb + (64 * wc + 16 * cb + c) * R2P +
+                                               4 * ((4 * kb + gq) ^ ((4 * wc + cb) & 7)));
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
