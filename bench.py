@@ -235,7 +235,8 @@ def robust_sweep(args):
     n_cand = int(os.environ.get("LMAG_ROBUST_CANDIDATES", "256"))
     cfg = synth.config2(2, n_cand=n_cand)
     sysm = spin_chain_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2,
-                             hold="foh", chunk_slices=args.chunk)
+                             hold="foh", chunk_slices=args.chunk, basis=args.basis)
+    real = args.basis == "hermitian"
     amps = np.concatenate(cfg["amps_per_cand"])
     ns_c = np.asarray(cfg["n_slices_per_cand"])
     off_c = np.concatenate([[0], np.cumsum(ns_c)[:-1]])
@@ -300,7 +301,7 @@ def large_system(args):
     sysm = spin_chain_system(cfg["n_spins"], cfg["T1"], cfg["T2"], precision="f32",
                              magnus_order=2, hold="foh", chunk_slices=args.chunk,
                              workspace_bytes_max=int(args.workspace_gb * (1 << 30)),
-                             block_basis=args.block_basis)
+                             basis=args.basis)
     t_setup = time.perf_counter() - t0
     N = cfg["n_slices"]
     a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
@@ -310,7 +311,7 @@ def large_system(args):
         tuned = sysm.autotune(a, [N], cfg["dt"], cfg["U_target"], static_coef=b, reps=1)
     elif args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
         sysm.load_tuning(args.tuning)
-        tag = "h" if args.block_basis == "hermitian" else ""
+        tag = "h" if args.basis == "hermitian" else ""
         key = f"p32{tag}_o2_d{cfg['d']}_s{int(np.floor(np.log2(N)))}"
         with open(args.tuning) as f:
             for line in f:
@@ -334,7 +335,7 @@ def large_system(args):
     # Hermitian operators each is one real product (2 n^3)
     flops = (flops_from_hist(hist, forward_flops_per_slice)
              + flops_from_hist(hist, backward_flops_per_slice)) * (n / N_SUPER) ** 3
-    if args.block_basis == "hermitian":
+    if args.basis == "hermitian":
         flops /= 4.0
     return {"metric": f"fwd+grad evaluations/s ({cfg['n_spins']} spins, {N} slices)",
             "value": 1.0 / dt, "unit": "evals/s", "n_gpus": 1, "higher_is_better": True,
@@ -343,7 +344,7 @@ def large_system(args):
                                    f"{cfg['dt'] * 1e3:g} ns, FOH 2nd order, FP32 fwd+grad",
                        "workspace_budget_gib": args.workspace_gb or None,
                        "representation": ("real (basis of Hermitian operators)"
-                                          if args.block_basis == "hermitian"
+                                          if args.basis == "hermitian"
                                           else "complex (column stacking)"),
                        "autotune": {"chunk": tuned[0], "product_kernel": tuned[1], "ms": tuned[2]}
                        if tuned else None,
@@ -367,7 +368,7 @@ def hubbard(args):
     sysm = hubbard_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2, hold="foh",
                           chunk_slices=args.chunk,
                           workspace_bytes_max=int(args.workspace_gb * (1 << 30)),
-                          block_basis=args.block_basis)
+                          basis=args.basis)
     t_setup = time.perf_counter() - t0
     N = cfg["n_slices"]
     a = torch.tensor(cfg["amps"], dtype=torch.float32, device="cuda")
@@ -377,7 +378,7 @@ def hubbard(args):
     if args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
         # the autotuner's stored choice for this size (same key as the library's)
         sysm.load_tuning(args.tuning)
-        tag = "h" if args.block_basis == "hermitian" else ""
+        tag = "h" if args.basis == "hermitian" else ""
         key = f"p32{tag}_o2_d{cfg['d']}_s{int(np.floor(np.log2(N)))}"
         with open(args.tuning) as f:
             for line in f:
@@ -409,7 +410,7 @@ def hubbard(args):
                                    "2nd order, T1/T2 per dot", "plan_propagate": plan_prop,
                        "plan_fwd_grad": sysm.last_plan(), "autotune": tuned,
                        "representation": ("real (basis of Hermitian operators)"
-                                          if args.block_basis == "hermitian"
+                                          if args.basis == "hermitian"
                                           else "complex (column stacking)")},
             "seconds_fwd_grad": t_fg, "seconds_set_system": t_setup, "F": float(F.item()),
             "context": "paper (Sec. IV): 1 min 15 s per propagator on an AMD EPYC 9634 CPU for this "
@@ -428,8 +429,8 @@ def main():
                     help="workspace budget of the large-system workloads in GiB (0 = 85 %% of free "
                          "device memory); beyond it the adjoint recomputes the forward")
     ap.add_argument("--no-latency", action="store_true", help="skip the single-pulse latency")
-    ap.add_argument("--block-basis", default="hermitian", choices=["hermitian", "column"],
-                    help="representation of the large-system workloads: the real basis of "
+    ap.add_argument("--basis", default="hermitian", choices=["hermitian", "column"],
+                    help="representation of the superoperators (FP32): the real basis of "
                          "Hermitian operators (default) or column stacking (complex)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune chunk length and inverse variant before the timed steps")
@@ -499,7 +500,8 @@ def main():
     B = args.batch
     cfg = synth.config1_batch(B)
     sysm = spin_chain_system(3, cfg["T1"], cfg["T2"], precision="f32", magnus_order=2,
-                             hold="foh", chunk_slices=args.chunk)
+                             hold="foh", chunk_slices=args.chunk, basis=args.basis)
+    real = args.basis == "hermitian"
     amps = torch.tensor(cfg["amps_batch"].reshape(B * 4096, 2), dtype=torch.float32,
                         device=dev).contiguous()
     n_slices = np.full(B, 4096, dtype=np.int32)
@@ -517,7 +519,7 @@ def main():
     if args.tuning and os.path.exists(args.tuning) and args.chunk == 0 and not args.autotune:
         # the autotuner's stored choice for this size (same key as the library's)
         sysm.load_tuning(args.tuning)
-        key = f"p32_o2_d8_s{int(np.floor(np.log2(B * 4096)))}"
+        key = f"p32{'h' if real else ''}_o2_d8_s{int(np.floor(np.log2(B * 4096)))}"
         with open(args.tuning) as f:
             for line in f:
                 rec = json.loads(line)
@@ -546,6 +548,10 @@ def main():
     value = B * args.steps / elapsed
     fwd_flops = flops_from_hist(hist, forward_flops_per_slice)
     bwd_flops = flops_from_hist(hist, backward_flops_per_slice)
+    if real:
+        # the same products on real matrices: 2 n^3 flops where a complex one counts 8 n^3
+        fwd_flops /= 4
+        bwd_flops /= 4
     stage_ms = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
     kernels = {
         "k_backward": (bwd_flops, stage_ms["backward"]),
@@ -558,10 +564,15 @@ def main():
                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
                 "traffic": read_traffic(dom, plan["total_slices"]),
-                "flops_per_launch": fl, "ms_per_launch": ms,
-                # the matrix cores execute each complex product in the 3M form
-                # (3 real products, 6 n^3 flops) against the 8 n^3 counted above
-                "frac_executed_3m": 0.75 * achieved / PEAK_FP32_MFMA_TFLOPS}
+                "flops_per_launch": fl, "ms_per_launch": ms}
+    if real:
+        # the products are real (one MFMA product each); in complex flops the
+        # column-stacking form of the same work would count four times as many
+        roofline["complex_equivalent_tflops"] = 4 * achieved
+    else:
+        # the matrix cores execute each complex product in the 3M form
+        # (3 real products, 6 n^3 flops) against the 8 n^3 counted above
+        roofline["frac_executed_3m"] = 0.75 * achieved / PEAK_FP32_MFMA_TFLOPS
     other = [k for k in kernels if k != dom][0]
     fl2, ms2 = kernels[other]
     total_flops = fwd_flops + bwd_flops
@@ -575,6 +586,8 @@ def main():
                                "FOH second-order Magnus, FP32 forward+adjoint gradient, "
                                f"batch of {B} pulses per step",
                    "batch_pulses": B, "n_slices": 4096, "superop_dim": 64,
+                   "representation": ("real (basis of Hermitian operators)" if real
+                                      else "complex (column stacking)"),
                    "chunk_slices": plan["chunk_slices"], "grid": plan["grid"],
                    "inverse": "auto (power series, MFMA Neumann or Gauss-Jordan per slice bound)"
                    if not tuned or tuned[1] == 0 else ("Gauss-Jordan" if tuned[1] == 1 else "Neumann"),

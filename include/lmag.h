@@ -122,11 +122,15 @@ typedef struct {
                                 /* one chunk per compute unit up to 64 slices per unit,*/
                                 /* above that about four chunks per workgroup within  */
                                 /* 64..256 slices (64 when the adjoint recomputes)    */
-  int block_basis;              /* superoperators larger than 64 x 64 and order 6:  */
-                                /* 0 = the real basis of Hermitian operators (every */
-                                /* matrix of the path is real there: one real MFMA  */
-                                /* product per complex one), 1 = column stacking    */
-                                /* (complex); results agree up to rounding          */
+  int basis;                    /* representation of the superoperators in single  */
+                                /* precision: 0 = the real basis of Hermitian       */
+                                /* operators (every matrix of the path is real      */
+                                /* there: one real MFMA product per complex one),   */
+                                /* 1 = column stacking (complex). Results agree up  */
+                                /* to rounding; the slice degrees and squarings can */
+                                /* differ (each is chosen from the 1-norm of the    */
+                                /* slice exponent in its own basis). Double         */
+                                /* precision always uses column stacking.           */
 } lmag_system_desc;
 
 /* Install (or replace) the system. Builds the superoperator basis on the
@@ -237,7 +241,7 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx *ctx, const lmag_batch *batch, 
  * three workgroups per CU; 7: as 6 with the grouping of 5; 8: as 0 with the A
  * tiles double-buffered in LDS by direct global-to-LDS loads (grouped as 5
  * where n <= 1024) -- at the automatic chunk length, half and twice it. In the
- * real basis of Hermitian operators (block_basis 0) the candidates are the real
+ * real basis of Hermitian operators (basis 0) the candidates are the real
  * product kernel (0) and, where n <= 1024, the same with the grouping of 5 (5).
  * 64 x 64 systems: the
  * persistent slice kernels, for every candidate chunk length (slices per work

@@ -39,7 +39,7 @@ class SystemDesc(ctypes.Structure):
                 ("n_ctrl", c_int), ("H_ctrl", c_double_p), ("n_jump", c_int),
                 ("L_jump", c_double_p), ("precision", c_int), ("magnus_order", c_int),
                 ("hold", c_int), ("workspace_bytes_max", c_size_t),
-                ("chunk_slices", c_int), ("block_basis", c_int)]
+                ("chunk_slices", c_int), ("basis", c_int)]
 
 
 class Batch(ctypes.Structure):

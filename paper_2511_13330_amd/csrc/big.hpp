@@ -104,4 +104,12 @@ hipError_t launch_from_real(const float* R, const int32_t* Xi, int d, int batch,
 hipError_t launch_rtile_flags(const double* basis, int nb, int n, uint8_t* flags, hipStream_t s);
 hipError_t launch_rcast(const double* in, float* out, size_t count, hipStream_t s);
 
+// The 64 x 64 path in the same basis (d <= 8, complex tiles with zero
+// imaginary parts). In place on count row-major 64 x 64 complex FP64 tiles:
+// S <- (Re(T S T^dag), 0), also written as complex FP32 into out32 if given.
+hipError_t launch_tile_to_real(double* tiles, int count, int d, float* out32, hipStream_t s);
+// In place on the n x n complex FP32 outputs (n = d^2) of the items' sources:
+// (R, .) <- T^dag R T.
+hipError_t launch_out_from_real(void* out, const Item* items, int n_items, int d, hipStream_t s);
+
 }  // namespace lmag

@@ -80,6 +80,8 @@ struct SliceArgs {
                             // with a sparse basis only its support positions, compacted)
   long long* clk;           // [32] per-phase cycle counters of workgroup 0, or null
   int recompute;            // backward recomputes each chunk's forward tiles
+  int real;                 // FP32 tiles in the basis of Hermitian operators: every tile
+                            // is real (zero imaginary parts), one MFMA product each
   void* rscratch;           // [grid][max_chunk][WS_TILES] tiles (recompute mode)
   int max_chunk;            // slices per chunk (scratch stride)
   PadeTable pade;
@@ -142,6 +144,8 @@ struct LogicalArgs {
   int f_by_src;
   double* st64;             // out [n_items][64][64] complex seed M
   float* st32;              // out, same in float (may be null)
+  int real;                 // basis of Hermitian operators: P holds T P, and the seed
+                            // keeps its real part (the gradient of a real map)
 };
 hipError_t launch_logical(const LogicalArgs& a, hipStream_t s);
 

@@ -473,6 +473,7 @@ __global__ void __launch_bounds__(WG) k_logical(LogicalArgs a) {
       m.re += q.re * p.re + q.im * p.im;
       m.im += q.im * p.re - q.re * p.im;
     }
+    if (a.real) m.im = 0.0;
     M64[e] = m;
     if (M32) M32[e] = cpx<float>{(float)m.re, (float)m.im};
   }

@@ -734,3 +734,91 @@ hipError_t launch_rcast(const double* in, float* out, size_t count, hipStream_t 
 }
 
 }  // namespace lmag
+
+namespace lmag {
+
+// The 64 x 64 slice kernels in the same basis (d <= 8): tiles stay complex in
+// memory, with zero imaginary parts, and each product takes one real MFMA.
+// Indices at or beyond d^2 (the zero padding of a tile) map to themselves.
+namespace {
+__device__ __forceinline__ TPair t_row_pad(int a, int d) {
+  return a < d * d ? t_row(a, d) : TPair{a, 1.0, 0.0, 0.0, 0.0};
+}
+}  // namespace
+
+// In place, one workgroup per 64 x 64 tile: R = Re(T S T^dag) of a complex
+// FP64 tile S, written back as (R, 0), and as complex FP32 into out32 when
+// given. The real part is the whole of T S T^dag for a Hermiticity-preserving
+// S; for any other S it is the projection that a real first-order change of R
+// sees (Re Tr(G^dag dS) = Tr(Re(T G T^dag)^T dR) for real dR), which is what a
+// gradient seed needs.
+__global__ void __launch_bounds__(256) k_tile_to_real(cpx<double>* tiles, int d, cpx<float>* out32) {
+  __shared__ cpx<double> S[64 * 64];
+  cpx<double>* X = tiles + (size_t)blockIdx.x * 4096;
+  for (int e = threadIdx.x; e < 4096; e += 256) S[e] = X[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int a = e / 64, b = e % 64;
+    const TPair ta = t_row_pad(a, d), tb = t_row_pad(b, d);
+    const int ia[2] = {a, ta.partner}, jb[2] = {b, tb.partner};
+    const double ar[2] = {ta.sr, ta.pr}, ai[2] = {ta.si, ta.pi};
+    const double br[2] = {tb.sr, tb.pr}, bi[2] = {tb.si, tb.pi};
+    double re = 0.0;
+    for (int x = 0; x < (a == ta.partner ? 1 : 2); ++x)
+      for (int y = 0; y < (b == tb.partner ? 1 : 2); ++y) {
+        const cpx<double> s = S[ia[x] * 64 + jb[y]];
+        const double ur = ar[x] * s.re - ai[x] * s.im, ui = ar[x] * s.im + ai[x] * s.re;
+        re += ur * br[y] + ui * bi[y];   // Re(T[a][i] S[i][j] conj(T[b][j]))
+      }
+    X[e] = cpx<double>{re, 0.0};
+    if (out32) out32[(size_t)blockIdx.x * 4096 + e] = cpx<float>{(float)re, 0.f};
+  }
+}
+
+hipError_t launch_tile_to_real(double* tiles, int count, int d, float* out32, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (d < 1 || d > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tile_to_real, dim3(count), dim3(256), 0, s, (cpx<double>*)tiles, d, (cpx<float>*)out32);
+  return hipGetLastError();
+}
+
+// In place, one workgroup per item: the n x n complex FP32 matrix (n = d^2)
+// at out + items[b].src n^2 holds a real matrix R in its real parts and
+// becomes T^dag R T, column stacking.
+__global__ void __launch_bounds__(256) k_out_from_real(cpx<float>* out, const Item* items, int d) {
+  __shared__ float R[64 * 64];
+  const int n = d * d;
+  cpx<float>* X = out + (size_t)items[blockIdx.x].src * n * n;
+  for (int e = threadIdx.x; e < n * n; e += 256) R[e] = X[e].re;
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, j = e % n;
+    // X[i][j] = sum over a in {i, p(i)}, c in {j, p(j)} of conj(T[a][i]) R[a][c] T[c][j]
+    const TPair ti = t_row(i, d), tj = t_row(j, d);
+    const int as[2] = {i, ti.partner}, cs[2] = {j, tj.partner};
+    double re = 0.0, im = 0.0;
+    for (int x = 0; x < (i == ti.partner ? 1 : 2); ++x) {
+      const int a = as[x];
+      const TPair ta = t_row(a, d);
+      const double tr = (a == i) ? ta.sr : ta.pr, tim = (a == i) ? ta.si : ta.pi;   // T[a][i]
+      for (int y = 0; y < (j == tj.partner ? 1 : 2); ++y) {
+        const int c = cs[y];
+        const TPair tc = t_row(c, d);
+        const double ur = (c == j) ? tc.sr : tc.pr, ui = (c == j) ? tc.si : tc.pi;   // T[c][j]
+        const double r = (double)R[a * n + c];
+        re += r * (tr * ur + tim * ui);
+        im += r * (tr * ui - tim * ur);
+      }
+    }
+    X[e] = cpx<float>{(float)re, (float)im};
+  }
+}
+
+hipError_t launch_out_from_real(void* out, const Item* items, int n_items, int d, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (d < 1 || d > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_out_from_real, dim3(n_items), dim3(256), 0, s, (cpx<float>*)out, items, d);
+  return hipGetLastError();
+}
+
+}  // namespace lmag

@@ -44,15 +44,15 @@ __device__ __forceinline__ cpx<T>* slot(Shared<T>& sh, cpx<T>* gs) {
 template <typename T, bool TRANS>
 __device__ __forceinline__ void put(const RT<T>& X, cpx<T>* S) { rt_store<T, TRANS>(X, S, PITCH); }
 
-template <typename T, bool PIPE = true>
+template <typename T, bool PIPE = true, bool RE = false>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) {
-  gemm_acc<T, false, PITCH, PIPE>(acc, A, B);
+  gemm_acc<T, false, PITCH, PIPE, NoHook, RE>(acc, A, B);
 }
 
 // mm with a hook that moves a share of a global tile at each k-step
-template <typename T, bool PIPE = true, typename H>
+template <typename T, bool PIPE = true, bool RE = false, typename H>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B, const H& hook) {
-  gemm_acc<T, false, PITCH, PIPE, H>(acc, A, B, hook);
+  gemm_acc<T, false, PITCH, PIPE, H, RE>(acc, A, B, hook);
 }
 
 // Element (row(q, r), col) of this thread in a row-major 64 x 64 tile at M
@@ -495,7 +495,7 @@ struct CodeWindow {
 // made that product spill.
 // A holds Omega_n / 2^s (loaded by the caller, which prefetches it during the
 // previous slice's chain product).
-template <typename T, bool ST>
+template <typename T, bool ST, bool RE = false>
 __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& sh, cpx<T>* gs,
                           const SliceArgs& a, uint32_t code, cpx<T>* ws, Clock& ck) {
   constexpr bool hk = sizeof(T) == 4;   // stores inside products
@@ -516,10 +516,10 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   rt_zero(A2);
   // unpipelined: measured faster, and it leaves the kernel without spills
   if constexpr (st && hk) {
-    mm<T, false>(A2, slot<T, 0>(sh, gs), A, TileStore<T>{Pl, ws + WS_PLOC * TILE});
+    mm<T, false, RE>(A2, slot<T, 0>(sh, gs), A, TileStore<T>{Pl, ws + WS_PLOC * TILE});
   } else {
     if constexpr (st) rt_store<T, false>(Pl, ws + WS_PLOC * TILE, 64);
-    mm<T, false>(A2, slot<T, 0>(sh, gs), A);
+    mm<T, false, RE>(A2, slot<T, 0>(sh, gs), A);
   }
   ck.mark(1);
   // single precision stores A^2 during the next product
@@ -542,9 +542,9 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     rt_add_diag(Bk, (T)r[2]);
     ck.mark(3);
     if constexpr (st)
-      mm<T, false>(R, slot<T, 1>(sh, gs), Bk, TileStore<T>{A2, ws + WS_A2 * TILE});
+      mm<T, false, RE>(R, slot<T, 1>(sh, gs), Bk, TileStore<T>{A2, ws + WS_A2 * TILE});
     else
-      mm<T, false>(R, slot<T, 1>(sh, gs), Bk);
+      mm<T, false, RE>(R, slot<T, 1>(sh, gs), Bk);
     if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
   } else {
   RT<T> V;   // the even part minus I
@@ -563,22 +563,22 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     __syncthreads();
     RT<T> A4;
     rt_zero(A4);
-    mm(A4, slot<T, 1>(sh, gs), A2);
+    mm<T, true, RE>(A4, slot<T, 1>(sh, gs), A2);
     rt_axpy(W, (T)b[5], A4);
     rt_axpy(V, (T)b[4], A4);
     if (m == 7) {
       RT<T> A6;
       rt_zero(A6);
-      mm(A6, slot<T, 1>(sh, gs), A4);
+      mm<T, true, RE>(A6, slot<T, 1>(sh, gs), A4);
       rt_axpy(W, (T)b[7], A6);
       rt_axpy(V, (T)b[6], A6);
     }
   }
   rt_zero(U);
   if constexpr (st && hk)
-    mm(U, slot<T, 0>(sh, gs), W, TileStore<T>{A2, ws + WS_A2 * TILE});
+    mm<T, true, RE>(U, slot<T, 0>(sh, gs), W, TileStore<T>{A2, ws + WS_A2 * TILE});
   else
-    mm(U, slot<T, 0>(sh, gs), W);
+    mm<T, true, RE>(U, slot<T, 0>(sh, gs), W);
   }
   // P = I + X_P with X_P = (V - I) + U (in U); Q = I + E_Q with E_Q = (V - I) - U (in V)
 #pragma unroll
@@ -597,13 +597,13 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     __syncthreads();
     RT<T> A4;
     rt_zero(A4);
-    mm(A4, slot<T, 1>(sh, gs), A2);
+    mm<T, true, RE>(A4, slot<T, 1>(sh, gs), A2);
     RT<T> odd;
     rt_poly1(odd, A2, (T)c[3], (T)c[1]);
     rt_axpy(odd, (T)c[5], A4);
     rt_poly1(V, A2, (T)c[2], T(0));
     rt_axpy(V, (T)c[4], A4);
-    mm(V, slot<T, 0>(sh, gs), odd);   // X_Q = even - I + A odd
+    mm<T, true, RE>(V, slot<T, 0>(sh, gs), odd);   // X_Q = even - I + A odd
   } else if (K > 0 && K < 16) {
     // binary Neumann product on MFMA: Q^{-1} = (I + F)(I + F^2)(I + F^4)...,
     // F = I - Q = -E_Q; with X = Q^{-1} - I each level is X += F2 + F2 X
@@ -617,13 +617,13 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
       __syncthreads();
       RT<T> F2;
       rt_zero(F2);
-      mm(F2, slot<T, 2>(sh, gs), F);
+      mm<T, true, RE>(F2, slot<T, 2>(sh, gs), F);
       __syncthreads();
       put<T, false>(F2, slot<T, 2>(sh, gs));
       __syncthreads();
       RT<T> T1;
       rt_copy(T1, F2);
-      mm(T1, slot<T, 2>(sh, gs), V);
+      mm<T, true, RE>(T1, slot<T, 2>(sh, gs), V);
       rt_axpy(V, T(1), T1);
       rt_copy(F, F2);
     }
@@ -642,9 +642,9 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   rt_copy(R, U);
   rt_axpy(R, T(1), V);
   if constexpr (st && hk)
-    mm<T, false>(R, slot<T, 1>(sh, gs), U, TileStore<T>{V, ws + WS_QINV * TILE});
+    mm<T, false, RE>(R, slot<T, 1>(sh, gs), U, TileStore<T>{V, ws + WS_QINV * TILE});
   else
-    mm(R, slot<T, 1>(sh, gs), U);
+    mm<T, true, RE>(R, slot<T, 1>(sh, gs), U);
   if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
   }
   ck.mark(4);
@@ -656,7 +656,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     RT<T> R2;
     rt_copy(R2, R);
     rt_scale(R2, T(2));
-    mm(R2, slot<T, 2>(sh, gs), R);
+    mm<T, true, RE>(R2, slot<T, 2>(sh, gs), R);
     rt_copy(R, R2);
   }
   ck.mark(5);
@@ -709,19 +709,19 @@ __device__ __forceinline__ void rp_add(RunProd<T>& P, const RT<T>& X) {
 }
 
 // P <- P + D P (D in LDS or global scratch at Dm; the product uses hi)
-template <typename T>
+template <typename T, bool RE = false>
 __device__ __forceinline__ void chain_step(RunProd<T>& P, const cpx<T>* Dm) {
   RT<T> Pn;
   rt_zero(Pn);
-  mm<T, false>(Pn, Dm, P.hi);
+  mm<T, false, RE>(Pn, Dm, P.hi);
   rp_add(P, Pn);
 }
 
-template <typename T, typename H>
+template <typename T, bool RE = false, typename H>
 __device__ __forceinline__ void chain_step(RunProd<T>& P, const cpx<T>* Dm, const H& hook) {
   RT<T> Pn;
   rt_zero(Pn);
-  mm<T, false>(Pn, Dm, P.hi, hook);
+  mm<T, false, RE>(Pn, Dm, P.hi, hook);
   rp_add(P, Pn);
 }
 
@@ -759,7 +759,7 @@ __device__ __forceinline__ int grab(Shared<T>& sh, int* counter) {
 // with the stores behind a run-time test, the compiler's count of memory
 // operations in flight is that of the path without them, and the first use of
 // the prefetched Omega tile would also wait for every store.
-template <typename T, bool ST>
+template <typename T, bool ST, bool RE = false>
 __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
   __shared__ Shared<T> sh;
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
@@ -781,13 +781,13 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
         const int n = ch.first + k;
         cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
         RT<T> D;
-        fwd_slice<T, ST>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
+        fwd_slice<T, ST, RE>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
         put<T, false>(D, slot<T, 3>(sh, gs));   // slot 3's last reader is the previous chain
         __syncthreads();
         // the next slice's Omega tile, spread over the chain product (the chunk's
         // last slice reloads its own, so that the loads are unconditional)
-        chain_step<T>(P, slot<T, 3>(sh, gs),
-                      TileLoad<T, false>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
+        chain_step<T, RE>(P, slot<T, 3>(sh, gs),
+                          TileLoad<T, false>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
         ck.mark(6);
       }
     }
@@ -807,7 +807,7 @@ template <typename T> constexpr bool bwd_carry = sizeof(T) == 4;
 // chunk's first slice n itself again: unconditional loads keep the compiler's
 // count of operations in flight exact), nx being slice nn's workspace.
 // kpack: this thread's compact-K_n^T word (sparse basis), see SparseBasis.
-template <typename T>
+template <typename T, bool RE = false>
 __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* gs,
                           const SliceArgs& a, int n, uint32_t code, const cpx<T>* ws, int nn,
                           const cpx<T>* nx, Clock& ck, uint32_t kpack) {
@@ -834,10 +834,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   rt_zero(E);
   if constexpr (bwd_carry<T>) {
     // (this product and the D product run unpipelined: measured faster here)
-    mm<T, false>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true>{R, ws + WS_S * TILE});
+    mm<T, false, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true>{R, ws + WS_S * TILE});
   } else {
     rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
-    mm(E, slot<T, 0>(sh, gs), Pl);
+    mm<T, true, RE>(E, slot<T, 0>(sh, gs), Pl);
   }
   if (s) rt_scale(E, sc);
   ck.mark(1);
@@ -849,11 +849,11 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   ck.mark(2);
   RT<T> L2;
   rt_zero(L2);
-  mm(L2, slot<T, 0>(sh, gs), E);
+  mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E);
   if constexpr (bwd_carry<T>)
-    mm(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
+    mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
   else
-    mm(L2, slot<T, 1>(sh, gs), A);
+    mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A);
   ck.mark(3);
   RT<T> K;
   if (ser2) {
@@ -880,9 +880,9 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_axpy(Lq, (T)r[4], L2);
     ck.mark(5);
     // both unpipelined: measured faster here
-    mm<T, false>(K, slot<T, 2>(sh, gs), Bq);
+    mm<T, false, RE>(K, slot<T, 2>(sh, gs), Bq);
     ck.mark(6);
-    mm<T, false>(K, slot<T, 3>(sh, gs), Lq);
+    mm<T, false, RE>(K, slot<T, 3>(sh, gs), Lq);
   } else {
   RT<T> W, LW, LV;
   const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
@@ -900,22 +900,22 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
       __syncthreads();
       RT<T> A4, L4;
       rt_zero(A4);
-      mm(A4, slot<T, 2>(sh, gs), A2);
+      mm<T, true, RE>(A4, slot<T, 2>(sh, gs), A2);
       rt_zero(L4);
-      mm(L4, slot<T, 2>(sh, gs), L2);
-      mm(L4, slot<T, 3>(sh, gs), A2);
+      mm<T, true, RE>(L4, slot<T, 2>(sh, gs), L2);
+      mm<T, true, RE>(L4, slot<T, 3>(sh, gs), A2);
       rt_axpy(W, (T)b[5], A4);
       rt_axpy(LW, (T)b[5], L4);
       rt_axpy(LV, (T)b[4], L4);
       if (m == 7) {
         RT<T> T6;
         rt_zero(T6);
-        mm(T6, slot<T, 3>(sh, gs), A4);   // L2 A4
-        mm(T6, slot<T, 2>(sh, gs), L4);   // A2 L4
+        mm<T, true, RE>(T6, slot<T, 3>(sh, gs), A4);   // L2 A4
+        mm<T, true, RE>(T6, slot<T, 2>(sh, gs), L4);   // A2 L4
         rt_axpy(LW, (T)b[7], T6);
         rt_axpy(LV, (T)b[6], T6);
         rt_zero(T6);
-        mm(T6, slot<T, 2>(sh, gs), A4);   // A6
+        mm<T, true, RE>(T6, slot<T, 2>(sh, gs), A4);   // A6
         rt_axpy(W, (T)b[7], T6);
       }
     }
@@ -928,8 +928,8 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_scale(LU, (T)b[1]);
   } else {
     rt_zero(LU);
-    mm(LU, slot<T, 0>(sh, gs), LW);
-    mm(LU, slot<T, 1>(sh, gs), W);
+    mm<T, true, RE>(LU, slot<T, 0>(sh, gs), LW);
+    mm<T, true, RE>(LU, slot<T, 1>(sh, gs), W);
   }
   ck.mark(5);
   // L_Q = L_V - L_U (into LW), L_P = L_V + L_U (into LU)
@@ -952,13 +952,13 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   {
     RT<T> Tm;
     rt_zero(Tm);
-    mm(Tm, slot<T, 1>(sh, gs), R);
+    mm<T, true, RE>(Tm, slot<T, 1>(sh, gs), R);
 #pragma unroll
     for (int q = 0; q < 4; ++q) { LU.re[q] -= Tm.re[q]; LU.im[q] -= Tm.im[q]; }
   }
   // L = Q^{-1} X = X + (Q^{-1} - I) X
   rt_copy(K, LU);
-  mm(K, slot<T, 2>(sh, gs), LU);
+  mm<T, true, RE>(K, slot<T, 2>(sh, gs), LU);
   }
   for (int k = 0; k < s; ++k) {
     __syncthreads();
@@ -969,11 +969,11 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     RT<T> Kn, Rn;
     rt_copy(Kn, K);
     rt_scale(Kn, T(2));
-    mm(Kn, slot<T, 0>(sh, gs), K);
-    mm(Kn, slot<T, 1>(sh, gs), R);
+    mm<T, true, RE>(Kn, slot<T, 0>(sh, gs), K);
+    mm<T, true, RE>(Kn, slot<T, 1>(sh, gs), R);
     rt_copy(Rn, R);
     rt_scale(Rn, T(2));
-    mm(Rn, slot<T, 0>(sh, gs), R);
+    mm<T, true, RE>(Rn, slot<T, 0>(sh, gs), R);
     rt_copy(K, Kn);
     rt_copy(R, Rn);
   }
@@ -1004,13 +1004,13 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     const TileLoad<T, true, 0> lp{Pl, nx + WS_PLOC * TILE};
     const TileLoad<T, true, 8> la{A, tile_at<T>(a.omega, (size_t)nn)};
     if (a.sp.n_sup > 0)
-      mm(Zn, slot<T, 0>(sh, gs), Z,
+      mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z,
          Hooks3<SupportStore<T>, TileLoad<T, true, 0>, TileLoad<T, true, 8>>{{K, kt, kpack}, lp, la});
     else
-      mm(Zn, slot<T, 0>(sh, gs), Z,
+      mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z,
          Hooks3<TileStore<T>, TileLoad<T, true, 0>, TileLoad<T, true, 8>>{{K, kt}, lp, la});
   } else {
-    mm(Zn, slot<T, 0>(sh, gs), Z);
+    mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z);
   }
   rt_copy(Z, Zn);
   ck.mark(9);
@@ -1019,7 +1019,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
 // RC: recompute mode (the chunk's forward is re-run into per-workgroup scratch);
 // a separate instantiation so that the stored-workspace kernel carries none of
 // its register pressure.
-template <typename T, bool RC>
+template <typename T, bool RC, bool RE = false>
 __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
   __shared__ Shared<T> sh;
   cpx<T>* gs = a.gscratch ? reinterpret_cast<cpx<T>*>(a.gscratch) + (size_t)blockIdx.x * 2 * SLOT
@@ -1045,13 +1045,13 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
         for (int k = k0; k < k1; ++k) {
           cpx<T>* ws = rs + (size_t)k * WS_TILES * TILE;
           RT<T> D;
-          fwd_slice<T, true>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
+          fwd_slice<T, true, RE>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
           if (k + 1 < ch.count) {
             rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
             __syncthreads();
             put<T, false>(D, slot<T, 3>(sh, gs));
             __syncthreads();
-            chain_step<T>(P, slot<T, 3>(sh, gs));
+            chain_step<T, RE>(P, slot<T, 3>(sh, gs));
           }
         }
       }
@@ -1080,7 +1080,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       CodeWindow cw;
       cw.load(a, ch.first + k0, k1 - k0);
       for (int k = k1 - 1; k >= k0; --k)
-        bwd_slice<T>(Z, Pl, A, sh, gs, a, ch.first + k, cw.at(k - k0), ws_of(k),
+        bwd_slice<T, RE>(Z, Pl, A, sh, gs, a, ch.first + k, cw.at(k - k0), ws_of(k),
                      ch.first + (k > 0 ? k - 1 : 0), ws_of(k > 0 ? k - 1 : 0), ck, kpack);
     }
   }
@@ -1089,7 +1089,10 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
 
 hipError_t launch_slice_forward(int prec, const SliceArgs& a, int grid, hipStream_t s) {
   const bool st = a.store && a.ws_tiles;
-  if (prec == 32) {
+  if (prec == 32 && a.real) {
+    if (st) hipLaunchKernelGGL((k_forward<float, true, true>), dim3(grid), dim3(WG), 0, s, a);
+    else hipLaunchKernelGGL((k_forward<float, false, true>), dim3(grid), dim3(WG), 0, s, a);
+  } else if (prec == 32) {
     if (st) hipLaunchKernelGGL((k_forward<float, true>), dim3(grid), dim3(WG), 0, s, a);
     else hipLaunchKernelGGL((k_forward<float, false>), dim3(grid), dim3(WG), 0, s, a);
   } else {
@@ -1142,7 +1145,10 @@ hipError_t launch_traces(int prec, const SliceArgs& a, int n_total, hipStream_t 
 }
 
 hipError_t launch_slice_backward(int prec, const SliceArgs& a, int grid, hipStream_t s) {
-  if (prec == 32) {
+  if (prec == 32 && a.real) {
+    if (a.recompute) hipLaunchKernelGGL((k_backward<float, true, true>), dim3(grid), dim3(WG), 0, s, a);
+    else hipLaunchKernelGGL((k_backward<float, false, true>), dim3(grid), dim3(WG), 0, s, a);
+  } else if (prec == 32) {
     if (a.recompute) hipLaunchKernelGGL((k_backward<float, true>), dim3(grid), dim3(WG), 0, s, a);
     else hipLaunchKernelGGL((k_backward<float, false>), dim3(grid), dim3(WG), 0, s, a);
   } else {

@@ -483,6 +483,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
   sa.recompute = grad && p.recompute; sa.rscratch = sa.recompute ? at(L.rscratch) : nullptr;
   sa.max_chunk = p.chunk_size;
   sa.sp = c->sp;
+  sa.real = c->real ? 1 : 0;
   if (sa.recompute) { sa.store = 0; sa.ws_tiles = nullptr; }
   { StageTimer t(c, 1, s); HIPCHK(launch_omega(c->prec, sa, p.total_slices, s), "omega"); }
   { StageTimer t(c, 2, s); HIPCHK(launch_slice_forward(c->prec, sa, grid, s), "forward"); }
@@ -511,6 +512,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     ea.prec = c->prec; ea.items = items; ea.n_items = (int)p.items.size(); ea.pre = pre_cur;
     ea.out = S_out; ea.n = c->n;
     HIPCHK(launch_extract(ea, s), "extract");
+    if (c->real) HIPCHK(launch_out_from_real(S_out, items, ea.n_items, c->d, s), "extract (column stacking)");
   }
   if (!fidelity) return LMAG_OK;
 
@@ -523,6 +525,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     la.kind = c->score_kind; la.L = c->score_L; la.P = c->logP_dev; la.T = (const double*)U_target;
     la.score = F_items; la.f_by_src = grouped ? 0 : 1;
     la.st64 = (double*)at(L.st64); la.st32 = c->prec == 32 ? (float*)at(L.st) : nullptr;
+    la.real = c->real ? 1 : 0;
     { StageTimer t(c, 4, s); HIPCHK(launch_logical(la, s), "logical score"); }
   } else {
     TargetArgs ta{};
@@ -530,6 +533,7 @@ lmag_status run(lmag_ctx* c, const lmag_batch* b, const Plan& p, const Layout& L
     ta.st64 = (double*)at(L.st64);
     ta.st32 = c->prec == 32 ? (float*)at(L.st) : nullptr;
     HIPCHK(launch_targets(ta, s), "targets");
+    if (c->real) HIPCHK(launch_tile_to_real(ta.st64, n_targets, c->d, ta.st32, s), "targets (real)");
   }
   const void* st_tiles = c->prec == 32 ? at(L.st) : at(L.st64);
   EnvArgs ev{};
@@ -1691,9 +1695,10 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       return c->fail(LMAG_E_INVALID, "magnus_order must be 1, 2 or 6");
     if (s->hold != LMAG_ZOH && s->hold != LMAG_FOH) return c->fail(LMAG_E_INVALID, "hold must be ZOH or FOH");
     if (s->chunk_slices < 0) return c->fail(LMAG_E_INVALID, "chunk_slices < 0");
-    if (s->block_basis != 0 && s->block_basis != 1)
-      return c->fail(LMAG_E_INVALID, "block_basis must be 0 (Hermitian-operator basis) or 1 (column stacking)");
-    const bool real = big && s->block_basis == 0;
+    if (s->basis != 0 && s->basis != 1)
+      return c->fail(LMAG_E_INVALID, "basis must be 0 (Hermitian-operator basis) or 1 (column stacking)");
+    const bool real = s->basis == 0 && s->precision == 32;
+    const bool rbig = real && big;   // real FP32 matrices; the 64 x 64 tiles stay complex
     const size_t dd2 = (size_t)d * d * 2;
     if ((s->n_static && !finite_array(s->H_static, s->n_static * dd2)) ||
         (s->n_ctrl && !finite_array(s->H_ctrl, s->n_ctrl * dd2)) ||
@@ -1726,7 +1731,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
     double* tmp = nullptr;
     const size_t nops = (size_t)(ns + nc + s->n_jump) * dd2;
     if (hipMalloc((void**)&c->basis64, nb * tb) != hipSuccess ||
-        hipMalloc(&c->basis32, nb * nn * (real ? 4 : 8)) != hipSuccess ||
+        hipMalloc(&c->basis32, nb * nn * (rbig ? 4 : 8)) != hipSuccess ||
         hipMalloc((void**)&ops, std::max<size_t>(8, nops * 8)) != hipSuccess ||
         hipMalloc((void**)&ldl, std::max<size_t>(8, (size_t)s->n_jump * dd2 * 8)) != hipSuccess ||
         (big && hipMalloc((void**)&tmp, tb) != hipSuccess)) {
@@ -1773,7 +1778,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       for (int p = 0; p < nc; ++p)
         for (int q = p + 1; q < nc; ++q) HIPCHK(comm(tile(p), tile(q), tile(j++)), "comm");
     }
-    if (real) {
+    if (rbig) {
       // the real form R_j = T B_j T^dag in the basis of Hermitian operators,
       // kept in FP64 for the tile lists and cast to the FP32 copy
       double* r64 = nullptr;
@@ -1790,6 +1795,9 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       (void)hipFree(c->basis64);
       c->basis64 = r64;
     } else {
+      // 64 x 64 tiles in the real basis: (R_j, 0) in place, in FP64 for the
+      // sparse-support analysis below
+      if (real) HIPCHK(launch_tile_to_real(c->basis64, nb, d, nullptr, st), "basis (real)");
       HIPCHK(launch_cast(c->basis64, (float*)c->basis32, (size_t)nb * nn * 2, st), "cast");
       HIPCHK(hipDeviceSynchronize(), "set_system sync");
     }
@@ -1801,7 +1809,7 @@ lmag_status lmag_set_system(lmag_ctx* c, const lmag_system_desc* s) {
       uint8_t* fl = nullptr;
       std::vector<uint8_t> flh((size_t)nb * nt);
       if (hipMalloc((void**)&fl, flh.size()) == hipSuccess) {
-        if ((real ? launch_rtile_flags(c->basis64, nb, d * d, fl, st)
+        if ((rbig ? launch_rtile_flags(c->basis64, nb, d * d, fl, st)
                   : launch_tile_flags(c->basis64, nb, d * d, fl, st)) == hipSuccess &&
             hipMemcpy(flh.data(), fl, flh.size(), hipMemcpyDeviceToHost) == hipSuccess) {
           std::vector<int32_t> lists(nt + 1, 0);
@@ -2216,6 +2224,27 @@ lmag_status lmag_logical_score_and_grad(lmag_ctx* c, const lmag_batch* b, int ki
         h[((size_t)i * L + k) * 2] = P[((size_t)k * c->n + i) * 2];
         h[((size_t)i * L + k) * 2 + 1] = P[((size_t)k * c->n + i) * 2 + 1];
       }
+    if (c->real) {
+      // in the basis of Hermitian operators the score reads T P: with
+      // U = T^dag R T, P^dag U P = (T P)^dag R (T P). Row a = k + l d of T
+      // has T[a][a] = 1 (k = l), 1/sqrt 2 (k < l) or i/sqrt 2 (k > l), and
+      // T[a][l + k d] = 1/sqrt 2 (k < l) or -i/sqrt 2 (k > l).
+      const double r = std::sqrt(0.5);
+      std::vector<double> t(h.size(), 0.0);
+      const int d = c->d;
+      for (int a = 0; a < c->n; ++a) {
+        const int kk = a % d, ll = a / d, q = ll + kk * d;
+        for (int k = 0; k < L; ++k) {
+          const double* x = &h[((size_t)a * L + k) * 2];
+          const double* y = &h[((size_t)q * L + k) * 2];
+          double* o = &t[((size_t)a * L + k) * 2];
+          if (kk == ll) { o[0] = x[0]; o[1] = x[1]; }
+          else if (kk < ll) { o[0] = r * (x[0] + y[0]); o[1] = r * (x[1] + y[1]); }
+          else { o[0] = r * (y[1] - x[1]); o[1] = r * (x[0] - y[0]); }   // i r x - i r y
+        }
+      }
+      h.swap(t);
+    }
     HIPCHK(hipMemcpyAsync(c->logP_dev, h.data(), h.size() * 8, hipMemcpyHostToDevice, s), "P upload");
     HIPCHK(hipStreamSynchronize(s), "P upload");
     c->score_kind = kind;

@@ -32,7 +32,7 @@ class System:
 
     def __init__(self, H_static, H_ctrl, L_jump, precision="f32", magnus_order=2,
                  hold="foh", device=0, workspace_bytes_max=0, chunk_slices=0,
-                 block_basis="hermitian"):
+                 basis="hermitian"):
         self.d = int(np.asarray(H_ctrl if len(H_ctrl) else H_static).shape[-1])
         self.n = self.d * self.d
         self.precision = precision
@@ -48,12 +48,12 @@ class System:
         hs, phs = _ops(H_static, self.d) if self.n_static else (None, None)
         hc, phc = _ops(H_ctrl, self.d) if self.n_ctrl else (None, None)
         lj, plj = _ops(L_jump, self.d) if len(L_jump) else (None, None)
-        if block_basis not in ("hermitian", "column"):
-            raise ValueError("block_basis must be 'hermitian' (real) or 'column' (complex)")
+        if basis not in ("hermitian", "column"):
+            raise ValueError("basis must be 'hermitian' (real) or 'column' (complex)")
         desc = SystemDesc(self.d, self.n_static, phs, self.n_ctrl, phc, len(L_jump), plj,
                           _PREC[precision], magnus_order, _HOLD[hold],
                           workspace_bytes_max, chunk_slices,
-                          0 if block_basis == "hermitian" else 1)
+                          0 if basis == "hermitian" else 1)
         check(L.lmag_set_system(self._ctx, ctypes.byref(desc)), self._ctx)
 
     def close(self):

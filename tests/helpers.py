@@ -10,14 +10,14 @@ def oracle_system(cfg, dissipative=True, eps=None, dB=None):
 
 
 def lib_system(cfg, precision=None, order=None, hold=None, dissipative=True, chunk=0,
-               workspace_bytes_max=0, block_basis="hermitian"):
+               workspace_bytes_max=0, basis="hermitian"):
     from paper_2511_13330_amd import spin_chain_system
     T1, T2 = (cfg["T1"], cfg["T2"]) if dissipative else (np.inf, np.inf)
     return spin_chain_system(cfg["n_spins"], T1, T2,
                              precision=precision or cfg["precision"],
                              magnus_order=order or cfg["order"], hold=hold or cfg["hold"],
                              chunk_slices=chunk, workspace_bytes_max=workspace_bytes_max,
-                             block_basis=block_basis)
+                             basis=basis)
 
 
 def rounded(amps, precision):

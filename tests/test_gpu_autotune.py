@@ -36,17 +36,18 @@ def test_autotune_choice_is_used_and_keeps_parity(tmp_path, monkeypatch):
     assert fresh.last_plan()["chunk_slices"] == C
 
 
+@pytest.mark.parametrize("basis", ["hermitian", "column"])
 @pytest.mark.parametrize("inverse", [0, 1, 2])
-def test_each_inverse_variant_keeps_parity(tmp_path, inverse):
+def test_each_inverse_variant_keeps_parity(tmp_path, inverse, basis):
     # 0: power series / Neumann / Gauss-Jordan chosen per slice; 1: Gauss-Jordan;
     # 2: Neumann or Gauss-Jordan. Forced through a tuning line for this size.
     cfg = synth.small_case(62, n_slices=48)
     amps = rounded(cfg["amps"], "f32")
     total = 48
-    key = f"p32_o2_d8_s{int(np.floor(np.log2(total)))}"
+    key = f"p32{'h' if basis == 'hermitian' else ''}_o2_d8_s{int(np.floor(np.log2(total)))}"
     f = tmp_path / "t.jsonl"
     f.write_text(json.dumps({"key": key, "chunk": 7, "inverse": inverse, "ms": 1.0}) + "\n")
-    sysm = lib_system(cfg)
+    sysm = lib_system(cfg, basis=basis)
     sysm.load_tuning(f)
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     F, g = sysm.fidelity_and_grad(a, [total], cfg["dt"], cfg["U_target"],

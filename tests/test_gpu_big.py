@@ -17,9 +17,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def run(cfg, amps, chunk=0, want_grad=True, dissipative=True, block_basis="hermitian"):
+def run(cfg, amps, chunk=0, want_grad=True, dissipative=True, basis="hermitian"):
     sysm = lib_system(cfg, "f32", cfg["order"], cfg["hold"], chunk=chunk, dissipative=dissipative,
-                      block_basis=block_basis)
+                      basis=basis)
     a = torch.tensor(amps, dtype=torch.float32, device="cuda")
     b = np.asarray(cfg["B"])[None, :]
     N = len(amps)
@@ -34,7 +34,7 @@ def run(cfg, amps, chunk=0, want_grad=True, dissipative=True, block_basis="hermi
 def test_four_spin_small_matches_oracle(chunk, basis):
     cfg = synth.small_case(71, n_spins=4, n_slices=12, dt=2.5e-4)
     amps = rounded(cfg["amps"], "f32")
-    sysm, U, F, g = run(cfg, amps, chunk, block_basis=basis)
+    sysm, U, F, g = run(cfg, amps, chunk, basis=basis)
     osys = oracle_system(cfg)
     U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
     assert rel(U, U_ref) < 2e-5
@@ -48,7 +48,7 @@ def test_four_spin_with_squarings(basis):
     # 1 ns slices of large amplitudes push ||Omega||_1 above theta_3: s > 0
     cfg = synth.small_case(72, n_spins=4, n_slices=6, dt=4e-3)
     amps = rounded(cfg["amps"], "f32")
-    sysm, U, F, g = run(cfg, amps, 2, block_basis=basis)
+    sysm, U, F, g = run(cfg, amps, 2, basis=basis)
     hist = sysm.selection_histogram()
     assert hist[1, 1:].sum() > 0   # Pade-3 with squarings
     osys = oracle_system(cfg)
@@ -272,7 +272,7 @@ def test_four_spin_product_kernels_match_oracle(basis, variant, tmp_path):
     slices."""
     cfg = synth.small_case(75, n_spins=4, n_slices=14, dt=2e-3)
     amps = rounded(cfg["amps"], "f32")
-    sysm = lib_system(cfg, "f32", 2, "foh", block_basis=basis)
+    sysm = lib_system(cfg, "f32", 2, "foh", basis=basis)
     path = tmp_path / "tune.jsonl"
     _tuning_line(path, 16, 14, 4, variant, basis)
     sysm.load_tuning(str(path))
@@ -368,7 +368,7 @@ def test_hermitian_and_column_bases_agree():
     amps = rounded(cfg["amps"], "f32")
     out = {}
     for basis in ("hermitian", "column"):
-        sysm, U, F, g = run(cfg, amps, 8, block_basis=basis)
+        sysm, U, F, g = run(cfg, amps, 8, basis=basis)
         out[basis] = (U, F, g, sysm.last_plan()["workspace_bytes"])
     (Uh, Fh, gh, wh), (Uc, Fc, gc, wc) = out["hermitian"], out["column"]
     assert rel(Uh, Uc) < 2e-5

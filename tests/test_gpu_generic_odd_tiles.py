@@ -76,7 +76,7 @@ def reference():
 def test_nine_tile_rows_every_product_kernel(reference, basis, variant, tmp_path):
     from paper_2511_13330_amd.system import System
     (Hs, Hc, Ls, coef, amps, dt, UT), U_ref, F_ref, g_ref = reference
-    sysm = System(Hs, Hc, Ls, precision="f32", magnus_order=2, hold="foh", block_basis=basis)
+    sysm = System(Hs, Hc, Ls, precision="f32", magnus_order=2, hold="foh", basis=basis)
     N = len(amps)
     with open(tmp_path / "tune.jsonl", "w") as f:
         f.write('{"key": "p32%s_o2_d%d_s%d", "chunk": 3, "variant": %d, "ms": 0.0}\n'

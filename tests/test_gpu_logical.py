@@ -30,12 +30,13 @@ def lib_case(kind, prec, cfg, amps, V, sysm):
 
 
 @pytest.mark.parametrize("kind", ["projected", "linear"])
-@pytest.mark.parametrize("prec,chunk", [("f64", 7), ("f32", 7), ("f32", 0)])
-def test_logical_score_small(kind, prec, chunk):
+@pytest.mark.parametrize("prec,chunk,basis", [("f64", 7, "column"), ("f32", 7, "hermitian"),
+                                              ("f32", 7, "column"), ("f32", 0, "hermitian")])
+def test_logical_score_small(kind, prec, chunk, basis):
     cfg = synth.small_case(41, n_slices=40, dt=2.5e-4)
     amps = rounded(cfg["amps"], prec)
     V = synth.haar_unitary(np.random.default_rng(42), 2)
-    sysm = lib_system(cfg, prec, 2, "foh", chunk=chunk)
+    sysm = lib_system(cfg, prec, 2, "foh", chunk=chunk, basis=basis)
     s, g = lib_case(kind, prec, cfg, amps, V, sysm)
     Pf, Tf = CASES[kind]
     P, T = Pf(), Tf(V)

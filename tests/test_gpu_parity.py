@@ -26,11 +26,12 @@ def lib_fid(sysm, cfg, amps, want_grad=True, **kw):
 
 
 # ----------------------------------------------------------- small cases
-@pytest.mark.parametrize("prec,order,hold,chunk", [
-    ("f64", 1, "zoh", 7), ("f64", 2, "foh", 6), ("f32", 2, "foh", 7), ("f32", 1, "zoh", 0)])
-def test_small_propagator_and_fidelity(prec, order, hold, chunk):
+@pytest.mark.parametrize("prec,order,hold,chunk,basis", [
+    ("f64", 1, "zoh", 7, "column"), ("f64", 2, "foh", 6, "column"), ("f32", 2, "foh", 7, "hermitian"),
+    ("f32", 2, "foh", 7, "column"), ("f32", 1, "zoh", 0, "hermitian"), ("f32", 1, "zoh", 0, "column")])
+def test_small_propagator_and_fidelity(prec, order, hold, chunk, basis):
     cfg = synth.small_case(100 + chunk, n_slices=40, dt=2.5e-4 if order == 2 else 1e-3)
-    sysm = lib_system(cfg, prec, order, hold, chunk=chunk)
+    sysm = lib_system(cfg, prec, order, hold, chunk=chunk, basis=basis)
     amps = rounded(cfg["amps"], prec)
     osys = oracle_system(cfg)
     U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], order, hold))
@@ -43,17 +44,38 @@ def test_small_propagator_and_fidelity(prec, order, hold, chunk):
     assert abs(F[0] - F_ref) < (1e-13 if prec == "f64" else 1e-7)
 
 
-@pytest.mark.parametrize("prec,order,hold,chunk", [
-    ("f64", 2, "foh", 7), ("f64", 1, "zoh", 5), ("f32", 2, "foh", 7)])
-def test_small_gradient(prec, order, hold, chunk):
+@pytest.mark.parametrize("prec,order,hold,chunk,basis", [
+    ("f64", 2, "foh", 7, "column"), ("f64", 1, "zoh", 5, "column"), ("f32", 2, "foh", 7, "hermitian"),
+    ("f32", 2, "foh", 7, "column")])
+def test_small_gradient(prec, order, hold, chunk, basis):
     cfg = synth.small_case(200 + chunk, n_slices=30, dt=2.5e-4 if order == 2 else 1e-3)
-    sysm = lib_system(cfg, prec, order, hold, chunk=chunk)
+    sysm = lib_system(cfg, prec, order, hold, chunk=chunk, basis=basis)
     amps = rounded(cfg["amps"], prec)
     osys = oracle_system(cfg)
     F_ref, g_ref = oracle.grad_adjoint(osys, amps, cfg["dt"], order, hold, cfg["U_target"])
     F, g = lib_fid(sysm, cfg, amps)
     assert abs(F[0] - F_ref) < (1e-12 if prec == "f64" else 1e-7)
     assert rel(g, g_ref) < (1e-9 if prec == "f64" else 1e-4)
+
+
+def test_padded_tiles_both_bases():
+    """Two spins (d = 4): the superoperator fills the top-left 16 x 16 of a
+    64 x 64 tile. In the basis of Hermitian operators the padding maps to
+    itself; propagator, fidelity and gradient agree with the oracle in both
+    bases."""
+    cfg = synth.small_case(502, n_spins=2, n_slices=35, dt=2.5e-4)
+    amps = rounded(cfg["amps"], "f32")
+    osys = oracle_system(cfg)
+    U_ref = oracle.propagate(osys.omegas(amps, cfg["dt"], 2, "foh"))
+    F_ref, g_ref = oracle.grad_adjoint(osys, amps, cfg["dt"], 2, "foh", cfg["U_target"])
+    for basis in ("hermitian", "column"):
+        sysm = lib_system(cfg, "f32", 2, "foh", chunk=6, basis=basis)
+        U = sysm.propagate(to_dev(amps, sysm), [35], cfg["dt"],
+                           static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+        assert rel(U, U_ref) < 2e-6, basis
+        F, g = lib_fid(sysm, cfg, amps)
+        assert abs(F[0] - F_ref) < 1e-7, basis
+        assert rel(g, g_ref) < 1e-4, basis
 
 
 def test_zoh_second_order_equals_first_order():
@@ -106,15 +128,36 @@ def test_config0_full_fp64():
     assert abs(F[0] - F_ref) < 1e-12
 
 
-@pytest.fixture(scope="module")
-def config1_run():
+@pytest.fixture(scope="module", params=["hermitian", "column"])
+def config1_run(request):
     cfg = synth.config1()
-    sysm = lib_system(cfg)
+    sysm = lib_system(cfg, basis=request.param)
     amps = rounded(cfg["amps"], "f32")
     F, g = lib_fid(sysm, cfg, amps)
     U = sysm.propagate(to_dev(amps, sysm), [4096], cfg["dt"],
                        static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
+    sysm.basis = request.param
     return cfg, amps, F, g, U, sysm
+
+
+def hermitian_basis_change(d):
+    """T with (T S T^dag) real for every Hermiticity-preserving superoperator S
+    in column stacking (vec(rho)[k + l d] = rho[k, l]): row k + l d is the
+    coordinate on |k><k| (k = l), on (|k><l| + |l><k|) / sqrt 2 (k < l) or on
+    i (|l><k| - |k><l|) / sqrt 2 (k > l)."""
+    n = d * d
+    T = np.zeros((n, n), dtype=complex)
+    h = np.sqrt(0.5)
+    for a in range(n):
+        k, l = a % d, a // d
+        q = l + k * d
+        if k == l:
+            T[a, a] = 1.0
+        elif k < l:
+            T[a, a], T[a, q] = h, h
+        else:
+            T[a, a], T[a, q] = 1j * h, -1j * h
+    return T
 
 
 def test_config1_propagator_and_fidelity(config1_run):
@@ -125,8 +168,16 @@ def test_config1_propagator_and_fidelity(config1_run):
     F_ref, _ = oracle.fidelity(U_ref, cfg["U_target"])
     assert abs(F[0] - F_ref) <= 1e-6
     hist = sysm.selection_histogram()
-    # the propagate call: s = 0 everywhere, Pade-2 for all but the few slices above theta_2
-    assert hist[:2, 0].sum() == 4096 and hist[0, 0] > 0.99 * 4096
+    # the propagate call: s = 0 everywhere, Pade-3 exactly for the slices whose
+    # exponent's 1-norm in the kernel's basis exceeds theta_2 (up to slices at
+    # the threshold within FP32 rounding)
+    oms = osys.omegas(amps, cfg["dt"], 2, "foh")
+    if sysm.basis == "hermitian":
+        T = hermitian_basis_change(8)
+        oms = [(T @ o @ T.conj().T).real for o in oms]
+    norms = np.array([np.abs(o).sum(axis=0).max() for o in oms])
+    above = int((norms > 8.093024022188482e-2).sum())   # theta_2 of the FP32 degree choice
+    assert hist[:2, 0].sum() == 4096 and abs(int(hist[1, 0]) - above) <= 2, (above, hist[:2, 0])
 
 
 def test_config1_gradient_sampled(config1_run):
