@@ -60,10 +60,10 @@ __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B, 
 // register r) and a lane part (the row of lane group g); the address is the
 // uniform part folded into the base plus one 32-bit lane offset shared by all
 // sixteen registers, which keeps the hooks below to a register or two.
-template <typename T, bool TRANS>
-__device__ __forceinline__ cpx<T>* tile_elem(cpx<T>* M, int q, int r, const Lane& L) {
+template <typename T, bool TRANS, typename E>
+__device__ __forceinline__ E* tile_elem(E* M, int q, int r, const Lane& L) {
   const int ru = 16 * q + Sub<T>::row(0, r), rl = Sub<T>::row(L.g, 0);
-  cpx<T>* base = M + (TRANS ? ru : ru * 64);
+  E* base = M + (TRANS ? ru : ru * 64);
   return base + (uint32_t)(TRANS ? L.col * 64 + rl : rl * 64 + L.col);
 }
 
@@ -73,7 +73,10 @@ __device__ __forceinline__ cpx<T>* tile_elem(cpx<T>* M, int q, int r, const Lane
 // load these rows are adjacent in memory: one 16-byte access), so that the
 // tile has arrived well before the product that follows needs it. A store
 // moves register (q, r) = (st / 4, st % 4) at step st.
-template <typename T, bool TRANS, int S0 = 0>
+// RE: the global tile is real, stored as a row-major 64 x 64 array of T in
+// the first half of its slot (half the bytes of the complex tile); a load sets
+// the imaginary parts to zero.
+template <typename T, bool TRANS, int S0 = 0, bool RE = false>
 struct TileLoad {
   RT<T>& X;
   const cpx<T>* M;
@@ -83,23 +86,65 @@ struct TileLoad {
     const int e = 2 * (st - S0), q = e >> 2, r = e & 3;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const cpx<T> v = *tile_elem<T, TRANS>(const_cast<cpx<T>*>(M), q, r + u, L);
-      X.re[q][r + u] = v.re; X.im[q][r + u] = v.im;
+      if constexpr (RE) {
+        X.re[q][r + u] = *tile_elem<T, TRANS>(reinterpret_cast<const T*>(M), q, r + u, L);
+        X.im[q][r + u] = T(0);
+      } else {
+        const cpx<T> v = *tile_elem<T, TRANS>(M, q, r + u, L);
+        X.re[q][r + u] = v.re; X.im[q][r + u] = v.im;
+      }
     }
   }
 };
 
-template <typename T>
+template <typename T, bool RE = false>
 struct TileStore {
   const RT<T>& X;
   cpx<T>* M;
   __device__ __forceinline__ void operator()(int st) const {
     const Lane L;
     const int q = st >> 2, r = st & 3;
-    cpx<T> v; v.re = X.re[q][r]; v.im = X.im[q][r];
-    *tile_elem<T, false>(M, q, r, L) = v;
+    if constexpr (RE) {
+      *tile_elem<T, false>(reinterpret_cast<T*>(M), q, r, L) = X.re[q][r];
+    } else {
+      cpx<T> v; v.re = X.re[q][r]; v.im = X.im[q][r];
+      *tile_elem<T, false>(M, q, r, L) = v;
+    }
   }
 };
+
+// Whole-tile transfers between a register tile and a global tile (pitch 64),
+// complex or, with RE, real as in TileLoad.
+template <typename T, bool TRANS, bool RE>
+__device__ __forceinline__ void gl_load(RT<T>& X, const cpx<T>* M) {
+  if constexpr (RE) {
+    const T* R = reinterpret_cast<const T*>(M);
+    const Lane L;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        X.re[q][r] = *tile_elem<T, TRANS>(R, q, r, L);
+        X.im[q][r] = T(0);
+      }
+  } else {
+    rt_load<T, TRANS>(X, M, 64);
+  }
+}
+
+template <typename T, bool RE>
+__device__ __forceinline__ void gl_store(const RT<T>& X, cpx<T>* M) {
+  if constexpr (RE) {
+    T* R = reinterpret_cast<T*>(M);
+    const Lane L;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) *tile_elem<T, false>(R, q, r, L) = X.re[q][r];
+  } else {
+    rt_store<T, false>(X, M, 64);
+  }
+}
 
 // Compact store of the support entries of a tile (sparse basis): kpack holds
 // this thread's 16-bit mask of support registers and, above it, the slot of its
@@ -214,10 +259,16 @@ __global__ void __launch_bounds__(WG) k_omega(SliceArgs a, int n_total) {
     __syncthreads();
     const T f = (T)ldexp(1.0, -ms_sh[1]);
     cpx<T>* out = tile_at<T>(a.omega, (size_t)n);
+    if (a.real) {   // the real tile of the slice kernels' real mode
+      T* ro = reinterpret_cast<T*>(out);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      cpx<T> v; v.re = acc[s][e].re * f; v.im = acc[s][e].im * f;
-      out[(rb + e) * 64 + col] = v;
+      for (int e = 0; e < 16; ++e) ro[(rb + e) * 64 + col] = acc[s][e].re * f;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        cpx<T> v; v.re = acc[s][e].re * f; v.im = acc[s][e].im * f;
+        out[(rb + e) * 64 + col] = v;
+      }
     }
   }
 }
@@ -297,9 +348,13 @@ __global__ void __launch_bounds__(WG) k_omega_sparse(SliceArgs a, int n_total) {
       // streaming stores: the tiles (32 KiB per slice) far exceed the caches
       // before the slice kernels read them (measured 1.56 -> 1.46 ms per launch)
       const cpx<T> x = col[r][c];
-      cpx<T>* dst = out + (b * RB + r) * 64 + c;
-      __builtin_nontemporal_store(x.re, &dst->re);
-      __builtin_nontemporal_store(x.im, &dst->im);
+      if (a.real) {   // the real tile of the slice kernels' real mode
+        __builtin_nontemporal_store(x.re, reinterpret_cast<T*>(out) + (b * RB + r) * 64 + c);
+      } else {
+        cpx<T>* dst = out + (b * RB + r) * 64 + c;
+        __builtin_nontemporal_store(x.re, &dst->re);
+        __builtin_nontemporal_store(x.im, &dst->im);
+      }
     }
   }
 }
@@ -516,14 +571,14 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   rt_zero(A2);
   // unpipelined: measured faster, and it leaves the kernel without spills
   if constexpr (st && hk) {
-    mm<T, false, RE>(A2, slot<T, 0>(sh, gs), A, TileStore<T>{Pl, ws + WS_PLOC * TILE});
+    mm<T, false, RE>(A2, slot<T, 0>(sh, gs), A, TileStore<T, RE>{Pl, ws + WS_PLOC * TILE});
   } else {
-    if constexpr (st) rt_store<T, false>(Pl, ws + WS_PLOC * TILE, 64);
+    if constexpr (st) gl_store<T, RE>(Pl, ws + WS_PLOC * TILE);
     mm<T, false, RE>(A2, slot<T, 0>(sh, gs), A);
   }
   ck.mark(1);
   // single precision stores A^2 during the next product
-  if constexpr (st && !hk) rt_store<T, false>(A2, ws + WS_A2 * TILE, 64);
+  if constexpr (st && !hk) gl_store<T, RE>(A2, ws + WS_A2 * TILE);
   const int K = sc.K;
   if (sizeof(T) == 4 && m == 2 && K >= 16) {
     // r_2(A) by its power series, truncated at degree 4 (the selection rule keeps
@@ -542,10 +597,10 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     rt_add_diag(Bk, (T)r[2]);
     ck.mark(3);
     if constexpr (st)
-      mm<T, false, RE>(R, slot<T, 1>(sh, gs), Bk, TileStore<T>{A2, ws + WS_A2 * TILE});
+      mm<T, false, RE>(R, slot<T, 1>(sh, gs), Bk, TileStore<T, RE>{A2, ws + WS_A2 * TILE});
     else
       mm<T, false, RE>(R, slot<T, 1>(sh, gs), Bk);
-    if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
+    if constexpr (st) gl_store<T, RE>(R, ws + WS_S * TILE);
   } else {
   RT<T> V;   // the even part minus I
   RT<T> U;   // the odd part
@@ -576,7 +631,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   }
   rt_zero(U);
   if constexpr (st && hk)
-    mm<T, true, RE>(U, slot<T, 0>(sh, gs), W, TileStore<T>{A2, ws + WS_A2 * TILE});
+    mm<T, true, RE>(U, slot<T, 0>(sh, gs), W, TileStore<T, RE>{A2, ws + WS_A2 * TILE});
   else
     mm<T, true, RE>(U, slot<T, 0>(sh, gs), W);
   }
@@ -633,7 +688,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     rt_add_diag(V, T(-1));
   }
   ck.mark(3);
-  if constexpr (st && !hk) rt_store<T, false>(V, ws + WS_QINV * TILE, 64);
+  if constexpr (st && !hk) gl_store<T, RE>(V, ws + WS_QINV * TILE);
   // D = r_m(A) - I = X_Q + X_P + X_Q X_P (slot 1 may still be read by the
   // inverse's last product in other waves)
   __syncthreads();
@@ -642,10 +697,10 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   rt_copy(R, U);
   rt_axpy(R, T(1), V);
   if constexpr (st && hk)
-    mm<T, false, RE>(R, slot<T, 1>(sh, gs), U, TileStore<T>{V, ws + WS_QINV * TILE});
+    mm<T, false, RE>(R, slot<T, 1>(sh, gs), U, TileStore<T, RE>{V, ws + WS_QINV * TILE});
   else
     mm<T, true, RE>(R, slot<T, 1>(sh, gs), U);
-  if constexpr (st) rt_store<T, false>(R, ws + WS_S * TILE, 64);
+  if constexpr (st) gl_store<T, RE>(R, ws + WS_S * TILE);
   }
   ck.mark(4);
   // squarings: (I + D)^2 = I + 2 D + D^2
@@ -772,7 +827,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
     RunProd<T> P;
     rp_identity(P);
     RT<T> A;
-    rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
+    gl_load<T, false, RE>(A, tile_at<T>(a.omega, (size_t)ch.first));
     for (int k0 = 0; k0 < ch.count; k0 += CODE_WINDOW) {
       const int k1 = min(ch.count, k0 + CODE_WINDOW);
       CodeWindow cw;
@@ -787,7 +842,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
         // the next slice's Omega tile, spread over the chain product (the chunk's
         // last slice reloads its own, so that the loads are unconditional)
         chain_step<T, RE>(P, slot<T, 3>(sh, gs),
-                          TileLoad<T, false>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
+                          TileLoad<T, false, 0, RE>{A, tile_at<T>(a.omega, (size_t)(k + 1 < ch.count ? n + 1 : n))});
         ck.mark(6);
       }
     }
@@ -834,14 +889,14 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   rt_zero(E);
   if constexpr (bwd_carry<T>) {
     // (this product and the D product run unpipelined: measured faster here)
-    mm<T, false, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true>{R, ws + WS_S * TILE});
+    mm<T, false, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true, 0, RE>{R, ws + WS_S * TILE});
   } else {
-    rt_load<T, true>(Pl, ws + WS_PLOC * TILE, 64);
+    gl_load<T, true, RE>(Pl, ws + WS_PLOC * TILE);
     mm<T, true, RE>(E, slot<T, 0>(sh, gs), Pl);
   }
   if (s) rt_scale(E, sc);
   ck.mark(1);
-  if constexpr (!bwd_carry<T>) rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)n), 64);
+  if constexpr (!bwd_carry<T>) gl_load<T, true, RE>(A, tile_at<T>(a.omega, (size_t)n));
   __syncthreads();
   put<T, false>(A, slot<T, 0>(sh, gs));
   put<T, false>(E, slot<T, 1>(sh, gs));
@@ -851,7 +906,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   rt_zero(L2);
   mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E);
   if constexpr (bwd_carry<T>)
-    mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
+    mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true, 0, RE>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
   else
     mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A);
   ck.mark(3);
@@ -890,7 +945,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_poly1(LV, L2, (T)b[2], T(0));
   } else {
     RT<T> A2;
-    rt_load<T, true>(A2, ws + WS_A2 * TILE, 64);
+    gl_load<T, true, RE>(A2, ws + WS_A2 * TILE);
     rt_poly1(W, A2, (T)b[3], (T)b[1]);
     rt_poly1(LW, L2, (T)b[3], T(0));
     rt_poly1(LV, L2, (T)b[2], T(0));
@@ -939,13 +994,13 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     LW.re[q] = vr - LU.re[q]; LW.im[q] = vi - LU.im[q];
     LU.re[q] = vr + LU.re[q]; LU.im[q] = vi + LU.im[q];
   }
-  if constexpr (!bwd_carry<T>) rt_load<T, true>(R, ws + WS_S * TILE, 64);
+  if constexpr (!bwd_carry<T>) gl_load<T, true, RE>(R, ws + WS_S * TILE);
   // X = L_P - L_Q r_m(A) = (L_P - L_Q) - L_Q D
 #pragma unroll
   for (int q = 0; q < 4; ++q) { LU.re[q] -= LW.re[q]; LU.im[q] -= LW.im[q]; }
   __syncthreads();
   put<T, false>(LW, slot<T, 1>(sh, gs));
-  if constexpr (!bwd_carry<T>) rt_load<T, true>(Qi, ws + WS_QINV * TILE, 64);
+  if constexpr (!bwd_carry<T>) gl_load<T, true, RE>(Qi, ws + WS_QINV * TILE);
   put<T, false>(Qi, slot<T, 2>(sh, gs));
   __syncthreads();
   ck.mark(6);
@@ -1001,14 +1056,14 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   rt_copy(Zn, Z);
   if constexpr (bwd_carry<T>) {
     // P_loc^T (needed first) in the first half of the k-steps, Omega in the second
-    const TileLoad<T, true, 0> lp{Pl, nx + WS_PLOC * TILE};
-    const TileLoad<T, true, 8> la{A, tile_at<T>(a.omega, (size_t)nn)};
+    const TileLoad<T, true, 0, RE> lp{Pl, nx + WS_PLOC * TILE};
+    const TileLoad<T, true, 8, RE> la{A, tile_at<T>(a.omega, (size_t)nn)};
     if (a.sp.n_sup > 0)
       mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z,
-         Hooks3<SupportStore<T>, TileLoad<T, true, 0>, TileLoad<T, true, 8>>{{K, kt, kpack}, lp, la});
+         Hooks3<SupportStore<T>, TileLoad<T, true, 0, RE>, TileLoad<T, true, 8, RE>>{{K, kt, kpack}, lp, la});
     else
       mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z,
-         Hooks3<TileStore<T>, TileLoad<T, true, 0>, TileLoad<T, true, 8>>{{K, kt}, lp, la});
+         Hooks3<TileStore<T>, TileLoad<T, true, 0, RE>, TileLoad<T, true, 8, RE>>{{K, kt}, lp, la});
   } else {
     mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z);
   }
@@ -1037,7 +1092,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
       RunProd<T> P;
       rp_identity(P);
       RT<T> A;
-      rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first), 64);
+      gl_load<T, false, RE>(A, tile_at<T>(a.omega, (size_t)ch.first));
       for (int k0 = 0; k0 < ch.count; k0 += CODE_WINDOW) {
         const int k1 = min(ch.count, k0 + CODE_WINDOW);
         CodeWindow cw;
@@ -1047,7 +1102,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
           RT<T> D;
           fwd_slice<T, true, RE>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
           if (k + 1 < ch.count) {
-            rt_load<T, false>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1), 64);
+            gl_load<T, false, RE>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1));
             __syncthreads();
             put<T, false>(D, slot<T, 3>(sh, gs));
             __syncthreads();
@@ -1065,8 +1120,8 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
     RT<T> Pl, A;
     if constexpr (bwd_carry<T>) {
       if (RC) __syncthreads();   // the recomputed tiles are read by other threads
-      rt_load<T, true>(Pl, ws_of(ch.count - 1) + WS_PLOC * TILE, 64);
-      rt_load<T, true>(A, tile_at<T>(a.omega, (size_t)ch.first + ch.count - 1), 64);
+      gl_load<T, true, RE>(Pl, ws_of(ch.count - 1) + WS_PLOC * TILE);
+      gl_load<T, true, RE>(A, tile_at<T>(a.omega, (size_t)ch.first + ch.count - 1));
       // Wait here, once per chunk, for Z, P_loc and Omega. Otherwise the compiler's
       // count of operations in flight at the loop head is that of this entry
       // path, where nothing follows these loads, and every slice's first wait
