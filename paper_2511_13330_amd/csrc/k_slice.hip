@@ -904,7 +904,14 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   ck.mark(2);
   RT<T> L2;
   rt_zero(L2);
-  mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E);
+  // real mode: the next slice's P_loc^T arrives during this product (Pl's last
+  // use was the E product) and its Omega tile during the next one after A's
+  // last use, not in the slice's last product: the loop-carried registers are
+  // then complete at the loop's back edge instead of waited for there
+  if constexpr (bwd_carry<T> && RE)
+    mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E, TileLoad<T, true, 0, RE>{Pl, nx + WS_PLOC * TILE});
+  else
+    mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E);
   if constexpr (bwd_carry<T>)
     mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true, 0, RE>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
   else
@@ -935,7 +942,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_axpy(Lq, (T)r[4], L2);
     ck.mark(5);
     // both unpipelined: measured faster here
-    mm<T, false, RE>(K, slot<T, 2>(sh, gs), Bq);
+    if constexpr (bwd_carry<T> && RE)
+      mm<T, false, RE>(K, slot<T, 2>(sh, gs), Bq, TileLoad<T, true, 0, RE>{A, tile_at<T>(a.omega, (size_t)nn)});
+    else
+      mm<T, false, RE>(K, slot<T, 2>(sh, gs), Bq);
     ck.mark(6);
     mm<T, false, RE>(K, slot<T, 3>(sh, gs), Lq);
   } else {
@@ -1007,7 +1017,10 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   {
     RT<T> Tm;
     rt_zero(Tm);
-    mm<T, true, RE>(Tm, slot<T, 1>(sh, gs), R);
+    if constexpr (bwd_carry<T> && RE)
+      mm<T, true, RE>(Tm, slot<T, 1>(sh, gs), R, TileLoad<T, true, 0, RE>{A, tile_at<T>(a.omega, (size_t)nn)});
+    else
+      mm<T, true, RE>(Tm, slot<T, 1>(sh, gs), R);
 #pragma unroll
     for (int q = 0; q < 4; ++q) { LU.re[q] -= Tm.re[q]; LU.im[q] -= Tm.im[q]; }
   }
@@ -1054,7 +1067,12 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   __syncthreads();
   RT<T> Zn;
   rt_copy(Zn, Z);
-  if constexpr (bwd_carry<T>) {
+  if constexpr (bwd_carry<T> && RE) {
+    if (a.sp.n_sup > 0)
+      mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z, SupportStore<T>{K, kt, kpack});
+    else
+      mm<T, true, RE>(Zn, slot<T, 0>(sh, gs), Z, TileStore<T>{K, kt});
+  } else if constexpr (bwd_carry<T>) {
     // P_loc^T (needed first) in the first half of the k-steps, Omega in the second
     const TileLoad<T, true, 0, RE> lp{Pl, nx + WS_PLOC * TILE};
     const TileLoad<T, true, 8, RE> la{A, tile_at<T>(a.omega, (size_t)nn)};
