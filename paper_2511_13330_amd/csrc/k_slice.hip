@@ -28,7 +28,7 @@ constexpr int MAXNB = 32;
 constexpr int NPHASE = 16;
 
 template <typename T> struct Shared {
-  cpx<T> slots[Cfg<T>::NLDS * SLOT];
+  alignas(16) cpx<T> slots[Cfg<T>::NLDS * SLOT];   // 16-byte reads of real tiles
   cpx<T> colbuf[128];
   double red[4 * MAXNB];
   long long clk[NPHASE];
@@ -41,18 +41,32 @@ __device__ __forceinline__ cpx<T>* slot(Shared<T>& sh, cpx<T>* gs) {
   else return gs + (K - Cfg<T>::NLDS) * SLOT;
 }
 
-template <typename T, bool TRANS>
-__device__ __forceinline__ void put(const RT<T>& X, cpx<T>* S) { rt_store<T, TRANS>(X, S, PITCH); }
+// RE (real mode, single precision): slots hold real tiles in the rl_store
+// layout, and the products read them with 16-byte loads along k.
+template <typename T, bool TRANS, bool RE = false>
+__device__ __forceinline__ void put(const RT<T>& X, cpx<T>* S) {
+  if constexpr (RE) rl_store<T>(X, reinterpret_cast<T*>(S));
+  else rt_store<T, TRANS>(X, S, PITCH);
+}
+
+// a slot back into a register tile
+template <typename T, bool RE>
+__device__ __forceinline__ void get(RT<T>& X, const cpx<T>* S) {
+  if constexpr (RE) rl_load<T>(X, reinterpret_cast<const T*>(S));
+  else rt_load<T, false>(X, S, PITCH);
+}
 
 template <typename T, bool PIPE = true, bool RE = false>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) {
-  gemm_acc<T, false, PITCH, PIPE, NoHook, RE>(acc, A, B);
+  if constexpr (RE) gemm_rl<T, PIPE>(acc, reinterpret_cast<const T*>(A), B);
+  else gemm_acc<T, false, PITCH, PIPE, NoHook, RE>(acc, A, B);
 }
 
 // mm with a hook that moves a share of a global tile at each k-step
 template <typename T, bool PIPE = true, bool RE = false, typename H>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B, const H& hook) {
-  gemm_acc<T, false, PITCH, PIPE, H, RE>(acc, A, B, hook);
+  if constexpr (RE) gemm_rl<T, PIPE, H>(acc, reinterpret_cast<const T*>(A), B, hook);
+  else gemm_acc<T, false, PITCH, PIPE, H, RE>(acc, A, B, hook);
 }
 
 // Element (row(q, r), col) of this thread in a row-major 64 x 64 tile at M
@@ -565,7 +579,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   // its last read only where no barrier has passed since: the previous slice's
   // last reads of slots 0 and 1 (and of 3, by the chain) are all at least one
   // barrier back when this slice first writes them.
-  put<T, false>(A, slot<T, 0>(sh, gs));
+  put<T, false, RE>(A, slot<T, 0>(sh, gs));
   __syncthreads();
   RT<T> A2;
   rt_zero(A2);
@@ -585,11 +599,11 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     // the tail below u/2): D = r_2(A) - I = rho_1 A + A^2 (rho_2 I + rho_3 A + rho_4 A^2),
     // one product, during which A^2 is stored for the adjoint
     const double* r = a.pade.r2;   // computed once on the host
-    put<T, false>(A2, slot<T, 1>(sh, gs));
+    put<T, false, RE>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
     ck.mark(2);
     RT<T> Bk;   // A again, from LDS: a register copy here makes this branch spill
-    rt_load<T, false>(Bk, slot<T, 0>(sh, gs), PITCH);
+    get<T, RE>(Bk, slot<T, 0>(sh, gs));
     rt_copy(R, Bk);
     rt_scale(R, (T)r[1]);
     rt_scale(Bk, (T)r[3]);
@@ -614,7 +628,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   rt_poly1(W, A2, (T)b[3], (T)b[1]);
   rt_poly1(V, A2, (T)b[2], T(0));
   if (sizeof(T) == 8 && m >= 5) {   // single precision uses m in {2, 3} only
-    put<T, false>(A2, slot<T, 1>(sh, gs));
+    put<T, false, RE>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
     RT<T> A4;
     rt_zero(A4);
@@ -648,7 +662,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     // Pade-3: Q^{-1} = sum_{k<=5} c_k A^k, the power series of 1/q_3 (its tail
     // is below the unit roundoff by the selection rule); c_0 = 1
     const double* c = a.pade.c3;   // computed once on the host
-    put<T, false>(A2, slot<T, 1>(sh, gs));
+    put<T, false, RE>(A2, slot<T, 1>(sh, gs));
     __syncthreads();
     RT<T> A4;
     rt_zero(A4);
@@ -668,13 +682,13 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
     rt_copy(V, F);
     for (int k = 1; k < K; ++k) {
       __syncthreads();
-      put<T, false>(F, slot<T, 2>(sh, gs));
+      put<T, false, RE>(F, slot<T, 2>(sh, gs));
       __syncthreads();
       RT<T> F2;
       rt_zero(F2);
       mm<T, true, RE>(F2, slot<T, 2>(sh, gs), F);
       __syncthreads();
-      put<T, false>(F2, slot<T, 2>(sh, gs));
+      put<T, false, RE>(F2, slot<T, 2>(sh, gs));
       __syncthreads();
       RT<T> T1;
       rt_copy(T1, F2);
@@ -692,7 +706,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   // D = r_m(A) - I = X_Q + X_P + X_Q X_P (slot 1 may still be read by the
   // inverse's last product in other waves)
   __syncthreads();
-  put<T, false>(V, slot<T, 1>(sh, gs));
+  put<T, false, RE>(V, slot<T, 1>(sh, gs));
   __syncthreads();
   rt_copy(R, U);
   rt_axpy(R, T(1), V);
@@ -706,7 +720,7 @@ __device__ void fwd_slice(RT<T>& R, const RT<T>& A, const RT<T>& Pl, Shared<T>& 
   // squarings: (I + D)^2 = I + 2 D + D^2
   for (int k = 0; k < s; ++k) {
     __syncthreads();
-    put<T, false>(R, slot<T, 2>(sh, gs));
+    put<T, false, RE>(R, slot<T, 2>(sh, gs));
     __syncthreads();
     RT<T> R2;
     rt_copy(R2, R);
@@ -837,7 +851,7 @@ __global__ void __launch_bounds__(WG, 1) k_forward(SliceArgs a) {
         cpx<T>* ws = ST ? tile_at<T>(a.ws_tiles, (size_t)n * WS_TILES) : nullptr;
         RT<T> D;
         fwd_slice<T, ST, RE>(D, A, P.hi, sh, gs, a, cw.at(k - k0), ws, ck);
-        put<T, false>(D, slot<T, 3>(sh, gs));   // slot 3's last reader is the previous chain
+        put<T, false, RE>(D, slot<T, 3>(sh, gs));   // slot 3's last reader is the previous chain
         __syncthreads();
         // the next slice's Omega tile, spread over the chain product (the chunk's
         // last slice reloads its own, so that the loads are unconditional)
@@ -882,7 +896,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
 
   // E = M_n^T / 2^s,  M_n^T = Z_n^T P_loc,n^T
   __syncthreads();
-  put<T, false>(Z, slot<T, 0>(sh, gs));
+  put<T, false, RE>(Z, slot<T, 0>(sh, gs));
   __syncthreads();
   ck.mark(11);
   RT<T> E;
@@ -898,8 +912,8 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   ck.mark(1);
   if constexpr (!bwd_carry<T>) gl_load<T, true, RE>(A, tile_at<T>(a.omega, (size_t)n));
   __syncthreads();
-  put<T, false>(A, slot<T, 0>(sh, gs));
-  put<T, false>(E, slot<T, 1>(sh, gs));
+  put<T, false, RE>(A, slot<T, 0>(sh, gs));
+  put<T, false, RE>(E, slot<T, 1>(sh, gs));
   __syncthreads();
   ck.mark(2);
   RT<T> L2;
@@ -926,15 +940,15 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     // A polynomial's derivative commutes with transposition, so the same formula
     // holds for the transposed operands held here (Qi holds (A^2)^T).
     const double* r = a.pade.r2;
-    put<T, false>(L2, slot<T, 2>(sh, gs));
-    put<T, false>(Qi, slot<T, 3>(sh, gs));
+    put<T, false, RE>(L2, slot<T, 2>(sh, gs));
+    put<T, false, RE>(Qi, slot<T, 3>(sh, gs));
     __syncthreads();
     ck.mark(4);
     RT<T> Bq, Lq;
     rt_copy(Bq, A);
     rt_scale(Bq, (T)r[3]);
     rt_axpy(Bq, (T)r[4], Qi);
-    rt_load<T, false>(Lq, slot<T, 1>(sh, gs), PITCH);   // E
+    get<T, RE>(Lq, slot<T, 1>(sh, gs));   // E
     rt_copy(K, Lq);
     rt_scale(K, (T)r[1]);
     rt_axpy(K, (T)r[2], L2);
@@ -960,8 +974,8 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_poly1(LW, L2, (T)b[3], T(0));
     rt_poly1(LV, L2, (T)b[2], T(0));
     if (sizeof(T) == 8 && m >= 5) {   // single precision uses m = 3 only
-      put<T, false>(A2, slot<T, 2>(sh, gs));
-      put<T, false>(L2, slot<T, 3>(sh, gs));
+      put<T, false, RE>(A2, slot<T, 2>(sh, gs));
+      put<T, false, RE>(L2, slot<T, 3>(sh, gs));
       __syncthreads();
       RT<T> A4, L4;
       rt_zero(A4);
@@ -989,7 +1003,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   ck.mark(4);
   RT<T> LU;
   if (pade2) {
-    rt_load<T, false>(LU, slot<T, 1>(sh, gs), PITCH);
+    get<T, RE>(LU, slot<T, 1>(sh, gs));
     rt_scale(LU, (T)b[1]);
   } else {
     rt_zero(LU);
@@ -1009,9 +1023,9 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
 #pragma unroll
   for (int q = 0; q < 4; ++q) { LU.re[q] -= LW.re[q]; LU.im[q] -= LW.im[q]; }
   __syncthreads();
-  put<T, false>(LW, slot<T, 1>(sh, gs));
+  put<T, false, RE>(LW, slot<T, 1>(sh, gs));
   if constexpr (!bwd_carry<T>) gl_load<T, true, RE>(Qi, ws + WS_QINV * TILE);
-  put<T, false>(Qi, slot<T, 2>(sh, gs));
+  put<T, false, RE>(Qi, slot<T, 2>(sh, gs));
   __syncthreads();
   ck.mark(6);
   {
@@ -1030,8 +1044,8 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   }
   for (int k = 0; k < s; ++k) {
     __syncthreads();
-    put<T, false>(R, slot<T, 0>(sh, gs));
-    put<T, false>(K, slot<T, 1>(sh, gs));
+    put<T, false, RE>(R, slot<T, 0>(sh, gs));
+    put<T, false, RE>(K, slot<T, 1>(sh, gs));
     __syncthreads();
     // with R = I + D: K <- R K + K R = 2 K + D K + K D ; D <- 2 D + D D
     RT<T> Kn, Rn;
@@ -1063,7 +1077,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   // Z_{n-1}^T = S_n^T Z_n^T = Z_n^T + D^T Z_n^T (with s = 0 no wave still reads
   // slot 0 here, but the barrier keeps the waves together: measured faster)
   __syncthreads();
-  put<T, false>(R, slot<T, 0>(sh, gs));
+  put<T, false, RE>(R, slot<T, 0>(sh, gs));
   __syncthreads();
   RT<T> Zn;
   rt_copy(Zn, Z);
@@ -1122,7 +1136,7 @@ __global__ void __launch_bounds__(WG, 1) k_backward(SliceArgs a) {
           if (k + 1 < ch.count) {
             gl_load<T, false, RE>(A, tile_at<T>(a.omega, (size_t)ch.first + k + 1));
             __syncthreads();
-            put<T, false>(D, slot<T, 3>(sh, gs));
+            put<T, false, RE>(D, slot<T, 3>(sh, gs));
             __syncthreads();
             chain_step<T, RE>(P, slot<T, 3>(sh, gs));
           }

@@ -315,6 +315,88 @@ __device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ 
   }
 }
 
+// Real tiles in LDS (single precision; the real mode of the slice kernels): a
+// row-major 64 x 64 float array with a row pitch of RPITCH_LDS floats, in the
+// memory of a complex slot. Rows are 16-byte aligned, and a lane's four k
+// values of one 16-wide k block are adjacent: one 16-byte read per (q, kb).
+constexpr int RPITCH_LDS = 68;
+
+// S[row][col] = X.re (the imaginary parts are not stored)
+template <typename T>
+__device__ __forceinline__ void rl_store(const RT<T>& X, T* __restrict__ S) {
+  const Lane L;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[L.template row<T>(q, r) * RPITCH_LDS + L.col] = X.re[q][r];
+}
+
+// X.re = S, X.im = 0
+template <typename T>
+__device__ __forceinline__ void rl_load(RT<T>& X, const T* __restrict__ S) {
+  const Lane L;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      X.re[q][r] = S[L.template row<T>(q, r) * RPITCH_LDS + L.col];
+      X.im[q][r] = T(0);
+    }
+}
+
+// acc.re += A B.re for a real A in LDS (rl_store layout) and a real register
+// tile B; acc.im is left as it is. Lane (w, g, c) reads A[16 q + c][16 kb +
+// 4 g .. 4 g + 3]: the k values of the kb block's four MFMA steps t (k = 16 kb
+// + 4 g + t, the order in which B holds them). hook(st), st = 4 kb + t, runs
+// ahead of step st's MFMAs as in gemm_acc. PIPE: the next block's reads are
+// issued before the current block's MFMAs.
+template <typename T, bool PIPE = true, typename H = NoHook>
+__device__ __forceinline__ void gemm_rl(RT<T>& acc, const T* __restrict__ A, const RT<T>& B,
+                                        const H& hook = H{}) {
+  static_assert(sizeof(T) == 4, "real LDS tiles are single precision");
+  typedef float f4rl __attribute__((ext_vector_type(4)));
+  constexpr bool hooked = !std::is_same<H, NoHook>::value;
+  const Lane L;
+  const T* base = A + L.c * RPITCH_LDS + 4 * L.g;
+  auto ld = [&](int kb, int q) -> f4rl {
+    return *reinterpret_cast<const f4rl*>(base + 16 * q * RPITCH_LDS + 16 * kb);
+  };
+  f4rl cur[4], nxt[4];
+  if constexpr (PIPE) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cur[q] = ld(0, q);
+  }
+#pragma unroll
+  for (int kb = 0; kb < 4; ++kb) {
+    if constexpr (PIPE) {
+      if (kb + 1 < 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nxt[q] = ld(kb + 1, q);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cur[q] = ld(kb, q);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if constexpr (hooked) {
+        __builtin_amdgcn_sched_barrier(0);
+        hook(4 * kb + t);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      const T br = B.re[kb][t];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc.re[q] = mfma4<T>(cur[q][t], br, acc.re[q]);
+    }
+    if constexpr (PIPE) {
+      if (kb + 1 < 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
+      }
+    }
+  }
+}
+
 // Column 1-norm max_j sum_i |X_ij| accumulated in FP64. red: 4 doubles of LDS.
 template <typename T>
 __device__ __forceinline__ double rt_norm1(const RT<T>& X, double* red) {
