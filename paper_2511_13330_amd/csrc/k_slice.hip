@@ -902,8 +902,9 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   RT<T> E;
   rt_zero(E);
   if constexpr (bwd_carry<T>) {
-    // (this product and the D product run unpipelined: measured faster here)
-    mm<T, false, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true, 0, RE>{R, ws + WS_S * TILE});
+    // (this product and the D product run unpipelined in the complex form,
+    // pipelined in the real one: measured faster each)
+    mm<T, RE, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true, 0, RE>{R, ws + WS_S * TILE});
   } else {
     gl_load<T, true, RE>(Pl, ws + WS_PLOC * TILE);
     mm<T, true, RE>(E, slot<T, 0>(sh, gs), Pl);
@@ -955,13 +956,14 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     rt_scale(Lq, (T)r[3]);
     rt_axpy(Lq, (T)r[4], L2);
     ck.mark(5);
-    // both unpipelined: measured faster here
+    // both unpipelined in the complex form, pipelined in the real one: measured
+    // faster each
     if constexpr (bwd_carry<T> && RE)
-      mm<T, false, RE>(K, slot<T, 2>(sh, gs), Bq, TileLoad<T, true, 0, RE>{A, tile_at<T>(a.omega, (size_t)nn)});
+      mm<T, true, RE>(K, slot<T, 2>(sh, gs), Bq, TileLoad<T, true, 0, RE>{A, tile_at<T>(a.omega, (size_t)nn)});
     else
       mm<T, false, RE>(K, slot<T, 2>(sh, gs), Bq);
     ck.mark(6);
-    mm<T, false, RE>(K, slot<T, 3>(sh, gs), Lq);
+    mm<T, RE, RE>(K, slot<T, 3>(sh, gs), Lq);
   } else {
   RT<T> W, LW, LV;
   const bool pade2 = sizeof(T) == 4 && m == 2;   // U = b_1 A: L_U = b_1 E, no A^2 needed
