@@ -255,7 +255,7 @@ def robust_sweep(args):
         tuned = sysm.autotune(a, ns, cfg["dt"], cfg["U_target"], reps=1, **kw)
     elif args.tuning and os.path.exists(args.tuning) and args.chunk == 0:
         sysm.load_tuning(args.tuning)
-        key = f"p32_o2_d8_s{int(np.floor(np.log2(int(ns.sum()))))}"
+        key = f"p32{'h' if real else ''}_o2_d8_s{int(np.floor(np.log2(int(ns.sum()))))}"
         with open(args.tuning) as f:
             for line in f:
                 rec = json.loads(line)
@@ -274,6 +274,8 @@ def robust_sweep(args):
     hist = sysm.selection_histogram()   # of the call's last wave: its (m, s) mix stands for all
     flops = (flops_from_hist(hist, forward_flops_per_slice)
              + flops_from_hist(hist, backward_flops_per_slice)) * slices / max(1, int(hist.sum()))
+    if real:
+        flops /= 4   # real products: 2 n^3 flops where a complex one counts 8 n^3
     return {"metric": "robust sweep: candidates x noise samples fwd+grad, seconds per sweep",
             "value": dt, "unit": "s/sweep", "n_gpus": 1, "higher_is_better": False,
             "vs_baseline": None, "dtype": "f32",
@@ -283,6 +285,8 @@ def robust_sweep(args):
                                    "3-spin FOH 2nd order", "items": int(len(ns)),
                        "slice_evaluations": slices, "waves": plan["waves"],
                        "chunk_slices": plan["chunk_slices"],
+                       "representation": ("real (basis of Hermitian operators)" if real
+                                          else "complex (column stacking)"),
                        "autotune": {"chunk": tuned[0], "inverse_variant": tuned[1],
                                     "ms_per_call_when_tuned": tuned[2]} if tuned else None},
             "slice_evals_per_s": slices / dt, "tflops_algorithmic": flops / dt / 1e12,
