@@ -28,3 +28,23 @@ def rounded(amps, precision):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def hermitian_basis_change(d):
+    """T with (T S T^dag) real for every Hermiticity-preserving superoperator S
+    in column stacking (vec(rho)[k + l d] = rho[k, l]): row k + l d is the
+    coordinate on |k><k| (k = l), on (|k><l| + |l><k|) / sqrt 2 (k < l) or on
+    i (|l><k| - |k><l|) / sqrt 2 (k > l)."""
+    n = d * d
+    T = np.zeros((n, n), dtype=complex)
+    h = np.sqrt(0.5)
+    for a in range(n):
+        k, l = a % d, a // d
+        q = l + k * d
+        if k == l:
+            T[a, a] = 1.0
+        elif k < l:
+            T[a, a], T[a, q] = h, h
+        else:
+            T[a, a], T[a, q] = 1j * h, -1j * h
+    return T

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import oracle_system, lib_system, rounded, rel
+from helpers import oracle_system, lib_system, rounded, rel, hermitian_basis_change
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -138,26 +138,6 @@ def config1_run(request):
                        static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
     sysm.basis = request.param
     return cfg, amps, F, g, U, sysm
-
-
-def hermitian_basis_change(d):
-    """T with (T S T^dag) real for every Hermiticity-preserving superoperator S
-    in column stacking (vec(rho)[k + l d] = rho[k, l]): row k + l d is the
-    coordinate on |k><k| (k = l), on (|k><l| + |l><k|) / sqrt 2 (k < l) or on
-    i (|l><k| - |k><l|) / sqrt 2 (k > l)."""
-    n = d * d
-    T = np.zeros((n, n), dtype=complex)
-    h = np.sqrt(0.5)
-    for a in range(n):
-        k, l = a % d, a // d
-        q = l + k * d
-        if k == l:
-            T[a, a] = 1.0
-        elif k < l:
-            T[a, a], T[a, q] = h, h
-        else:
-            T[a, a], T[a, q] = 1j * h, -1j * h
-    return T
 
 
 def test_config1_propagator_and_fidelity(config1_run):
