@@ -71,7 +71,7 @@ typedef enum {
   LMAG_E_NOSYSTEM = -2,    /* compute call before lmag_set_system */
   LMAG_E_NOMEM = -3,       /* device allocation failed */
   LMAG_E_DEVICE = -4,      /* HIP runtime / kernel error */
-  LMAG_E_UNSUPPORTED = -5  /* valid request outside what this build supports */
+  LMAG_E_UNSUPPORTED = -5  /* valid request outside what the library supports */
 } lmag_status;
 
 enum { LMAG_F32 = 32, LMAG_F64 = 64 };

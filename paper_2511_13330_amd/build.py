@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "liblmag.so")
 SOURCES = ["k_slice.hip", "k_aux.hip", "k_optim.hip", "k_mlp.hip", "k_big.hip", "k_real.hip", "lmag.cpp"]
 ARCH = os.environ.get("LMAG_OFFLOAD_ARCH", "gfx950")
 
-# packed FP32 instructions are disabled on purpose (build notes)
+# packed FP32 instructions (v_pk_*_f32) are disabled on purpose: some of their
+# forms have given wrong results on this hardware without any error
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
