@@ -157,7 +157,9 @@ typedef struct {
  * Omega_n (Eq. 13, plus the Gauss-Legendre commutator term at second order),
  * S_n = exp(Omega_n) by scale-and-square Pade (Eq. 14), and the ordered product
  * U = S_N ... S_1, later slices on the left (Eq. 15).
- * S_out: DEVICE [n_items][n][n] complex of the compute type: U of every item.
+ * S_out: DEVICE [n_items][n][n] complex of the compute type: U of every item,
+ * row-major, in column stacking whatever the system's basis (a propagator
+ * computed in the basis of Hermitian operators is transformed back).
  * Items may share amplitude rows. */
 lmag_status lmag_propagate(lmag_ctx *ctx, const lmag_batch *batch, void *S_out,
                            void *hip_stream);
