@@ -904,7 +904,12 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
   if constexpr (bwd_carry<T>) {
     // (this product and the D product run unpipelined in the complex form,
     // pipelined in the real one: measured faster each)
-    mm<T, RE, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true, 0, RE>{R, ws + WS_S * TILE});
+    if constexpr (RE)   // real mode: Q^{-1} (or A^2) in the second half, three products ahead of its use
+      mm<T, true, RE>(E, slot<T, 0>(sh, gs), Pl,
+                      Hooks3<TileLoad<T, true, 0, RE>, TileLoad<T, true, 8, RE>, NoHook>{
+                          {R, ws + WS_S * TILE}, {Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE}, {}});
+    else
+      mm<T, false, RE>(E, slot<T, 0>(sh, gs), Pl, TileLoad<T, true, 0, RE>{R, ws + WS_S * TILE});
   } else {
     gl_load<T, true, RE>(Pl, ws + WS_PLOC * TILE);
     mm<T, true, RE>(E, slot<T, 0>(sh, gs), Pl);
@@ -927,7 +932,7 @@ __device__ void bwd_slice(RT<T>& Z, RT<T>& Pl, RT<T>& A, Shared<T>& sh, cpx<T>* 
     mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E, TileLoad<T, true, 0, RE>{Pl, nx + WS_PLOC * TILE});
   else
     mm<T, true, RE>(L2, slot<T, 0>(sh, gs), E);
-  if constexpr (bwd_carry<T>)
+  if constexpr (bwd_carry<T> && !RE)
     mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A, TileLoad<T, true, 0, RE>{Qi, ws + (ser2 ? WS_A2 : WS_QINV) * TILE});
   else
     mm<T, true, RE>(L2, slot<T, 1>(sh, gs), A);
