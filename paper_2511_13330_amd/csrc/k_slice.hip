@@ -59,14 +59,14 @@ __device__ __forceinline__ void get(RT<T>& X, const cpx<T>* S) {
 template <typename T, bool PIPE = true, bool RE = false>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B) {
   if constexpr (RE) gemm_rl<T, PIPE>(acc, reinterpret_cast<const T*>(A), B);
-  else gemm_acc<T, false, PITCH, PIPE, NoHook, RE>(acc, A, B);
+  else gemm_acc<T, false, PITCH, PIPE>(acc, A, B);
 }
 
 // mm with a hook that moves a share of a global tile at each k-step
 template <typename T, bool PIPE = true, bool RE = false, typename H>
 __device__ __forceinline__ void mm(RT<T>& acc, const cpx<T>* A, const RT<T>& B, const H& hook) {
   if constexpr (RE) gemm_rl<T, PIPE, H>(acc, reinterpret_cast<const T*>(A), B, hook);
-  else gemm_acc<T, false, PITCH, PIPE, H, RE>(acc, A, B, hook);
+  else gemm_acc<T, false, PITCH, PIPE, H>(acc, A, B, hook);
 }
 
 // Element (row(q, r), col) of this thread in a row-major 64 x 64 tile at M

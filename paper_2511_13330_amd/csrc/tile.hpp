@@ -158,65 +158,13 @@ struct NoHook {
 // hook(st) runs at each of the 16 k-steps st, ahead of that step's MFMAs: a
 // share of a global tile load or store placed there drains while the matrix
 // cores work, where the whole transfer issued at once would stall the wave.
-// RE (single precision): both operands are real (the imaginary parts are zero,
-// as in the basis of Hermitian operators): one MFMA product on the real parts,
-// acc.im left as it is.
-template <typename T, bool TA, int PA, bool PIPE = true, typename H = NoHook, bool RE = false>
+template <typename T, bool TA, int PA, bool PIPE = true, typename H = NoHook>
 __device__ __forceinline__ void gemm_acc(RT<T>& acc, const cpx<T>* __restrict__ A, const RT<T>& B,
                                          const H& hook = H{}) {
   constexpr bool hooked = !std::is_same<H, NoHook>::value;
   const Lane L;
   const int g = L.g, c = L.c;
-  if constexpr (sizeof(T) == 4 && RE) {
-    auto ldr = [&](int st, int q) -> T {
-      const int kb = st >> 2, t = st & 3;
-      return TA ? A[(16 * kb + Sub<T>::row(g, t)) * PA + 16 * q + c].re
-                : A[(16 * q + c) * PA + 16 * kb + Sub<T>::row(g, t)].re;
-    };
-    if constexpr (!PIPE) {
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        T a[4][4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) a[q][t] = ldr(4 * kb + t, q);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          if constexpr (hooked) {
-            __builtin_amdgcn_sched_barrier(0);
-            hook(4 * kb + t);
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          const T br = B.re[kb][t];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc.re[q] = mfma4<T>(a[q][t], br, acc.re[q]);
-        }
-      }
-      return;
-    }
-    T cur[4], nxt[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) cur[q] = ldr(0, q);
-#pragma unroll
-    for (int st = 0; st < 16; ++st) {
-      if (st + 1 < 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nxt[q] = ldr(st + 1, q);
-      }
-      hook(st);
-      __builtin_amdgcn_sched_barrier(0);
-      const T br = B.re[st >> 2][st & 3];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc.re[q] = mfma4<T>(cur[q], br, acc.re[q]);
-      __builtin_amdgcn_sched_barrier(0);
-      if (st + 1 < 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cur[q] = nxt[q];
-      }
-    }
-    return;
-  } else if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4) {
     // 3M: K1 = (Ar + Ai) Br, Cr += K1 - Ai (Br + Bi), Ci += K1 + Ar (Bi - Br).
     // Software-pipelined over the 16 k-steps (kb, t): the next step's four A
     // values are requested before this step's 12 MFMAs, which cover the LDS
