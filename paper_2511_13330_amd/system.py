@@ -50,6 +50,9 @@ class System:
         lj, plj = _ops(L_jump, self.d) if len(L_jump) else (None, None)
         if basis not in ("hermitian", "column"):
             raise ValueError("basis must be 'hermitian' (real) or 'column' (complex)")
+        # FP32 computes in the real basis of Hermitian operators unless asked
+        # for column stacking; FP64 always uses column stacking
+        self.basis = basis if precision == "f32" else "column"
         desc = SystemDesc(self.d, self.n_static, phs, self.n_ctrl, phc, len(L_jump), plj,
                           _PREC[precision], magnus_order, _HOLD[hold],
                           workspace_bytes_max, chunk_slices,

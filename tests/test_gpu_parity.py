@@ -136,7 +136,7 @@ def config1_run(request):
     F, g = lib_fid(sysm, cfg, amps)
     U = sysm.propagate(to_dev(amps, sysm), [4096], cfg["dt"],
                        static_coef=np.asarray(cfg["B"])[None, :]).cpu().numpy()[0]
-    sysm.basis = request.param
+    assert sysm.basis == request.param
     return cfg, amps, F, g, U, sysm
 
 
